@@ -1,0 +1,163 @@
+"""Oracle: one MFWH application, the fixed-point iteration and GMRES.
+
+TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).
+
+One application W_h(V) (Algorithm 1 body, discretised as in Section 6 with
+the explicit scheme alpha = 0, beta = 1):
+
+  W^0 = sum_m V_m                                  (eq. WaveScheme, initial data)
+  W^1 = W^0 + (dt^2/2) (c^2 Delta_h W^0 - F^0)     (eq. implicitFirstStep, alpha = 0)
+  W^{n+1} = 2 W^n - W^{n-1} + dt^2 (c^2 Delta_h W^n - F^n),  n = 1..N_t-1
+  F^n = sum_m f_m cos(omega~_m t^n)                (eq. WaveSchemeForcing, alpha = 0)
+  W^n = 0 on the boundary                          (Dirichlet, g = 0)
+  q_m = (2 / T~_{f,m}) sum_{n=0}^{N_t} sigma_{n,m} K(omega~_m t^n; p_m) W^n   (eq. pDefQ)
+  V'  = B^{-1} q   pointwise                       (eq. waveHoltzMatrixIteration)
+
+The result on boundary points is zero.  "forcing off" drops F (the linear
+part S of the affine map, Section 7).
+"""
+import numpy as np
+
+from . import fd
+
+
+class Problem:
+    """Grid + operator data for the oracle.  ``c`` is the wave speed on the full
+    grid (None means c = 1)."""
+
+    def __init__(self, shape, order, lengths=None, c=None):
+        self.shape = tuple(int(s) for s in shape)
+        self.order = int(order)
+        self.h = fd.spacings(self.shape, lengths)
+        self.c2 = None if c is None else np.asarray(c, dtype=np.float64) ** 2
+
+    def L(self, W):
+        """L_ph W = c^2 Delta_h W."""
+        lap = fd.laplacian(W, self.h, self.order)
+        return lap if self.c2 is None else self.c2 * lap
+
+
+def wave_history(prob, plan, f, V, forcing=True):
+    """Yield W^0, W^1, ..., W^{N_t} of the explicit scheme (see module doc)."""
+    dt2 = plan.dt ** 2
+    W0 = fd.zero_boundary(np.sum(np.asarray(V, dtype=np.float64), axis=0))
+    f = np.asarray(f, dtype=np.float64)
+
+    def F(n):
+        if not forcing:
+            return 0.0
+        return np.tensordot(plan.phi[n], f, axes=(0, 0))
+
+    yield W0
+    W1 = fd.zero_boundary(W0 + 0.5 * dt2 * (prob.L(W0) - F(0)))
+    yield W1
+    for n in range(1, plan.nt):
+        W2 = fd.zero_boundary(2.0 * W1 - W0 + dt2 * (prob.L(W1) - F(n)))
+        yield W2
+        W0, W1 = W1, W2
+
+
+def filtered(prob, plan, f, V, forcing=True):
+    """q[m] = sum_n kappa[n, m] W^n  (eq. pDefQ)."""
+    q = np.zeros((plan.nf,) + prob.shape)
+    for n, W in enumerate(wave_history(prob, plan, f, V, forcing)):
+        for m in range(plan.nf):
+            q[m] += plan.kappa[n, m] * W
+    return q
+
+
+def apply(prob, plan, f, V, forcing=True):
+    """One MFWH application V -> B^{-1} q (boundary set to zero)."""
+    q = filtered(prob, plan, f, V, forcing)
+    out = np.tensordot(plan.Binv, q, axes=(1, 0))
+    for m in range(plan.nf):
+        fd.zero_boundary(out[m])
+    return out
+
+
+def fixed_point(prob, plan, f, iters, V0=None):
+    """MFWH fixed-point iteration (Algorithm 1).  Returns (V, r) where r[k-1]
+    is the combined residual r^(k) of eq. residual (interior points only)."""
+    V = np.zeros((plan.nf,) + prob.shape) if V0 is None else np.array(V0, dtype=np.float64)
+    na = int(np.prod([s - 2 for s in prob.shape]))
+    res = []
+    for _ in range(iters):
+        Vn = apply(prob, plan, f, V, True)
+        d = np.stack([fd.interior(x) for x in (Vn - V)])
+        res.append(np.sqrt(np.sum(d * d) / (plan.nf * na)))
+        V = Vn
+    return V, np.array(res)
+
+
+# ----------------------------------------------------------------------------
+# GMRES on A_h V = b_h, A_h = I - S_h, b_h = W_h(0)   (Section 7)
+# ----------------------------------------------------------------------------
+def _pack(prob, V):
+    return np.concatenate([fd.interior(x).ravel() for x in V])
+
+
+def _unpack(prob, x, nf):
+    ni = [s - 2 for s in prob.shape]
+    size = int(np.prod(ni))
+    return np.stack([fd.embed(x[m * size:(m + 1) * size].reshape(ni), prob.shape)
+                     for m in range(nf)])
+
+
+def gmres(prob, plan, f, restart=30, tol=1e-10, max_iter=500, V0=None):
+    """Restarted GMRES(m), modified Gram-Schmidt, Givens rotations.
+
+    Unknowns: the interior values of all N_f fields (reading c8).  Stops when
+    the true relative residual ||b - A x||_2 / ||b||_2 is <= tol (checked at
+    each restart) or after ``max_iter`` Arnoldi steps.
+    Returns (V, history) with history = estimated relative residual after each
+    Arnoldi step.
+    """
+    nf = plan.nf
+    b = _pack(prob, apply(prob, plan, f, np.zeros((nf,) + prob.shape), True))
+
+    def A(x):
+        Sx = _pack(prob, apply(prob, plan, f, _unpack(prob, x, nf), False))
+        return x - Sx
+
+    x = np.zeros_like(b) if V0 is None else _pack(prob, V0)
+    bnorm = np.linalg.norm(b)
+    hist = []
+    its = 0
+    while True:
+        r = b - A(x) if np.any(x) else b.copy()
+        beta = np.linalg.norm(r)
+        if beta / bnorm <= tol or its >= max_iter:
+            break
+        Q = [r / beta]
+        H = np.zeros((restart + 1, restart))
+        cs = np.zeros(restart)
+        sn = np.zeros(restart)
+        g = np.zeros(restart + 1)
+        g[0] = beta
+        k = 0
+        for j in range(restart):
+            w = A(Q[j])
+            for i in range(j + 1):
+                H[i, j] = np.dot(Q[i], w)
+                w = w - H[i, j] * Q[i]
+            H[j + 1, j] = hnext = np.linalg.norm(w)
+            for i in range(j):
+                t = cs[i] * H[i, j] + sn[i] * H[i + 1, j]
+                H[i + 1, j] = -sn[i] * H[i, j] + cs[i] * H[i + 1, j]
+                H[i, j] = t
+            den = np.hypot(H[j, j], H[j + 1, j])
+            cs[j], sn[j] = H[j, j] / den, H[j + 1, j] / den
+            H[j, j] = den
+            H[j + 1, j] = 0.0
+            g[j + 1] = -sn[j] * g[j]
+            g[j] = cs[j] * g[j]
+            its += 1
+            k = j + 1
+            hist.append(abs(g[j + 1]) / bnorm)
+            if abs(g[j + 1]) / bnorm <= tol or its >= max_iter or hnext == 0.0:
+                break
+            Q.append(w / hnext)
+        y = np.linalg.solve(np.triu(H[:k, :k]), g[:k])
+        for i in range(k):
+            x = x + y[i] * Q[i]
+    return _unpack(prob, x, nf), np.array(hist)

@@ -1,0 +1,222 @@
+"""Pins of the oracle's planning arithmetic against the paper and mathematics.
+
+Pins used here (none re-types the oracle's own formula):
+  * printed time-step / period / Lambda numbers and optimised parameters
+    (Section 8 text and captions; Table 2) from tests/golden/paper_printed.json;
+  * exactness of the quadrature on constants and linear functions, and its
+    O(dt^2) convergence to the integral of a smooth function;
+  * the continuous closed forms of eq. compFuncs as the dt -> 0 limit of the
+    discrete beta_d;
+  * Theorem 3 (mu_d = 1 at each modified frequency) and the constraints of
+    eq. constraintsT for optimised parameters;
+  * the stability limit cross-checked against the largest eigenvalue of the
+    sparse Laplacian computed by scipy.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+from oracle import fd
+from oracle import plan as P
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_printed.json")))
+
+
+def close_4sig(x, printed):
+    """|x - printed| within half a unit of the 4th significant digit."""
+    e = math.floor(math.log10(abs(printed)))
+    return abs(x - printed) <= 0.5 * 10.0 ** (e - 3) * 1.01   # 1 % slack for round-half cases
+
+
+@pytest.mark.parametrize("case", GOLD["recipe_implicit"], ids=lambda c: f"om{c['omega']}-np{c['np']}")
+def test_recipe_and_optimiser_printed(case):
+    om, np_ = case["omega"], case["np"]
+    Tf, dt, nt = P.time_step_implicit(om, np_)
+    assert nt == case["nt"]
+    assert round(Tf, case["Tf_digits"]) == pytest.approx(case["Tf"], abs=1e-12)
+    pl = P.Plan(om, Tf, dt, alpha=0.5)
+    assert list(pl.npm) == case["npm"]
+    p, lmax, nlam = P.optimise_filter_discrete(pl.omega_t, np_, nt)
+    assert nlam == case["n_lambda"]
+    assert lmax == pytest.approx(case["lambda_max"], abs=case["lambda_max_tol"])
+    if "p_tilde" in case:
+        for m, row in enumerate(case["p_tilde"]):
+            for k in range(3):
+                assert close_4sig(p[m, k], row[k]), (m, k, p[m, k], row[k])
+
+
+@pytest.mark.parametrize("row", GOLD["table2_continuous"]["rows"], ids=lambda r: f"np{r['np']}")
+def test_table2_continuous(row):
+    p, lmax, nlam = P.optimise_filter_continuous(GOLD["table2_continuous"]["omega"], row["np"])
+    assert lmax == pytest.approx(row["lambda_max"], rel=1e-12)
+    for m in range(2):
+        for k in range(3):
+            assert close_4sig(p[m, k], row["p_tilde"][m][k]), (m, k, p[m, k])
+
+
+def test_table2_discrete_limit():
+    """The discrete optimiser tends to the continuous one as N_t grows."""
+    pc, _, _ = P.optimise_filter_continuous([5.0, 9.0], 2)
+    errs = []
+    for nt in (500, 1000, 2000):
+        pd_, _, _ = P.optimise_filter_discrete([5.0, 9.0], 2, nt)
+        errs.append(np.max(np.abs(pd_ - pc)))
+    assert errs[0] / errs[1] > 3.0 and errs[1] / errs[2] > 3.0   # O(dt^2)
+    assert errs[-1] < 1e-4
+
+
+def test_explicit_square128_periods():
+    g = GOLD["explicit_square128"]
+    h = 1.0 / g["cells"]
+    Tf, dt, nt = P.time_step_explicit(g["omega"][0], g["np"], h, 2, 4, 1.0, g["cfl"])
+    pl = P.Plan(g["omega"], Tf, dt)
+    assert list(pl.npm) == g["npm"]
+    assert dt <= g["cfl"] * P.dt_max_explicit(h, 2, 4, 1.0)
+    # the modified first frequency completes exactly N_p periods
+    assert pl.omega_t[0] * Tf == pytest.approx(2 * math.pi * g["np"], rel=1e-13)
+
+
+@pytest.mark.parametrize("dim,order", [(1, 2), (1, 4), (2, 2), (2, 4), (3, 2), (3, 4)])
+def test_stability_limit_vs_sparse_eigenvalue(dim, order):
+    shape = (9,) * dim
+    h = fd.spacings(shape)
+    L = fd.laplacian_matrix(shape, h, order)
+    lam_max = -spla.eigsh(L.astype(float), k=1, which="SA", return_eigenvectors=False)[0]
+    dtm = P.dt_max_explicit(h, dim, order, 1.0)
+    # leapfrog is stable iff dt^2 * lam <= 4 for every eigenvalue lam of -Delta_h
+    assert dtm ** 2 * lam_max <= 4.0 * (1 + 1e-12)
+    # grid-independent bound is reached in the limit; on 9 points it is within 15 %
+    assert dtm ** 2 * lam_max > 4.0 * 0.85
+
+
+@pytest.mark.parametrize("T", [1.0, 1.2345, 2.0 - 1e-9, 0.731])
+def test_quadrature_exact_for_linear(T):
+    nt, dt = 20, 0.1
+    s = P.trap_weights(nt, dt, [T])[:, 0]
+    t = dt * np.arange(nt + 1)
+    assert s.sum() == pytest.approx(T, rel=1e-14)
+    assert s @ t == pytest.approx(T * T / 2, rel=1e-13)
+    assert np.all(s >= 0)
+    q = int(math.floor(T / dt))
+    assert np.all(s[q + 2:] == 0)
+
+
+def test_quadrature_second_order():
+    T = 2.37
+    exact = (1 - math.cos(3 * T)) / 3       # int_0^T sin(3t) dt
+    errs = []
+    for nt in (50, 100, 200):
+        dt = 2.5 / nt
+        t = dt * np.arange(nt + 1)
+        errs.append(abs(P.trap_weights(nt, dt, [T])[:, 0] @ np.sin(3 * t) - exact))
+    assert 3.5 < errs[0] / errs[1] < 4.5 and 3.5 < errs[1] / errs[2] < 4.5
+
+
+def test_beta_d_tends_to_closed_forms():
+    """beta_d -> a f_a + c f_c + s f_s (eq. compFuncs) at O(dt^2)."""
+    om = [5.0, 9.0]
+    p = np.array([[0.3, 0.9, 0.2], [-0.4, 1.1, -0.3]])
+    lam = np.linspace(0.0, 20.0, 101)
+    errs = []
+    for nt in (100, 200, 400):
+        dt = 2 * 2 * math.pi / om[0] / nt
+        Tf = nt * dt
+        pl = P.Plan(om, Tf, dt, params=p)
+        e = 0.0
+        for m in range(2):
+            bc = P.beta_continuous(lam, pl.omega_t[m], pl.tfm[m], p[m])
+            e = max(e, np.max(np.abs(pl.beta_d(m, lam) - bc)))
+        errs.append(e)
+    assert errs[0] / errs[1] > 3.5 and errs[1] / errs[2] > 3.5
+
+
+def test_closed_forms_vs_numerical_integration():
+    """eq. compFuncs against direct high-resolution quadrature of the
+    defining integrals (2/T) int_0^T g(t) cos(lam t) dt."""
+    from scipy.integrate import quad
+    om, T = 7.0, 2 * 2 * math.pi / 7.0
+    for lam in (0.0, 3.3, 7.0, 11.2):
+        ia = quad(lambda t: math.cos(lam * t), 0, T, limit=200)[0] * 2 / T
+        ic = quad(lambda t: math.cos(om * t) * math.cos(lam * t), 0, T, limit=200)[0] * 2 / T
+        is_ = quad(lambda t: math.sin(om * t) * math.cos(lam * t), 0, T, limit=200)[0] * 2 / T
+        assert P.f_a(lam, T) == pytest.approx(ia, abs=1e-12)
+        assert P.f_c(lam, om, T) == pytest.approx(ic, abs=1e-12)
+        assert P.f_s(lam, om, T) == pytest.approx(is_, abs=1e-12)
+
+
+def _some_plan(params=None):
+    om = [5.1, 10.1, 15.1]
+    Tf, dt, nt = P.time_step_explicit(om[0], 2, 1 / 64, 2, 4, 1.0, 0.9)
+    return P.Plan(om, Tf, dt, params=params)
+
+
+def test_theorem3_mu_one_at_modified_frequencies():
+    for params in (None, np.array([[0.1, 0.7, 0.3], [-0.2, 1.3, 0.1], [0.4, 0.8, -0.6]])):
+        pl = _some_plan(params)
+        assert np.allclose(pl.mu_d(pl.omega_t), 1.0, atol=1e-13)
+
+
+def test_theorem2_mu_is_nonzero_eigenvalue():
+    """mu(lambda) = sum gamma_m beta_m(lambda) is the one non-zero eigenvalue
+    of M = B^{-1} C_lambda (Theorems 1 and 2), checked with numpy.linalg.eigvals."""
+    pl = _some_plan()
+    for lam in (2.0, 7.7, 13.0, 30.0):
+        beta = np.array([pl.beta_d(m, lam) for m in range(3)])
+        M = pl.Binv @ np.outer(beta, np.ones(3))
+        ev = np.linalg.eigvals(M)
+        k = np.argmax(np.abs(ev))
+        assert ev[k].real == pytest.approx(float(pl.mu_d(lam)), rel=1e-10, abs=1e-12)
+        assert np.sort(np.abs(ev))[:2] == pytest.approx([0, 0], abs=1e-10)
+
+
+def test_optimised_constraints_discrete():
+    """For discrete-optimised p~: sum_j beta~_j(omega_m) = 1 (eq. coneT) and
+    mu_d'(omega_m) = 0 (eq. ctwoT)."""
+    om = np.array([5.1, 10.1, 15.1])
+    Tf, dt, nt = P.time_step_explicit(om[0], 2, 1 / 64, 2, 4, 1.0, 0.9)
+    om_t = P.omega_tilde(om, dt)
+    p, _, _ = P.optimise_filter_discrete(om_t, 2, nt)
+    pl = P.Plan(om, Tf, dt, params=p)
+    assert np.allclose(pl.B.sum(axis=0), 1.0, atol=1e-10)
+    assert np.allclose(pl.gamma(), 1.0, atol=1e-9)
+    eps = 1e-5
+    d = (pl.mu_d(om_t + eps) - pl.mu_d(om_t - eps)) / (2 * eps)
+    assert np.max(np.abs(d)) < 1e-6
+
+
+def test_adjusted_traditional_flat_at_first_frequency():
+    """eq. origParamAdjust: d beta_{d,1}/d lambda = 0 at omega~_1 (trapezoid
+    over whole periods, no partial interval)."""
+    om = [5.1, 10.1]
+    Tf, dt, nt = P.time_step_explicit(om[0], 1, 1 / 32, 2, 2, 1.0, 0.9)
+    om_t = P.omega_tilde(om, dt)
+    pl = P.Plan(om, Tf, dt, params=P.adjusted_traditional_params(om_t, dt))
+    eps = 1e-5
+    d = (pl.beta_d(0, om_t[0] + eps) - pl.beta_d(0, om_t[0] - eps)) / (2 * eps)
+    assert abs(d) < 1e-8
+    # the unadjusted -1/4 is not flat at this dt
+    pl0 = P.Plan(om, Tf, dt)
+    d0 = (pl0.beta_d(0, om_t[0] + eps) - pl0.beta_d(0, om_t[0] - eps)) / (2 * eps)
+    assert abs(d0) > 1e-6
+
+
+def test_omega_tilde_defining_property():
+    """2 - 2 cos(omega~ dt) = (omega dt)^2 for leapfrog (the symbol of D+D-)."""
+    om, dt = np.array([1.0, 5.0, 17.0]), 0.05
+    ot = P.omega_tilde(om, dt)
+    assert np.allclose(2 - 2 * np.cos(ot * dt), (om * dt) ** 2, rtol=1e-13)
+    with pytest.raises(ValueError):
+        P.omega_tilde([50.0], dt)        # omega dt = 2.5 > 2: no real omega~
+
+
+def test_plan_rejects_bad_input():
+    with pytest.raises(ValueError):
+        P.Plan([5.0, 3.0], 1.0, 0.01)
+    with pytest.raises(ValueError):
+        P.Plan([5.0, 5.0], 1.0, 0.01)
+    with pytest.raises(ValueError):
+        P.Plan([5.0], 1.0, 0.0123)      # not an integer number of steps
