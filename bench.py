@@ -1,0 +1,174 @@
+"""Benchmark of the MFWH hot path on one MI355X.
+
+One step = one complete MFWH solve of the 2D workload (1025^2 grid, order-4
+Laplacian, CFL 0.5, N_f = 4 frequencies drawn U(20, 60), Gaussian-sum
+forcings, least-squares filter): plan, b = W_h(0), restarted GMRES(30) in
+float64 to a true relative residual of 1e-8.  Every step runs the fused
+leapfrog + filter kernel for every wave solve of the Krylov iteration.
+
+value = interior grid points x time steps x N_f summed over all wave solves
+of the timed steps, divided by the wall time (inputs already in HBM).
+
+Extra fields:
+  roofline       the fused step kernel: algorithmic bytes per launch / the
+                 launch duration measured with HIP events on its stream during
+                 the timed steps, against the 8 TB/s HBM peak
+  cpu_baseline   the float64 oracle (NumPy, one core) stepping the same
+                 workload for a bounded number of time steps
+  time_to_1e8    wall time of one float64 GMRES solve and of one float32-
+                 stencil solve with float64 iterative refinement
+
+    python bench.py [--gpus 1] [--steps 3] [--warmup 1]
+    python bench.py --mode copy      # plain copy kernel of known size (counter calibration)
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "grid-point-steps/s ×Nf filters (%HBM peak); time-to-1e-8 residual vs plain"
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_baseline(w, budget_s=15.0):
+    """Time the oracle on a bounded sample: as many time steps of the float64
+    oracle's wave solve with filter accumulation as fit in ``budget_s``."""
+    from oracle import mfwh as omf, workload
+    prob, pl = workload.setup(dict(w), filt="traditional")
+    rng = np.random.default_rng(0)
+    V = rng.standard_normal((len(w["omega"]),) + tuple(w["shape"]))
+    q = np.zeros_like(V)
+    na = int(np.prod([s - 2 for s in w["shape"]]))
+    t0 = time.perf_counter()
+    steps = 0
+    for n, W in enumerate(omf.wave_history(prob, pl, w["f"], V, True)):
+        for m in range(len(w["omega"])):
+            q[m] += pl.kappa[n, m] * W
+        steps = n
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    nf = len(w["omega"])
+    return dict(value=na * steps * nf / dt, unit="grid-point-steps/s x Nf", cores=1,
+                kind="oracle",
+                sample=f"{steps} time steps (of {pl.nt}) of one float64 wave solve with "
+                       f"{nf} filter updates on the full {w['shape'][0]}x{w['shape'][1]} grid, "
+                       f"{dt:.1f} s, NumPy single-threaded; host has {os.cpu_count()} cpus")
+
+
+def copy_calibration(nbytes=1 << 30, reps=5):
+    import torch
+    a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"mode": "copy", "bytes_read": nbytes, "bytes_written": nbytes,
+                      "reps": reps}))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--mode", default="solve", choices=["solve", "copy"])
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    ap.add_argument("--no-fp32", action="store_true", help="skip the float32-stencil solve")
+    ap.add_argument("--n", type=int, default=1025, help="grid points per axis")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); multi-GPU slab "
+              "decomposition is a design, not part of this build", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if args.mode == "copy":
+        copy_calibration()
+        return
+
+    from paper_2507_23613_amd import _lib as L
+    from paper_2507_23613_amd import inputs
+    from paper_2507_23613_amd.problem import GpuProblem
+
+    w = inputs.config2(0, n=args.n)
+    nf = len(w["omega"])
+    log(f"workload {w['name']}: omega={np.round(w['omega'], 3).tolist()} N_p={w['np']}")
+    gp = GpuProblem(w, precision=L.MFWH_FP64, restart=30)
+    log(f"N_t={gp.nt} dt={gp.dt:.3e} interior={gp.interior_points}")
+
+    def solve():
+        v, info = gp.gmres(restart=30, max_iter=2000, tol=1e-8)
+        if not info["converged"]:
+            raise RuntimeError(f"GMRES did not converge: {info['status']} {info['rel_residual']}")
+        return info
+
+    for k in range(args.warmup):
+        info = solve()
+        log(f"warmup {k}: its={info['iterations']} applies={info['applies']}")
+    torch.cuda.synchronize()
+    L.mfwh_stats_read()                       # clear
+    L.mfwh_stats_enable(1, 8)
+    t0 = time.perf_counter()
+    total_ps, its, applies = 0, [], 0
+    for k in range(args.steps):
+        info = solve()
+        total_ps += info["point_steps"]
+        its.append(info["iterations"])
+        applies += info["applies"]
+        log(f"step {k}: its={info['iterations']} applies={info['applies']} "
+            f"res={info['rel_residual']:.2e}")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    L.mfwh_stats_enable(0, 8)
+    launches, kms, kbytes = L.mfwh_stats_read()
+    value = total_ps * nf / elapsed
+    avg_us = 1e3 * kms / max(1, launches)
+    bytes_per_launch = kbytes / max(1, launches)
+    achieved = kbytes / (kms * 1e6) if kms > 0 else 0.0
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "kernel": "k_step2d<double,2,128> (fused leapfrog + 4 filter updates)",
+            "avg_launch_us": round(avg_us, 3), "bytes_per_launch": round(bytes_per_launch),
+            "timed_launches": launches}
+
+    t2e = {"fp64_s": round(elapsed / args.steps, 3)}
+    if not args.no_fp32:
+        gp32 = GpuProblem(w, precision=L.MFWH_FP32_STENCIL, restart=30)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        _, info32 = gp32.gmres(restart=30, max_iter=2000, tol=1e-8, inner_tol=1e-5)
+        torch.cuda.synchronize()
+        t2e["fp32_stencil_refined_s"] = round(time.perf_counter() - t1, 3)
+        t2e["fp32_converged"] = bool(info32["converged"])
+        t2e["fp32_iterations"] = info32["iterations"]
+        t2e["fp32_outer"] = info32["outer"]
+        del gp32
+    cpu = None if args.no_cpu else cpu_baseline(w)
+    out = {
+        "metric": METRIC, "value": value, "unit": "grid-point-steps/s x Nf",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"{w['name']}-order4-cfl0.5-gmres30-tol1e-8",
+                   "grid": list(w["shape"]), "nf": nf, "np": int(w["np"]), "nt": gp.nt,
+                   "gmres_iterations": its, "wave_solves": applies,
+                   "omega": np.round(w["omega"], 4).tolist()},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "time_to_1e8": t2e,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

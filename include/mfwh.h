@@ -1,0 +1,224 @@
+/*
+ * mfwh.h -- C ABI of the MI355X Multi-Frequency WaveHoltz (MFWH) library.
+ *
+ * MFWH (arXiv 2507.23613) computes N_f discrete Helmholtz solutions
+ *     c^2 Delta_h U_m + omega_m^2 U_m = f_m   (interior),   U_m = 0 (boundary)
+ * at once (eq. MultipleHelmholtz, eq. discreteHelmholtz) by time-stepping ONE
+ * wave equation forced by sum_m f_m cos(omega~_m t) (eqs. waveEqnMultipleForcings,
+ * WaveScheme) over a filter period and accumulating N_f time filters of the wave
+ * field (eq. pDefQ).  The resulting affine map V -> S V + b (eq.
+ * discreteMFWHmapping) is iterated directly (Algorithm 1) or its fixed point is
+ * found with GMRES (Section 7).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Grid arrays are DEVICE pointers owned by the caller, row-major with x
+ *    varying fastest: element (ix, iy, iz) of field m is at
+ *        m * (n0*n1*n2) + iz * (n0*n1) + iy * n0 + ix,
+ *    n[] counting grid points INCLUDING both boundary points of each axis
+ *    (n[k] = 1 for axes beyond dim).  Multi-frequency arrays hold nf fields.
+ *  - All device arrays at the ABI are float64.  Boundary entries of inputs are
+ *    ignored (homogeneous Dirichlet data, g = 0, the setting of all the
+ *    paper's experiments); outputs get 0 on the boundary.
+ *  - Host arrays (omega, filter parameters, histories, plan outputs) are plain
+ *    host memory owned by the caller.
+ *  - Scratch: the library never allocates device memory.  Every GPU entry point
+ *    takes a caller-owned device workspace `ws` of at least
+ *    mfwh_workspace_bytes(...) bytes, 256-byte aligned.
+ *  - Streams: `stream` is a hipStream_t passed as void* (NULL = default stream).
+ *    mfwh_apply is asynchronous on the stream; the solvers synchronise the
+ *    stream to read scalars and return when the solution is in place.
+ *  - Errors: functions return an mfwh_status; no C++ exception crosses the ABI.
+ *    mfwh_last_error() returns a thread-local description of the last error.
+ *  - Calls that share a workspace must not overlap.
+ */
+#ifndef MFWH_H
+#define MFWH_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MFWH_MAX_NF 8          /* maximum number of frequencies per problem   */
+#define MFWH_MAX_RESTART 512   /* maximum GMRES restart length                */
+
+typedef enum {
+  MFWH_OK = 0,
+  MFWH_NOT_CONVERGED = 1,   /* result written and usable, tolerance not met     */
+  MFWH_EINVAL = -1,         /* bad argument (sizes, order, null pointers, ...)   */
+  MFWH_EUNSORTED = -2,      /* omega not positive and strictly ascending         */
+  MFWH_ECFL = -3,           /* omega_m*dt >= 2 (no modified frequency) or unstable dt */
+  MFWH_ESINGULAR = -4,      /* B (eq. filterA) or an optimiser system singular   */
+  MFWH_ENT = -5,            /* T/dt is not an integer number of steps >= 2       */
+  MFWH_EHIP = -6,           /* a HIP runtime call failed                          */
+  MFWH_EWORKSPACE = -7,     /* workspace too small or misaligned                  */
+  MFWH_ENONFINITE = -8      /* a NaN/Inf appeared in a residual                   */
+} mfwh_status;
+
+enum { MFWH_FP64 = 0,          /* wave field, forcing and c^2 in float64            */
+       MFWH_FP32_STENCIL = 1   /* wave field, forcing and c^2 in float32; filter
+                                  accumulators, iterates and Krylov data float64   */
+};
+
+/* Problem geometry and discretisation (Section 6). */
+typedef struct mfwh_grid {
+  int dim;            /* 1, 2 or 3                                                 */
+  int n[3];           /* points per axis incl. both boundary points, n[0] = x;
+                         n[k] >= 3 for k < dim, n[k] = 1 for k >= dim             */
+  double len[3];      /* domain length per axis: h_k = len[k] / (n[k] - 1)         */
+  int order;          /* spatial order p of L_ph = c^2 Delta_h: 2 or 4.  Order 4
+                         uses the odd reflection W_{-1} = -W_1 at the Dirichlet
+                         boundary for its one ghost value.                          */
+  int precision;      /* MFWH_FP64 or MFWH_FP32_STENCIL                            */
+  const double* c;    /* device, wave speed at every grid point, or NULL (c = 1)   */
+} mfwh_grid;
+
+/* Frequencies, filter and time grid (Sections 2, 3, 6). */
+typedef struct mfwh_time {
+  int nf;                /* number of frequencies, 1..MFWH_MAX_NF                  */
+  const double* omega;   /* host [nf]: physical frequencies, > 0, strictly ascending */
+  const double* filt;    /* host [nf][3]: filter parameters (a, c, s) of the kernel
+                            K(tau) = a + c cos(tau) + s sin(tau) (eq. newFilterKernel),
+                            or NULL for the traditional p_0 = (-1/4, 1, 0)          */
+  double T;              /* final time T_f of each wave solve                     */
+  double dt;             /* time step; N_t = T/dt must be an integer >= 2 (to 1e-9)
+                            and omega_nf * dt < 2                                   */
+} mfwh_time;
+
+/* Solver controls.  A NULL pointer selects the defaults in brackets. */
+typedef struct mfwh_solve_opts {
+  int restart;           /* GMRES restart length, 1..MFWH_MAX_RESTART       [30]   */
+  int max_iter;          /* max Arnoldi steps (GMRES) / iterations (FPI)   [1000] */
+  double tol;            /* target relative residual                        [1e-8] */
+  double inner_tol;      /* MFWH_FP32_STENCIL: relative tolerance of each inner
+                            GMRES solve of iterative refinement             [1e-5] */
+  int max_outer;         /* MFWH_FP32_STENCIL: max refinement steps          [20]  */
+} mfwh_solve_opts;
+
+/* Solver report (host struct filled on return). */
+typedef struct mfwh_solve_info {
+  int iterations;          /* Arnoldi steps (GMRES) or fixed-point iterations     */
+  int applies;             /* MFWH applications (wave solves) performed           */
+  int outer;               /* refinement steps (MFWH_FP32_STENCIL GMRES)          */
+  double rel_residual;     /* final relative residual (see each solver)           */
+  long long point_steps;   /* sum over applications of interior points x N_t      */
+} mfwh_solve_info;
+
+/* Description of the last error on the calling thread ("" if none). */
+const char* mfwh_last_error(void);
+
+/* ------------------------------------------------------------------------- *
+ * Host-side planning (no GPU needed)
+ * ------------------------------------------------------------------------- */
+
+/* Explicit time-step recipe (Section 6, "Time-step determination"; the paper
+ * defers the recipe to earlier work -- this library's reading): N_t =
+ * ceil(N_p * 2 pi/omega1 / (cfl * dt_max)) with dt_max the von Neumann limit
+ * of leapfrog for `g` (dim, order, spacing) and wave speed <= cmax, then dt
+ * chosen so that the modified first frequency (eq. omegaImplicit) completes
+ * exactly N_p periods in N_t steps.  Outputs: *T = N_t*dt, *dt, *nt. */
+int mfwh_plan_time(const mfwh_grid* g, double cmax, double omega1, int np, double cfl,
+                   double* T, double* dt, int* nt);
+
+/* Implicit (trapezoid, alpha = 1/2) recipe of the same section, provided for
+ * planning only: N_t = ceil(steps_per_period * N_p * omega_last / omega1),
+ * dt from the exact-period condition with the implicit omega~. */
+int mfwh_plan_time_implicit(double omega1, double omega_last, int np, int steps_per_period,
+                            double* T, double* dt, int* nt);
+
+/* The plan of one problem (explicit scheme): modified frequencies omega~_m
+ * (eq. omegaImplicit), N_{p,m} and T~_{f,m} (eq. TbarDef with omega~), the
+ * matrix B[m][j] = beta_{d,m}(omega~_j) (eq. filterA with eq. betadDefA) and
+ * its inverse, all row-major.  Any output pointer may be NULL. */
+int mfwh_plan_info(const mfwh_time* t, double* omega_tilde, int* npm, double* tfm,
+                   double* B, double* Binv);
+
+/* Per-step coefficients: kappa[n][m] = (2/T~_{f,m}) sigma_{n,m} K(omega~_m t^n; p_m)
+ * (eq. pDefQ with the quadrature of eq. DefNI) and phi[n][m] = cos(omega~_m t^n)
+ * (eq. WaveSchemeForcing), n = 0..N_t, host arrays of (N_t+1)*nf doubles. */
+int mfwh_plan_coefficients(const mfwh_time* t, double* kappa, double* phi);
+
+/* Traditional parameters adjusted for time discretisation: (a_m, 1, 0) with
+ * a_m = -tan(omega~ dt/2) / (2 tan(omega~ dt)) (eq. origParamAdjust).
+ * omega: physical frequencies [nf]; filt_out: host [nf][3]. */
+int mfwh_filter_adjusted(int nf, const double* omega, double dt, double* filt_out);
+
+/* Least-squares filter parameters (Section 5, Algorithm 2, with the discrete
+ * time quadrature used for the computations of Section 8).  omega_in: the
+ * frequencies the filter is built for (pass omega~), ascending [nf]; np: N_p;
+ * nt: N_t; ndelta, cdelta: eq. LambdaRange (20, 2 in the paper).  rcond <= 0
+ * solves the least-squares problem exactly (the paper's method); rcond > 0
+ * returns the minimum-norm solution with singular values <= rcond * largest
+ * dropped (for nearly singular frequency sets).  The 2 N_f constraints of
+ * eq. constraintsTM hold exactly either way.  filt_out: host [nf][3]
+ * (a~, c~, s~); lambda_max / n_lambda may be NULL. */
+int mfwh_optimize_filter(int nf, const double* omega_in, int np, int nt, int ndelta,
+                         double cdelta, double rcond, double* filt_out, double* lambda_max,
+                         int* n_lambda);
+
+/* ------------------------------------------------------------------------- *
+ * GPU entry points
+ * ------------------------------------------------------------------------- */
+
+/* Workspace bytes needed by every entry point below for this problem with a
+ * GMRES restart length up to `restart` (0 if GMRES is not used). */
+size_t mfwh_workspace_bytes(const mfwh_grid* g, const mfwh_time* t, int restart);
+
+/* One MFWH application (Algorithm 1 loop body with the explicit scheme of
+ * Section 6):  W^0 = sum_m v_in[m];  leapfrog W^{n+1} = 2W^n - W^{n-1}
+ * + dt^2 (c^2 Delta_h W^n - F^n), F^n = sum_m f[m] cos(omega~_m t^n) when
+ * with_forcing (else F = 0: the linear part S of Section 7), first step per
+ * eq. implicitFirstStep with alpha = 0; q_m = sum_n kappa[n][m] W^n; then
+ * v_out = B^{-1} q pointwise (eq. waveHoltzMatrixIteration).
+ * f, v_in, v_out: device [nf][grid]; v_out may equal v_in; f may be NULL when
+ * with_forcing == 0. */
+int mfwh_apply(const mfwh_grid* g, const mfwh_time* t, const double* f, const double* v_in,
+               double* v_out, int with_forcing, void* ws, size_t ws_bytes, void* stream);
+
+/* Fixed-point iteration v <- W_h(v) (Algorithm 1) starting from the given v
+ * (device [nf][grid], updated in place).  res_hist (host, may be NULL) gets
+ * r^(k) of eq. residual for k = 1..iterations.  Stops when r^(k) <= tol *
+ * r^(1) or after max_iter iterations; info->rel_residual = r^(last)/r^(1). */
+int mfwh_solve_fixed_point(const mfwh_grid* g, const mfwh_time* t, const double* f, double* v,
+                           const mfwh_solve_opts* opts, double* res_hist, mfwh_solve_info* info,
+                           void* ws, size_t ws_bytes, void* stream);
+
+/* GMRES(m) on A_h V = b_h, A_h = I - S_h, b_h = W_h(0) (Section 7, eq.
+ * krylovSystem), unknowns = interior values of all nf fields, classical
+ * Gram-Schmidt with re-orthogonalisation in float64, initial guess v (device
+ * [nf][grid], zero allowed), solution written to v.  Stops when
+ * ||b - A v||_2 <= tol ||b||_2 (true residual, float64).
+ * With MFWH_FP32_STENCIL the inner Krylov solves use float32-stencil
+ * applications on corrections and an outer float64 residual drives iterative
+ * refinement.  res_hist (host, may be NULL, max_iter entries) gets the
+ * estimated relative residual after each Arnoldi step. */
+int mfwh_solve_gmres(const mfwh_grid* g, const mfwh_time* t, const double* f, double* v,
+                     const mfwh_solve_opts* opts, double* res_hist, mfwh_solve_info* info,
+                     void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------- *
+ * Measurement hooks
+ * ------------------------------------------------------------------------- */
+
+/* Enable (1) / disable (0) HIP-event timing of the fused leapfrog+filter step
+ * kernel: while enabled, every `sample_every`-th step launch is bracketed by
+ * events on its stream.  Disabling does not clear the accumulated totals. */
+int mfwh_stats_enable(int on, int sample_every);
+/* Read and reset the totals: number of timed step launches, their summed
+ * duration in milliseconds and their summed algorithmic HBM bytes (interior
+ * points x bytes per point-step: read W^n and W^{n-1}, write W^{n+1}, read the
+ * forcings when on, read+write every active float64 accumulator, read c^2). */
+int mfwh_stats_read(long long* launches, double* total_ms, double* total_bytes);
+
+/* Override the launch shape of the step kernel for all later calls in this
+ * process (autotuning): bx threads along x (32, 64, 128 or 256), by threads
+ * along y (3D: 4, 8 or 2 with bx 64/64/128; 8 with bx 32), chunk rows (2D) or
+ * planes (3D) marched per block.  bx = 0 restores the built-in heuristic. */
+int mfwh_set_launch_shape(int bx, int by, int chunk);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MFWH_H */

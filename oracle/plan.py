@@ -284,13 +284,16 @@ def lambda_range(omega, npm, ndelta=20, cdelta=2.0):
     return lmax, nlam
 
 
-def _optimise(fa, fc, fs, fap, fcp, fsp, omega, lmax, nlam):
+def _optimise(fa, fc, fs, fap, fcp, fsp, omega, lmax, nlam, rcond=0.0):
     """Common linear algebra of Algorithm 2.
 
     fa(lam, m) etc. evaluate the component functions of frequency m at a
     vector lam; fap etc. their lambda-derivatives.  Returns (nf, 3) params
     (a~, c~, s~) with the 2 N_f linear constraints (eq. constraintsTM) met
     exactly and the midpoint-rule L2 norm of mu over Lambda minimised.
+    ``rcond`` > 0 solves the least-squares problem in the minimum-norm sense
+    with singular values <= rcond * largest dropped (a reading for badly
+    conditioned frequency sets; 0 gives the plain least-squares solution).
     """
     nf = len(omega)
     om = np.asarray(omega, dtype=np.float64)
@@ -312,12 +315,12 @@ def _optimise(fa, fc, fs, fap, fcp, fsp, omega, lmax, nlam):
     Ginvz = np.linalg.solve(G, z)
     M = Va - Vcs @ GinvH              # g_a(lambda_k)^T rows
     m0 = -(Vcs @ Ginvz)               # -mu_0(lambda_k)
-    xa, *_ = np.linalg.lstsq(M, m0, rcond=None)
+    xa, *_ = np.linalg.lstsq(M, m0, rcond=(rcond if rcond > 0 else None))
     y = np.linalg.solve(G, z - H @ xa)
     return np.stack([xa, y[:nf], y[nf:]], axis=1)
 
 
-def optimise_filter_discrete(omega, np_, nt, ndelta=20, cdelta=2.0):
+def optimise_filter_discrete(omega, np_, nt, ndelta=20, cdelta=2.0, rcond=0.0):
     """Optimised p~ with the discrete time quadrature (the form used in
     Section 8).  ``omega`` is the frequency vector fed to the method (the
     computations of Section 8 pass the modified frequencies).  The common
@@ -348,7 +351,7 @@ def optimise_filter_discrete(omega, np_, nt, ndelta=20, cdelta=2.0):
 
     lmax, nlam = lambda_range(om, npm, ndelta, cdelta)
     p = _optimise(mk("a", 0), mk("c", 0), mk("s", 0),
-                  mk("a", 1), mk("c", 1), mk("s", 1), om, lmax, nlam)
+                  mk("a", 1), mk("c", 1), mk("s", 1), om, lmax, nlam, rcond)
     return p, lmax, nlam
 
 

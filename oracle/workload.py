@@ -1,0 +1,31 @@
+"""Oracle: plan a workload dict (from the seeded input generators) with the
+oracle's own recipe, filter choice and Plan.
+
+TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).
+"""
+import numpy as np
+
+from . import mfwh
+from . import plan as P
+
+
+def setup(w, filt=None):
+    """Returns (Problem, Plan) for workload ``w``: explicit recipe with the
+    workload's N_p and CFL; filter "traditional" (p_0), "adjusted"
+    (eq. origParamAdjust) or "optimised" (Algorithm 2 on omega~)."""
+    prob = mfwh.Problem(w["shape"], w["order"], w["lengths"], w["c"])
+    cmax = 1.0 if w["c"] is None else float(np.max(w["c"]))
+    Tf, dt, nt = P.time_step_explicit(w["omega"][0], w["np"], prob.h, len(w["shape"]),
+                                      w["order"], cmax, w["cfl"])
+    om_t = P.omega_tilde(w["omega"], dt)
+    kind = w["filter"] if filt is None else filt
+    if kind == "optimised":
+        params, _, _ = P.optimise_filter_discrete(om_t, w["np"], nt,
+                                                  rcond=w.get("filter_rcond", 0.0))
+    elif kind == "adjusted":
+        params = P.adjusted_traditional_params(om_t, dt)
+    elif kind == "traditional":
+        params = None
+    else:
+        raise ValueError(kind)
+    return prob, P.Plan(w["omega"], Tf, dt, params)

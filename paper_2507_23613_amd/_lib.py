@@ -1,0 +1,275 @@
+"""Thin ctypes binding of libmfwh.so (argument marshalling only).
+
+Every function here has the name of the C entry point it calls (see
+include/mfwh.h) and only converts arguments: torch device tensors become raw
+device pointers, NumPy arrays become host pointers, status codes become
+exceptions.  All computation happens in the HIP library.  If the library is
+missing the import of this module fails loudly: there is no fallback.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libmfwh.so")
+
+c_int, c_double, c_void_p, c_longlong, c_size_t = (ctypes.c_int, ctypes.c_double,
+                                                   ctypes.c_void_p, ctypes.c_longlong,
+                                                   ctypes.c_size_t)
+P_double = ctypes.POINTER(c_double)
+P_int = ctypes.POINTER(c_int)
+
+MFWH_FP64 = 0
+MFWH_FP32_STENCIL = 1
+MFWH_MAX_NF = 8
+MFWH_MAX_RESTART = 512
+STATUS = {0: "MFWH_OK", 1: "MFWH_NOT_CONVERGED", -1: "MFWH_EINVAL", -2: "MFWH_EUNSORTED",
+          -3: "MFWH_ECFL", -4: "MFWH_ESINGULAR", -5: "MFWH_ENT", -6: "MFWH_EHIP",
+          -7: "MFWH_EWORKSPACE", -8: "MFWH_ENONFINITE"}
+
+
+class MfwhError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class mfwh_grid(ctypes.Structure):
+    _fields_ = [("dim", c_int), ("n", c_int * 3), ("len", c_double * 3), ("order", c_int),
+                ("precision", c_int), ("c", c_void_p)]
+
+
+class mfwh_time(ctypes.Structure):
+    _fields_ = [("nf", c_int), ("omega", P_double), ("filt", P_double), ("T", c_double),
+                ("dt", c_double)]
+
+
+class mfwh_solve_opts(ctypes.Structure):
+    _fields_ = [("restart", c_int), ("max_iter", c_int), ("tol", c_double),
+                ("inner_tol", c_double), ("max_outer", c_int)]
+
+
+class mfwh_solve_info(ctypes.Structure):
+    _fields_ = [("iterations", c_int), ("applies", c_int), ("outer", c_int),
+                ("rel_residual", c_double), ("point_steps", c_longlong)]
+
+
+def _load():
+    # PyTorch's HIP runtime must be the one in the process before the library
+    # (which links against it) is loaded
+    import torch  # noqa: F401
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python -m paper_2507_23613_amd.build` (no CPU fallback exists)")
+    lib = ctypes.CDLL(LIB_PATH)
+    sig = {
+        "mfwh_last_error": (ctypes.c_char_p, []),
+        "mfwh_plan_time": (c_int, [ctypes.POINTER(mfwh_grid), c_double, c_double, c_int,
+                                   c_double, P_double, P_double, P_int]),
+        "mfwh_plan_time_implicit": (c_int, [c_double, c_double, c_int, c_int, P_double,
+                                            P_double, P_int]),
+        "mfwh_plan_info": (c_int, [ctypes.POINTER(mfwh_time), P_double, P_int, P_double,
+                                   P_double, P_double]),
+        "mfwh_plan_coefficients": (c_int, [ctypes.POINTER(mfwh_time), P_double, P_double]),
+        "mfwh_filter_adjusted": (c_int, [c_int, P_double, c_double, P_double]),
+        "mfwh_optimize_filter": (c_int, [c_int, P_double, c_int, c_int, c_int, c_double,
+                                         c_double, P_double, P_double, P_int]),
+        "mfwh_workspace_bytes": (c_size_t, [ctypes.POINTER(mfwh_grid),
+                                            ctypes.POINTER(mfwh_time), c_int]),
+        "mfwh_apply": (c_int, [ctypes.POINTER(mfwh_grid), ctypes.POINTER(mfwh_time), c_void_p,
+                               c_void_p, c_void_p, c_int, c_void_p, c_size_t, c_void_p]),
+        "mfwh_solve_fixed_point": (c_int, [ctypes.POINTER(mfwh_grid), ctypes.POINTER(mfwh_time),
+                                           c_void_p, c_void_p, ctypes.POINTER(mfwh_solve_opts),
+                                           P_double, ctypes.POINTER(mfwh_solve_info), c_void_p,
+                                           c_size_t, c_void_p]),
+        "mfwh_solve_gmres": (c_int, [ctypes.POINTER(mfwh_grid), ctypes.POINTER(mfwh_time),
+                                     c_void_p, c_void_p, ctypes.POINTER(mfwh_solve_opts),
+                                     P_double, ctypes.POINTER(mfwh_solve_info), c_void_p,
+                                     c_size_t, c_void_p]),
+        "mfwh_stats_enable": (c_int, [c_int, c_int]),
+        "mfwh_stats_read": (c_int, [ctypes.POINTER(c_longlong), P_double, P_double]),
+        "mfwh_set_launch_shape": (c_int, [c_int, c_int, c_int]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+LIB = _load()
+
+
+def _check(rc, allow_not_converged=False):
+    if rc == 0 or (rc == 1 and allow_not_converged):
+        return rc
+    raise MfwhError(rc, LIB.mfwh_last_error().decode())
+
+
+def _dptr(a):
+    """float64 host array -> (keepalive, pointer)."""
+    arr = np.ascontiguousarray(a, dtype=np.float64)
+    return arr, arr.ctypes.data_as(P_double)
+
+
+def _tptr(t, what):
+    """Device tensor -> raw pointer (float64, contiguous, on a GPU)."""
+    if t is None:
+        return None
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{what} must be a torch tensor on a GPU")
+    if t.dtype != torch.float64 or not t.is_contiguous():
+        raise TypeError(f"{what} must be contiguous float64")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(getattr(stream, "cuda_stream", stream))
+
+
+# ----------------------------------------------------------------------------
+# struct builders (keep referenced arrays alive on the struct)
+# ----------------------------------------------------------------------------
+def make_grid(shape, lengths=None, order=4, precision=MFWH_FP64, c=None):
+    """shape: points per axis incl. boundary, x LAST (NumPy order)."""
+    d = len(shape)
+    lengths = [1.0] * d if lengths is None else list(lengths)
+    g = mfwh_grid()
+    g.dim = d
+    n = list(reversed([int(s) for s in shape])) + [1] * (3 - d)
+    ln = list(reversed([float(x) for x in lengths])) + [1.0] * (3 - d)
+    for k in range(3):
+        g.n[k] = n[k]
+        g.len[k] = ln[k]
+    g.order = int(order)
+    g.precision = int(precision)
+    g.c = _tptr(c, "c")
+    g._keep = c
+    return g
+
+
+def make_time(omega, T, dt, filt=None):
+    t = mfwh_time()
+    om, p = _dptr(omega)
+    t.nf = om.size
+    t.omega = p
+    if filt is not None:
+        fa, fp = _dptr(np.asarray(filt, dtype=np.float64).reshape(-1))
+        t.filt = fp
+    else:
+        fa = None
+        t.filt = None
+    t.T = float(T)
+    t.dt = float(dt)
+    t._keep = (om, fa)
+    return t
+
+
+def make_opts(restart=30, max_iter=1000, tol=1e-8, inner_tol=1e-5, max_outer=20):
+    o = mfwh_solve_opts()
+    o.restart, o.max_iter, o.tol = int(restart), int(max_iter), float(tol)
+    o.inner_tol, o.max_outer = float(inner_tol), int(max_outer)
+    return o
+
+
+# ----------------------------------------------------------------------------
+# entry points (same names as the C ABI)
+# ----------------------------------------------------------------------------
+def mfwh_plan_time(grid, cmax, omega1, np_, cfl):
+    T, dt, nt = c_double(), c_double(), c_int()
+    _check(LIB.mfwh_plan_time(ctypes.byref(grid), cmax, omega1, np_, cfl, ctypes.byref(T),
+                              ctypes.byref(dt), ctypes.byref(nt)))
+    return T.value, dt.value, nt.value
+
+
+def mfwh_plan_time_implicit(omega1, omega_last, np_, steps_per_period=10):
+    T, dt, nt = c_double(), c_double(), c_int()
+    _check(LIB.mfwh_plan_time_implicit(omega1, omega_last, np_, steps_per_period,
+                                       ctypes.byref(T), ctypes.byref(dt), ctypes.byref(nt)))
+    return T.value, dt.value, nt.value
+
+
+def mfwh_plan_info(time):
+    nf = time.nf
+    ot, tfm = np.zeros(nf), np.zeros(nf)
+    npm = np.zeros(nf, dtype=np.int32)
+    B, Binv = np.zeros((nf, nf)), np.zeros((nf, nf))
+    _check(LIB.mfwh_plan_info(ctypes.byref(time), ot.ctypes.data_as(P_double),
+                              npm.ctypes.data_as(P_int), tfm.ctypes.data_as(P_double),
+                              B.ctypes.data_as(P_double), Binv.ctypes.data_as(P_double)))
+    return dict(omega_tilde=ot, npm=npm, tfm=tfm, B=B, Binv=Binv)
+
+
+def mfwh_plan_coefficients(time):
+    nt = int(round(time.T / time.dt))
+    kap, phi = np.zeros((nt + 1, time.nf)), np.zeros((nt + 1, time.nf))
+    _check(LIB.mfwh_plan_coefficients(ctypes.byref(time), kap.ctypes.data_as(P_double),
+                                      phi.ctypes.data_as(P_double)))
+    return kap, phi
+
+
+def mfwh_filter_adjusted(omega, dt):
+    om, p = _dptr(omega)
+    out = np.zeros((om.size, 3))
+    _check(LIB.mfwh_filter_adjusted(om.size, p, dt, out.ctypes.data_as(P_double)))
+    return out
+
+
+def mfwh_optimize_filter(omega_in, np_, nt, ndelta=20, cdelta=2.0, rcond=0.0):
+    om, p = _dptr(omega_in)
+    out = np.zeros((om.size, 3))
+    lmax, nlam = c_double(), c_int()
+    _check(LIB.mfwh_optimize_filter(om.size, p, np_, nt, ndelta, cdelta, rcond,
+                                    out.ctypes.data_as(P_double), ctypes.byref(lmax),
+                                    ctypes.byref(nlam)))
+    return out, lmax.value, nlam.value
+
+
+def mfwh_workspace_bytes(grid, time, restart=0):
+    return int(LIB.mfwh_workspace_bytes(ctypes.byref(grid), ctypes.byref(time), int(restart)))
+
+
+def mfwh_apply(grid, time, f, v_in, v_out, with_forcing, ws, stream=None):
+    _check(LIB.mfwh_apply(ctypes.byref(grid), ctypes.byref(time), _tptr(f, "f"),
+                          _tptr(v_in, "v_in"), _tptr(v_out, "v_out"), int(with_forcing),
+                          ctypes.c_void_p(ws.data_ptr()), ws.numel() * ws.element_size(),
+                          _stream(stream)))
+
+
+def _solve(fn, grid, time, f, v, opts, ws, stream, hist_len):
+    hist = np.zeros(max(1, hist_len))
+    info = mfwh_solve_info()
+    rc = fn(ctypes.byref(grid), ctypes.byref(time), _tptr(f, "f"), _tptr(v, "v"),
+            ctypes.byref(opts), hist.ctypes.data_as(P_double), ctypes.byref(info),
+            ctypes.c_void_p(ws.data_ptr()), ws.numel() * ws.element_size(), _stream(stream))
+    _check(rc, allow_not_converged=True)
+    return dict(status=STATUS[rc], converged=(rc == 0), iterations=info.iterations,
+                applies=info.applies, outer=info.outer, rel_residual=info.rel_residual,
+                point_steps=info.point_steps, history=hist[:info.iterations].copy())
+
+
+def mfwh_solve_fixed_point(grid, time, f, v, opts, ws, stream=None):
+    return _solve(LIB.mfwh_solve_fixed_point, grid, time, f, v, opts, ws, stream, opts.max_iter)
+
+
+def mfwh_solve_gmres(grid, time, f, v, opts, ws, stream=None):
+    return _solve(LIB.mfwh_solve_gmres, grid, time, f, v, opts, ws, stream, opts.max_iter)
+
+
+def mfwh_stats_enable(on, sample_every=8):
+    _check(LIB.mfwh_stats_enable(int(on), int(sample_every)))
+
+
+def mfwh_stats_read():
+    n, ms, by = c_longlong(), c_double(), c_double()
+    _check(LIB.mfwh_stats_read(ctypes.byref(n), ctypes.byref(ms), ctypes.byref(by)))
+    return n.value, ms.value, by.value
+
+
+def mfwh_set_launch_shape(bx=0, by=1, chunk=8):
+    _check(LIB.mfwh_set_launch_shape(int(bx), int(by), int(chunk)))

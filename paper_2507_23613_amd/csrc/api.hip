@@ -1,0 +1,777 @@
+// C ABI of the MFWH library: planning helpers, one MFWH application, the
+// fixed-point iteration and GMRES (with float32-stencil iterative refinement).
+//
+// Device data never leaves the GPU during a solve except the few scalars a
+// Krylov step needs (one device->host copy of <= 2(j+1)+1 doubles per Arnoldi
+// step).  All scratch lives in the caller's workspace.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/mfwh.h"
+#include "kernels.h"
+#include "plan.h"
+
+namespace mfwh {
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIPCHK(...)                                                                   \
+  do {                                                                                \
+    hipError_t e_ = (__VA_ARGS__);                                                    \
+    if (e_ != hipSuccess)                                                             \
+      return fail(MFWH_EHIP, std::string(#__VA_ARGS__) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+#define CHK(...)                    \
+  do {                              \
+    int r_ = (__VA_ARGS__);         \
+    if (r_ < 0) return r_;          \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// step-kernel timing (HIP events on the launch stream)
+// ---------------------------------------------------------------------------
+struct Stats {
+  std::mutex mu;
+  bool on = false;
+  int every = 8;
+  long long counter = 0;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
+  std::vector<double> pending_bytes;
+  long long launches = 0;
+  double ms = 0.0, bytes = 0.0;
+};
+Stats& stats() {
+  static Stats s;
+  return s;
+}
+
+// ---------------------------------------------------------------------------
+// geometry and workspace
+// ---------------------------------------------------------------------------
+long long round_up(long long x, long long a) { return (x + a - 1) / a * a; }
+
+int make_geom(const mfwh_grid* g, Geom* G) {
+  if (!g) return fail(MFWH_EINVAL, "null grid");
+  if (g->dim < 1 || g->dim > 3) return fail(MFWH_EINVAL, "dim must be 1, 2 or 3");
+  if (g->order != 2 && g->order != 4) return fail(MFWH_EINVAL, "order must be 2 or 4");
+  if (g->precision != MFWH_FP64 && g->precision != MFWH_FP32_STENCIL)
+    return fail(MFWH_EINVAL, "precision must be MFWH_FP64 or MFWH_FP32_STENCIL");
+  for (int k = 0; k < 3; ++k) {
+    if (k < g->dim) {
+      if (g->n[k] < 3) return fail(MFWH_EINVAL, "need at least 3 points per axis");
+      if (!(g->len[k] > 0.0)) return fail(MFWH_EINVAL, "domain lengths must be positive");
+    } else if (g->n[k] != 1) {
+      return fail(MFWH_EINVAL, "n[k] must be 1 beyond dim");
+    }
+  }
+  const long long tot = (long long)g->n[0] * g->n[1] * g->n[2];
+  if (tot > (1LL << 33)) return fail(MFWH_EINVAL, "grid too large");
+  G->dim = g->dim;
+  G->nxi = g->n[0] - 2;
+  G->nyi = g->dim >= 2 ? g->n[1] - 2 : 1;
+  G->nzi = g->dim >= 3 ? g->n[2] - 2 : 1;
+  G->py = g->dim >= 2 ? round_up(G->nxi, 64) : G->nxi;
+  G->pz = G->py * G->nyi;
+  G->fs = round_up(G->pz * G->nzi, 64);
+  return MFWH_OK;
+}
+
+ExtLayout abi_layout(const mfwh_grid* g) {
+  ExtLayout l;
+  const long long n0 = g->n[0], n1 = g->n[1], n2 = g->n[2];
+  l.sy = n0;
+  l.sz = n0 * n1;
+  l.sf = n0 * n1 * n2;
+  l.base = 1 + (g->dim >= 2 ? n0 : 0) + (g->dim >= 3 ? n0 * n1 : 0);
+  return l;
+}
+
+ExtLayout int_layout(const Geom& G) {
+  ExtLayout l;
+  l.base = 0;
+  l.sy = G.py;
+  l.sz = G.pz;
+  l.sf = G.fs;
+  return l;
+}
+
+constexpr int kRedBlocks = 1024;   // reduction blocks of the finalize/BLAS kernels
+
+struct Workspace {
+  double *w64a = nullptr, *w64b = nullptr, *f64 = nullptr, *c64 = nullptr;
+  float *w32a = nullptr, *w32b = nullptr, *f32 = nullptr, *c32 = nullptr;
+  double* q = nullptr;
+  double* partial = nullptr;   // (restart+2) * kRedBlocks doubles
+  double* scal = nullptr;      // device scalars: 4 (restart+2) + 16 doubles
+  double* vec = nullptr;       // nvec vectors of nf*fs doubles
+  int nvec = 0;
+  int nscal = 0;
+  size_t bytes = 0;
+};
+
+// Carve the workspace (base may be null to only compute the size).
+Workspace carve(const Geom& G, int nf, bool fp32, bool varc, int restart, char* base) {
+  Workspace w;
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> char* {
+    off = (off + 255) / 256 * 256;
+    char* p = base ? base + off : nullptr;
+    off += bytes;
+    return p;
+  };
+  const size_t fs = (size_t)G.fs;
+  w.w64a = (double*)take(fs * 8);
+  w.w64b = (double*)take(fs * 8);
+  w.f64 = (double*)take(fs * 8 * nf);
+  if (varc) w.c64 = (double*)take(fs * 8);
+  if (fp32) {
+    w.w32a = (float*)take(fs * 4);
+    w.w32b = (float*)take(fs * 4);
+    w.f32 = (float*)take(fs * 4 * nf);
+    if (varc) w.c32 = (float*)take(fs * 4);
+  }
+  w.q = (double*)take(fs * 8 * nf);
+  const int rs = std::max(restart, 1) + 2;
+  w.partial = (double*)take((size_t)rs * kRedBlocks * 8);
+  w.scal = (double*)take((size_t)(4 * rs + 16) * 8);
+  w.nscal = 4 * rs + 16;
+  if (restart > 0) {
+    w.nvec = restart + 1 + 5;
+    w.vec = (double*)take((size_t)w.nvec * fs * nf * 8);
+  }
+  w.bytes = (off + 255) / 256 * 256;
+  return w;
+}
+
+// ---------------------------------------------------------------------------
+// one problem on the device
+// ---------------------------------------------------------------------------
+struct Problem {
+  const mfwh_grid* grid = nullptr;
+  Geom G{};
+  Plan P;
+  Workspace W;
+  hipStream_t s = nullptr;
+  bool fp32 = false, varc = false;
+  LaunchShape shape64, shape32;
+  long long point_steps = 0;
+  int applies = 0;
+};
+
+LaunchShape g_shape_override;   // bx == 0: use defaults
+bool g_shape_set = false;
+
+int setup(Problem& pr, const mfwh_grid* g, const mfwh_time* t, int restart, void* ws,
+          size_t ws_bytes, void* stream) {
+  CHK(make_geom(g, &pr.G));
+  std::string err;
+  int rc = build_plan(t, &pr.P, &err);
+  if (rc != MFWH_OK) return fail(rc, err);
+  pr.grid = g;
+  pr.fp32 = g->precision == MFWH_FP32_STENCIL;
+  pr.varc = g->c != nullptr;
+  pr.s = (hipStream_t)stream;
+  if (!ws) return fail(MFWH_EWORKSPACE, "null workspace");
+  if (((uintptr_t)ws) % 256) return fail(MFWH_EWORKSPACE, "workspace must be 256-byte aligned");
+  pr.W = carve(pr.G, t->nf, pr.fp32, pr.varc, restart, (char*)ws);
+  if (pr.W.bytes > ws_bytes)
+    return fail(MFWH_EWORKSPACE, "workspace too small: need " + std::to_string(pr.W.bytes) +
+                                     " bytes, got " + std::to_string(ws_bytes));
+  pr.shape64 = default_shape(pr.G, g->order, 8);
+  pr.shape32 = default_shape(pr.G, g->order, 4);
+  if (g_shape_set) pr.shape64 = pr.shape32 = g_shape_override;
+  // stability of explicit leapfrog for c = 1 (variable c is the caller's duty)
+  double h[3];
+  for (int k = 0; k < g->dim; ++k) h[k] = g->len[k] / (g->n[k] - 1);
+  if (!pr.varc && t->dt > dt_max_explicit(g->dim, h, g->order, 1.0) * (1 + 1e-12))
+    return fail(MFWH_ECFL, "dt exceeds the explicit stability limit");
+  return MFWH_OK;
+}
+
+// Convert forcing and wave speed into the internal layout(s).
+int prepare(Problem& pr, const double* f) {
+  const int nf = pr.P.nf;
+  const ExtLayout al = abi_layout(pr.grid), il = int_layout(pr.G);
+  ExtLayout cl = al, ci = il;
+  cl.sf = 0;
+  ci.sf = 0;
+  if (f) {
+    HIPCHK(launch_copy_fields<double, double>(pr.G, nf, f, al, pr.W.f64, il, 0, pr.s));
+    if (pr.fp32) HIPCHK(launch_copy_fields<double, float>(pr.G, nf, f, al, pr.W.f32, il, 0, pr.s));
+  }
+  if (pr.varc) {
+    HIPCHK(launch_copy_fields<double, double>(pr.G, 1, pr.grid->c, cl, pr.W.c64, ci, 1, pr.s));
+    if (pr.fp32)
+      HIPCHK(launch_copy_fields<double, float>(pr.G, 1, pr.grid->c, cl, pr.W.c32, ci, 1, pr.s));
+  }
+  return MFWH_OK;
+}
+
+template <typename T>
+void stencil_weights(const mfwh_grid* g, T wx[3], T wy[3], T wz[3]) {
+  T* ws[3] = {wx, wy, wz};
+  for (int k = 0; k < 3; ++k) {
+    ws[k][0] = ws[k][1] = ws[k][2] = T(0);
+    if (k >= g->dim) continue;
+    const double h = g->len[k] / (g->n[k] - 1);
+    if (g->order == 2) {
+      ws[k][0] = (T)(-2.0 / (h * h));
+      ws[k][1] = (T)(1.0 / (h * h));
+    } else {
+      const double d = 12.0 * h * h;
+      ws[k][0] = (T)(-30.0 / d);
+      ws[k][1] = (T)(16.0 / d);
+      ws[k][2] = (T)(-1.0 / d);
+    }
+  }
+}
+
+// Target of the finalize stage.
+struct Out {
+  double* out;
+  ExtLayout ol;
+  const double* xin = nullptr;   // out = alpha*xin + beta*B^{-1}q when set
+  ExtLayout xl{};
+  double alpha = 0.0, beta = 1.0;
+  double* partial = nullptr;     // FPI residual partial sums
+};
+
+// One MFWH application in precision T.  v == nullptr means V = 0.
+template <typename T>
+int apply_t(Problem& pr, const double* v, ExtLayout vl, bool forcing, const Out& o) {
+  const Plan& P = pr.P;
+  const int nf = P.nf;
+  T* wa;
+  T* wb;
+  const T* f;
+  const T* c2;
+  const LaunchShape* ls;
+  if constexpr (sizeof(T) == 8) {
+    wa = (T*)pr.W.w64a; wb = (T*)pr.W.w64b; f = (const T*)pr.W.f64; c2 = (const T*)pr.W.c64;
+    ls = &pr.shape64;
+  } else {
+    wa = (T*)pr.W.w32a; wb = (T*)pr.W.w32b; f = (const T*)pr.W.f32; c2 = (const T*)pr.W.c32;
+    ls = &pr.shape32;
+  }
+  if (v) HIPCHK(launch_init_w0<T>(pr.G, nf, v, vl, wa, pr.s));
+  else HIPCHK(launch_fill_t<T>(wa, pr.G.fs, T(0), pr.s));
+
+  StepArgs<T> a{};
+  a.c2 = pr.varc ? c2 : nullptr;
+  a.f = forcing ? f : nullptr;
+  a.q = pr.W.q;
+  a.g = pr.G;
+  stencil_weights<T>(pr.grid, a.wx, a.wy, a.wz);
+  a.force = forcing ? 1 : 0;
+  const double dt2 = P.dt * P.dt;
+  const int sort = sizeof(T) == 8 ? 8 : 4;
+  Stats& st = stats();
+  for (int n = 0; n < P.nt; ++n) {
+    const bool first = n == 0;
+    const bool even = (n & 1) == 0;
+    a.wc = even ? wa : wb;
+    a.wp = even ? wb : wa;
+    a.wout = even ? wb : wa;
+    a.first = first ? 1 : 0;
+    a.cA = first ? T(1) : T(2);
+    a.cB = first ? T(0) : T(-1);
+    a.cC = (T)(first ? 0.5 * dt2 : dt2);
+    int mask = 0, nact = 0;
+    for (int m = 0; m < MFWH_MAX_NF; ++m) {
+      if (m < nf) {
+        a.phi[m] = forcing ? (T)P.phi[(size_t)n * nf + m] : T(0);
+        a.kap[m] = P.kappa[(size_t)(n + 1) * nf + m];
+        a.kap0[m] = first ? P.kappa[m] : 0.0;
+        if (first || a.kap[m] != 0.0) { mask |= 1 << m; ++nact; }
+      } else {
+        a.phi[m] = T(0);
+        a.kap[m] = a.kap0[m] = 0.0;
+      }
+    }
+    a.mask = mask;
+    bool timed = false;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (st.on) {
+      std::lock_guard<std::mutex> lk(st.mu);
+      if ((st.counter++ % st.every) == 0 && st.pending.size() < 2000000) {
+        if (hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess) {
+          timed = true;
+          HIPCHK(hipEventRecord(e0, pr.s));
+        }
+      }
+    }
+    HIPCHK(launch_step<T>(a, pr.grid->order, nf, *ls, pr.s));
+    if (timed) {
+      HIPCHK(hipEventRecord(e1, pr.s));
+      // algorithmic bytes: read W^n, W^{n-1}, write W^{n+1}; forcing reads;
+      // read+write of every active accumulator; c^2
+      double bpp = (first ? 2 : 3) * sort + (forcing ? nf * sort : 0) +
+                   (first ? 1 : 2) * 8.0 * nact + (pr.varc ? sort : 0);
+      std::lock_guard<std::mutex> lk(st.mu);
+      st.pending.emplace_back(e0, e1);
+      st.pending_bytes.push_back(bpp * (double)pr.G.npts());
+    }
+  }
+  HIPCHK(launch_finalize(pr.G, nf, pr.W.q, P.Binv, o.xin, o.xl, o.alpha, o.beta, o.out, o.ol,
+                         o.partial, kRedBlocks, pr.s));
+  pr.point_steps += pr.G.npts() * (long long)P.nt;
+  pr.applies += 1;
+  return MFWH_OK;
+}
+
+int apply_any(Problem& pr, bool use32, const double* v, ExtLayout vl, bool forcing,
+              const Out& o) {
+  return use32 ? apply_t<float>(pr, v, vl, forcing, o) : apply_t<double>(pr, v, vl, forcing, o);
+}
+
+// ---------------------------------------------------------------------------
+// device vector helpers (internal vectors: nf*fs doubles, pads kept zero)
+// ---------------------------------------------------------------------------
+struct Vecs {
+  Problem* pr;
+  long long N;
+  int nb;
+  double* vec(int k) const { return pr->W.vec + (size_t)k * N; }
+};
+
+// dot products of y with K vectors starting at X (stride N) -> host out[K]
+int dots(Vecs& V, const double* X, int K, const double* y, double* dev_out, double* host_out) {
+  Problem& pr = *V.pr;
+  HIPCHK(launch_multidot(X, V.N, K, y, V.N, pr.W.partial, V.nb, pr.s));
+  HIPCHK(launch_reduce(pr.W.partial, V.nb, K, dev_out, pr.s));
+  if (host_out) {
+    HIPCHK(hipMemcpyAsync(host_out, dev_out, K * sizeof(double), hipMemcpyDeviceToHost, pr.s));
+    HIPCHK(hipStreamSynchronize(pr.s));
+  }
+  return MFWH_OK;
+}
+
+int norm2(Vecs& V, const double* x, double* out) {
+  double h;
+  CHK(dots(V, x, 1, x, V.pr->W.scal + V.pr->W.nscal - 8, &h));
+  *out = std::sqrt(h);
+  return MFWH_OK;
+}
+
+// ---------------------------------------------------------------------------
+// restarted GMRES on A x = rhs, A = I - S (S in float64 or float32 stencil),
+// x updated in place.  Vector slots: 0..m basis, m+1 work.
+// ---------------------------------------------------------------------------
+struct KrylovResult {
+  int its = 0;
+  double res = 0.0;   // last true residual norm
+  bool converged = false;
+};
+
+int gmres_core(Vecs& V, bool use32, const double* rhs, double* x, bool xzero, double tol_abs,
+               int m, int max_its, double bnorm, double* hist, int hist_off, KrylovResult* kr) {
+  Problem& pr = *V.pr;
+  const ExtLayout il = int_layout(pr.G);
+  double* work = V.vec(m + 1);
+  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+  std::vector<double> hh(2 * (m + 1) + 1);
+  const int rs = m + 2;
+  double* dh1 = pr.W.scal;               // device: first CGS pass coefficients
+  double* dh2 = pr.W.scal + rs;          // second pass
+  double* dnr = pr.W.scal + 2 * rs;      // |w|^2
+  double* dy = pr.W.scal + 3 * rs;       // solution coefficients
+  int its = 0;
+  while (true) {
+    double* v0 = V.vec(0);
+    if (xzero) {
+      HIPCHK(hipMemcpyAsync(v0, rhs, V.N * sizeof(double), hipMemcpyDeviceToDevice, pr.s));
+    } else {
+      Out o{v0, il, x, il, 1.0, -1.0, nullptr};   // v0 = x - S x = A x
+      CHK(apply_any(pr, use32, x, il, false, o));
+      HIPCHK(launch_axpby(1.0, rhs, -1.0, v0, V.N, pr.s));   // v0 = rhs - A x
+    }
+    double beta;
+    CHK(norm2(V, v0, &beta));
+    if (!std::isfinite(beta)) return fail(MFWH_ENONFINITE, "non-finite residual in GMRES");
+    kr->res = beta;
+    if (beta <= tol_abs) { kr->converged = true; break; }
+    if (its >= max_its) break;
+    {
+      double b2 = beta * beta;
+      HIPCHK(hipMemcpyAsync(dnr, &b2, sizeof(double), hipMemcpyHostToDevice, pr.s));
+      HIPCHK(launch_scale_by_rnorm(v0, dnr, v0, V.N, pr.s));
+      HIPCHK(hipStreamSynchronize(pr.s));
+    }
+    std::fill(H.begin(), H.end(), 0.0);
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    int k = 0;
+    bool done = false;
+    for (int j = 0; j < m && its < max_its; ++j) {
+      double* vj = V.vec(j);
+      Out o{work, il, vj, il, 1.0, -1.0, nullptr};
+      CHK(apply_any(pr, use32, vj, il, false, o));           // work = A v_j
+      // classical Gram-Schmidt, twice
+      HIPCHK(launch_multidot(V.vec(0), V.N, j + 1, work, V.N, pr.W.partial, V.nb, pr.s));
+      HIPCHK(launch_reduce(pr.W.partial, V.nb, j + 1, dh1, pr.s));
+      HIPCHK(launch_multiaxpy(V.vec(0), V.N, j + 1, dh1, -1.0, work, V.N, nullptr, V.nb, pr.s));
+      HIPCHK(launch_multidot(V.vec(0), V.N, j + 1, work, V.N, pr.W.partial, V.nb, pr.s));
+      HIPCHK(launch_reduce(pr.W.partial, V.nb, j + 1, dh2, pr.s));
+      HIPCHK(launch_multiaxpy(V.vec(0), V.N, j + 1, dh2, -1.0, work, V.N, pr.W.partial, V.nb,
+                              pr.s));
+      HIPCHK(launch_reduce(pr.W.partial, V.nb, 1, dnr, pr.s));
+      HIPCHK(hipMemcpyAsync(hh.data(), dh1, (j + 1) * sizeof(double), hipMemcpyDeviceToHost, pr.s));
+      HIPCHK(hipMemcpyAsync(hh.data() + (m + 1), dh2, (j + 1) * sizeof(double),
+                            hipMemcpyDeviceToHost, pr.s));
+      HIPCHK(hipMemcpyAsync(hh.data() + 2 * (m + 1), dnr, sizeof(double), hipMemcpyDeviceToHost,
+                            pr.s));
+      HIPCHK(hipStreamSynchronize(pr.s));
+      const double hnext = std::sqrt(hh[2 * (m + 1)]);
+      if (!std::isfinite(hnext)) return fail(MFWH_ENONFINITE, "non-finite Arnoldi vector");
+      for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hh[i] + hh[(m + 1) + i];
+      H[(size_t)(j + 1) * m + j] = hnext;
+      if (hnext > 0.0) HIPCHK(launch_scale_by_rnorm(work, dnr, V.vec(j + 1), V.N, pr.s));
+      // Givens rotations
+      for (int i = 0; i < j; ++i) {
+        const double a0 = H[(size_t)i * m + j], a1 = H[(size_t)(i + 1) * m + j];
+        H[(size_t)i * m + j] = cs[i] * a0 + sn[i] * a1;
+        H[(size_t)(i + 1) * m + j] = -sn[i] * a0 + cs[i] * a1;
+      }
+      const double a0 = H[(size_t)j * m + j], a1 = H[(size_t)(j + 1) * m + j];
+      const double den = std::hypot(a0, a1);
+      cs[j] = den > 0 ? a0 / den : 1.0;
+      sn[j] = den > 0 ? a1 / den : 0.0;
+      H[(size_t)j * m + j] = den;
+      H[(size_t)(j + 1) * m + j] = 0.0;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      ++its;
+      k = j + 1;
+      const double est = std::fabs(g[j + 1]);
+      if (hist) hist[hist_off + its - 1] = est / bnorm;
+      if (est <= tol_abs || hnext == 0.0) { done = true; break; }
+    }
+    // y = R^{-1} g ; x += V y
+    for (int i = k - 1; i >= 0; --i) {
+      double s = g[i];
+      for (int c = i + 1; c < k; ++c) s -= H[(size_t)i * m + c] * y[c];
+      y[i] = H[(size_t)i * m + i] != 0.0 ? s / H[(size_t)i * m + i] : 0.0;
+    }
+    if (k > 0) {
+      HIPCHK(hipMemcpyAsync(dy, y.data(), k * sizeof(double), hipMemcpyHostToDevice, pr.s));
+      HIPCHK(launch_multiaxpy(V.vec(0), V.N, k, dy, 1.0, x, V.N, nullptr, V.nb, pr.s));
+      HIPCHK(hipStreamSynchronize(pr.s));
+      xzero = false;
+    }
+    (void)done;
+    // loop: the true residual is recomputed at the top
+  }
+  kr->its += its;
+  return MFWH_OK;
+}
+
+void fill_opts(const mfwh_solve_opts* in, mfwh_solve_opts* o) {
+  o->restart = 30;
+  o->max_iter = 1000;
+  o->tol = 1e-8;
+  o->inner_tol = 1e-5;
+  o->max_outer = 20;
+  if (in) {
+    if (in->restart > 0) o->restart = in->restart;
+    if (in->max_iter > 0) o->max_iter = in->max_iter;
+    if (in->tol > 0) o->tol = in->tol;
+    if (in->inner_tol > 0) o->inner_tol = in->inner_tol;
+    if (in->max_outer > 0) o->max_outer = in->max_outer;
+  }
+}
+
+}  // namespace
+}  // namespace mfwh
+
+using namespace mfwh;
+
+// =============================================================================
+// C ABI
+// =============================================================================
+extern "C" {
+
+const char* mfwh_last_error(void) { return g_err.c_str(); }
+
+int mfwh_plan_time(const mfwh_grid* g, double cmax, double omega1, int np, double cfl,
+                   double* T, double* dt, int* nt) {
+  Geom G;
+  CHK(make_geom(g, &G));
+  if (!(cmax > 0) || !(omega1 > 0) || np < 1 || !(cfl > 0 && cfl <= 1.0) || !T || !dt || !nt)
+    return fail(MFWH_EINVAL, "bad plan_time arguments");
+  double h[3];
+  for (int k = 0; k < g->dim; ++k) h[k] = g->len[k] / (g->n[k] - 1);
+  const double dtm = dt_max_explicit(g->dim, h, g->order, cmax);
+  const double T1 = 2.0 * M_PI / omega1;
+  const long long n = (long long)std::ceil(np * T1 / (cfl * dtm) - 1e-9);
+  if (n < 2 || n > 100000000LL) return fail(MFWH_EINVAL, "number of steps out of range");
+  *nt = (int)n;
+  *dt = dt_exact_periods(omega1, np, (int)n, 0.0);
+  *T = n * *dt;
+  return MFWH_OK;
+}
+
+int mfwh_plan_time_implicit(double omega1, double omega_last, int np, int spp, double* T,
+                            double* dt, int* nt) {
+  if (!(omega1 > 0) || !(omega_last >= omega1) || np < 1 || spp < 1 || !T || !dt || !nt)
+    return fail(MFWH_EINVAL, "bad plan_time_implicit arguments");
+  const long long n = (long long)std::ceil((double)spp * np * omega_last / omega1 - 1e-9);
+  *nt = (int)n;
+  *dt = dt_exact_periods(omega1, np, (int)n, 0.5);
+  *T = n * *dt;
+  return MFWH_OK;
+}
+
+int mfwh_plan_info(const mfwh_time* t, double* omega_tilde, int* npm, double* tfm, double* B,
+                   double* Binv) {
+  Plan P;
+  std::string err;
+  int rc = build_plan(t, &P, &err);
+  if (rc != MFWH_OK) return fail(rc, err);
+  const int nf = P.nf;
+  for (int m = 0; m < nf; ++m) {
+    if (omega_tilde) omega_tilde[m] = P.omega_t[m];
+    if (npm) npm[m] = P.npm[m];
+    if (tfm) tfm[m] = P.tfm[m];
+  }
+  for (int i = 0; i < nf * nf; ++i) {
+    if (B) B[i] = P.B[i];
+    if (Binv) Binv[i] = P.Binv[i];
+  }
+  return MFWH_OK;
+}
+
+int mfwh_plan_coefficients(const mfwh_time* t, double* kappa, double* phi) {
+  Plan P;
+  std::string err;
+  int rc = build_plan(t, &P, &err);
+  if (rc != MFWH_OK) return fail(rc, err);
+  if (kappa) std::memcpy(kappa, P.kappa.data(), P.kappa.size() * sizeof(double));
+  if (phi) std::memcpy(phi, P.phi.data(), P.phi.size() * sizeof(double));
+  return MFWH_OK;
+}
+
+int mfwh_filter_adjusted(int nf, const double* omega, double dt, double* filt_out) {
+  if (nf < 1 || nf > MFWH_MAX_NF || !omega || !filt_out || !(dt > 0))
+    return fail(MFWH_EINVAL, "bad filter_adjusted arguments");
+  std::string err;
+  int rc = adjusted_params(nf, omega, dt, filt_out, &err);
+  return rc == MFWH_OK ? rc : fail(rc, err);
+}
+
+int mfwh_optimize_filter(int nf, const double* omega_in, int np, int nt, int ndelta,
+                         double cdelta, double rcond, double* filt_out, double* lambda_max,
+                         int* n_lambda) {
+  if (!omega_in || !filt_out) return fail(MFWH_EINVAL, "null argument");
+  std::string err;
+  int rc = optimize_filter(nf, omega_in, np, nt, ndelta, cdelta, rcond, filt_out, lambda_max,
+                           n_lambda, &err);
+  return rc == MFWH_OK ? rc : fail(rc, err);
+}
+
+size_t mfwh_workspace_bytes(const mfwh_grid* g, const mfwh_time* t, int restart) {
+  Geom G;
+  if (make_geom(g, &G) != MFWH_OK || !t || t->nf < 1 || t->nf > MFWH_MAX_NF) return 0;
+  restart = std::max(0, std::min(restart, MFWH_MAX_RESTART));
+  return carve(G, t->nf, g->precision == MFWH_FP32_STENCIL, g->c != nullptr, restart, nullptr)
+      .bytes;
+}
+
+int mfwh_apply(const mfwh_grid* g, const mfwh_time* t, const double* f, const double* v_in,
+               double* v_out, int with_forcing, void* ws, size_t ws_bytes, void* stream) {
+  Problem pr;
+  CHK(setup(pr, g, t, 0, ws, ws_bytes, stream));
+  if (!v_in || !v_out || (with_forcing && !f)) return fail(MFWH_EINVAL, "null array");
+  CHK(prepare(pr, with_forcing ? f : nullptr));
+  const ExtLayout al = abi_layout(g);
+  Out o{v_out, al};
+  CHK(apply_any(pr, pr.fp32, v_in, al, with_forcing != 0, o));
+  HIPCHK(launch_zero_boundary(g->dim, g->n, t->nf, v_out, pr.s));
+  return MFWH_OK;
+}
+
+int mfwh_solve_fixed_point(const mfwh_grid* g, const mfwh_time* t, const double* f, double* v,
+                           const mfwh_solve_opts* opts, double* res_hist, mfwh_solve_info* info,
+                           void* ws, size_t ws_bytes, void* stream) {
+  Problem pr;
+  CHK(setup(pr, g, t, 0, ws, ws_bytes, stream));
+  if (!v || !f) return fail(MFWH_EINVAL, "null array");
+  mfwh_solve_opts o;
+  fill_opts(opts, &o);
+  CHK(prepare(pr, f));
+  const ExtLayout al = abi_layout(g);
+  HIPCHK(launch_zero_boundary(g->dim, g->n, t->nf, v, pr.s));
+  const double denom = (double)t->nf * (double)pr.G.npts();
+  double r1 = 0.0, r = 0.0;
+  int k = 0;
+  int status = MFWH_NOT_CONVERGED;
+  const int nb = (int)std::min<long long>((pr.G.npts() + 255) / 256, kRedBlocks);
+  for (k = 1; k <= o.max_iter; ++k) {
+    Out out{v, al, nullptr, {}, 0.0, 1.0, pr.W.partial};
+    CHK(apply_any(pr, pr.fp32, v, al, true, out));
+    HIPCHK(launch_reduce(pr.W.partial, nb, 1, pr.W.scal, pr.s));
+    double s2;
+    HIPCHK(hipMemcpyAsync(&s2, pr.W.scal, sizeof(double), hipMemcpyDeviceToHost, pr.s));
+    HIPCHK(hipStreamSynchronize(pr.s));
+    r = std::sqrt(s2 / denom);
+    if (!std::isfinite(r)) return fail(MFWH_ENONFINITE, "non-finite fixed-point residual");
+    if (k == 1) r1 = r;
+    if (res_hist) res_hist[k - 1] = r;
+    if (r <= o.tol * r1 || r == 0.0) { status = MFWH_OK; break; }
+  }
+  if (k > o.max_iter) k = o.max_iter;
+  if (info) {
+    info->iterations = k;
+    info->applies = pr.applies;
+    info->outer = 0;
+    info->rel_residual = r1 > 0 ? r / r1 : 0.0;
+    info->point_steps = pr.point_steps;
+  }
+  return status;
+}
+
+int mfwh_solve_gmres(const mfwh_grid* g, const mfwh_time* t, const double* f, double* v,
+                     const mfwh_solve_opts* opts, double* res_hist, mfwh_solve_info* info,
+                     void* ws, size_t ws_bytes, void* stream) {
+  mfwh_solve_opts o;
+  fill_opts(opts, &o);
+  if (o.restart > MFWH_MAX_RESTART) return fail(MFWH_EINVAL, "restart too large");
+  Problem pr;
+  CHK(setup(pr, g, t, o.restart, ws, ws_bytes, stream));
+  if (!v || !f) return fail(MFWH_EINVAL, "null array");
+  CHK(prepare(pr, f));
+  const ExtLayout al = abi_layout(g), il = int_layout(pr.G);
+  const int nf = t->nf;
+  Vecs V{&pr, (long long)nf * pr.G.fs, 0};
+  V.nb = blas_blocks(V.N);
+  const int m = o.restart;
+  double* X = V.vec(m + 2);
+  double* B = V.vec(m + 3);
+  double* R = V.vec(m + 4);
+  double* D = V.vec(m + 5);
+  // Kernels write interior points only: clear every vector once so the row
+  // padding of the internal layout is zero and stays zero under the BLAS-1
+  // operations (which run over the padded length).
+  HIPCHK(launch_fill(pr.W.vec, (long long)pr.W.nvec * V.N, 0.0, pr.s));
+  // b = W_h(0) in float64 (Section 7)
+  {
+    Out ob{B, il};
+    CHK(apply_t<double>(pr, nullptr, il, true, ob));
+  }
+  double bnorm;
+  CHK(norm2(V, B, &bnorm));
+  if (!(bnorm > 0)) return fail(MFWH_EINVAL, "zero right-hand side (all forcings vanish)");
+  // initial guess -> internal layout (pads already zero)
+  HIPCHK(launch_copy_fields<double, double>(pr.G, nf, v, al, X, il, 0, pr.s));
+  double xn;
+  CHK(norm2(V, X, &xn));
+  bool xzero = xn == 0.0;
+  KrylovResult kr;
+  int status = MFWH_NOT_CONVERGED;
+  int outer = 0;
+  double relres = 1.0;
+  if (!pr.fp32) {
+    CHK(gmres_core(V, false, B, X, xzero, o.tol * bnorm, m, o.max_iter, bnorm, res_hist, 0, &kr));
+    relres = kr.res / bnorm;
+    if (kr.converged) status = MFWH_OK;
+  } else {
+    // iterative refinement: float64 outer residual, float32-stencil inner GMRES
+    for (outer = 0; outer < o.max_outer; ++outer) {
+      if (xzero) {
+        HIPCHK(hipMemcpyAsync(R, B, V.N * sizeof(double), hipMemcpyDeviceToDevice, pr.s));
+      } else {
+        Out orr{R, il, X, il, 1.0, -1.0, nullptr};
+        CHK(apply_t<double>(pr, X, il, false, orr));
+        HIPCHK(launch_axpby(1.0, B, -1.0, R, V.N, pr.s));
+      }
+      double rn;
+      CHK(norm2(V, R, &rn));
+      if (!std::isfinite(rn)) return fail(MFWH_ENONFINITE, "non-finite outer residual");
+      relres = rn / bnorm;
+      if (relres <= o.tol) { status = MFWH_OK; break; }
+      if (kr.its >= o.max_iter) break;
+      HIPCHK(launch_fill(D, V.N, 0.0, pr.s));
+      KrylovResult ki;
+      const double tol_in = std::max(o.inner_tol * rn, 0.3 * o.tol * bnorm);
+      CHK(gmres_core(V, true, R, D, true, tol_in, m, o.max_iter - kr.its, bnorm, res_hist,
+                     kr.its, &ki));
+      kr.its += ki.its;
+      HIPCHK(launch_axpby(1.0, D, 1.0, X, V.N, pr.s));
+      xzero = false;
+    }
+  }
+  HIPCHK(launch_copy_fields<double, double>(pr.G, nf, X, il, v, al, 0, pr.s));
+  HIPCHK(launch_zero_boundary(g->dim, g->n, nf, v, pr.s));
+  HIPCHK(hipStreamSynchronize(pr.s));
+  if (info) {
+    info->iterations = kr.its;
+    info->applies = pr.applies;
+    info->outer = outer;
+    info->rel_residual = relres;
+    info->point_steps = pr.point_steps;
+  }
+  return status;
+}
+
+int mfwh_stats_enable(int on, int sample_every) {
+  Stats& st = stats();
+  std::lock_guard<std::mutex> lk(st.mu);
+  st.on = on != 0;
+  st.every = std::max(1, sample_every);
+  st.counter = 0;
+  return MFWH_OK;
+}
+
+int mfwh_stats_read(long long* launches, double* total_ms, double* total_bytes) {
+  Stats& st = stats();
+  std::lock_guard<std::mutex> lk(st.mu);
+  for (size_t k = 0; k < st.pending.size(); ++k) {
+    auto& pe = st.pending[k];
+    HIPCHK(hipEventSynchronize(pe.second));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, pe.first, pe.second));
+    st.ms += ms;
+    st.bytes += st.pending_bytes[k];
+    st.launches += 1;
+    (void)hipEventDestroy(pe.first);
+    (void)hipEventDestroy(pe.second);
+  }
+  st.pending.clear();
+  st.pending_bytes.clear();
+  if (launches) *launches = st.launches;
+  if (total_ms) *total_ms = st.ms;
+  if (total_bytes) *total_bytes = st.bytes;
+  st.launches = 0;
+  st.ms = 0.0;
+  st.bytes = 0.0;
+  return MFWH_OK;
+}
+
+int mfwh_set_launch_shape(int bx, int by, int chunk) {
+  if (bx == 0) {
+    g_shape_set = false;
+    return MFWH_OK;
+  }
+  if (!((bx == 64 || bx == 128 || bx == 256 || bx == 32) && by >= 1 && chunk >= 1))
+    return fail(MFWH_EINVAL, "bad launch shape");
+  g_shape_override.bx = bx;
+  g_shape_override.by = by;
+  g_shape_override.chunk = chunk;
+  g_shape_set = true;
+  return MFWH_OK;
+}
+
+}  // extern "C"

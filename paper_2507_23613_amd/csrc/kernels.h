@@ -1,0 +1,93 @@
+// Device-side data structures and kernel launchers of the MFWH library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "../../include/mfwh.h"
+
+namespace mfwh {
+
+// Internal layout of a grid field: interior points only (the Dirichlet
+// boundary values are zero and never stored), x fastest, rows padded to 64
+// elements so every row starts on a 256/512-byte boundary.
+struct Geom {
+  int dim;
+  int nxi, nyi, nzi;        // interior points per axis (1 for unused axes)
+  long long py, pz, fs;     // y pitch, z pitch, field stride (elements)
+  __host__ __device__ long long npts() const { return (long long)nxi * nyi * nzi; }
+};
+
+// Addressing of an arbitrary caller array by interior index (i, j, k):
+//   offset = base + k*sz + j*sy + i,  field stride sf.
+struct ExtLayout {
+  long long base, sy, sz, sf;
+};
+
+// Arguments of one fused leapfrog + filter step.
+//   W^{n+1} = cA W^n + cB W^{n-1} + cC (c^2 Delta_h W^n - sum_m phi_m f_m)
+//   q_m    += kap_m W^{n+1}                      (first == 0)
+//   q_m     = kap0_m W^n + kap_m W^{n+1}          (first == 1)
+template <typename T>
+struct StepArgs {
+  const T* wc;          // W^n
+  const T* wp;          // W^{n-1} (not read when first)
+  T* wout;              // W^{n+1} (may alias wp)
+  const T* c2;          // c^2 or nullptr (c = 1)
+  const T* f;           // forcing fields [nf][fs] or nullptr
+  double* q;            // filter accumulators [nf][fs]
+  Geom g;
+  T wx[3], wy[3], wz[3];  // symmetric stencil weights per axis: w[0] centre, w[k] offset +-k
+  T cA, cB, cC;
+  T phi[MFWH_MAX_NF];
+  double kap[MFWH_MAX_NF];
+  double kap0[MFWH_MAX_NF];
+  int first;
+  int force;
+  int mask;             // bit m: filter m is updated at this step
+  int nchunk;           // chunks along the march axis
+  int chunk;            // rows / planes per chunk
+  int ntx, nty;         // tiles along x (and y in 3D)
+  int nblocks;          // logical blocks (grid is padded to a multiple of 8)
+};
+
+struct LaunchShape {
+  int bx = 64;      // threads along x per block
+  int by = 1;       // threads along y per block (3D)
+  int chunk = 8;    // rows (2D) / planes (3D) marched per block
+};
+
+// kernels.hip
+template <typename T>
+hipError_t launch_step(const StepArgs<T>& a, int order, int nf, const LaunchShape& ls,
+                       hipStream_t s);
+LaunchShape default_shape(const Geom& g, int order, int bytes_w);
+
+template <typename T>
+hipError_t launch_init_w0(const Geom& g, int nf, const double* v, ExtLayout vl, T* w0,
+                          hipStream_t s);
+template <typename TI, typename TO>
+hipError_t launch_copy_fields(const Geom& g, int nf, const TI* src, ExtLayout sl, TO* dst,
+                              ExtLayout dl, int square, hipStream_t s);
+hipError_t launch_finalize(const Geom& g, int nf, const double* q, const double* binv,
+                           const double* xin, ExtLayout xl, double alpha, double beta,
+                           double* out, ExtLayout ol, double* partial, int nblk_red,
+                           hipStream_t s);
+hipError_t launch_zero_boundary(int dim, const int* n, int nf, double* v, hipStream_t s);
+hipError_t launch_fill(double* x, long long n, double v, hipStream_t s);
+template <typename T>
+hipError_t launch_fill_t(T* x, long long n, T v, hipStream_t s);
+
+// BLAS-1 on contiguous float64 vectors (deterministic two-pass reductions)
+int blas_blocks(long long n);
+hipError_t launch_multidot(const double* X, long long ldx, int K, const double* y,
+                           long long n, double* partial, int nb, hipStream_t s);
+hipError_t launch_reduce(const double* partial, int nb, int K, double* out, hipStream_t s);
+hipError_t launch_multiaxpy(const double* X, long long ldx, int K, const double* h,
+                            double sign, double* y, long long n, double* partial_sq, int nb,
+                            hipStream_t s);
+hipError_t launch_scale_by_rnorm(const double* x, const double* nrm2, double* y, long long n,
+                                 hipStream_t s);
+hipError_t launch_axpby(double a, const double* x, double b, double* y, long long n,
+                        hipStream_t s);
+
+}  // namespace mfwh

@@ -1,0 +1,37 @@
+// Host-side plan of one MFWH problem (float64).  See plan.cpp.
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "../../include/mfwh.h"
+
+namespace mfwh {
+
+struct Plan {
+  int nf = 0;
+  int nt = 0;                       // number of time steps N_t
+  double dt = 0.0, T = 0.0;         // T = N_t dt
+  double omega[MFWH_MAX_NF] = {};   // physical frequencies
+  double omega_t[MFWH_MAX_NF] = {}; // modified frequencies (explicit scheme)
+  int npm[MFWH_MAX_NF] = {};        // N_{p,m}
+  double tfm[MFWH_MAX_NF] = {};     // T~_{f,m}
+  double params[MFWH_MAX_NF][3] = {};
+  int last_active[MFWH_MAX_NF] = {};  // last step n with kappa[n][m] != 0
+  std::vector<double> kappa;        // (nt+1) x nf, row n
+  std::vector<double> phi;          // (nt+1) x nf, row n
+  double B[MFWH_MAX_NF * MFWH_MAX_NF] = {};
+  double Binv[MFWH_MAX_NF * MFWH_MAX_NF] = {};
+};
+
+double omega_tilde(double omega, double dt, double alpha);
+double dt_max_explicit(int dim, const double* h, int order, double cmax);
+double dt_exact_periods(double omega1, int np, int nt, double alpha);
+void trapezoid_weights(int nt, double dt, double T, double* sigma, int stride);
+int build_plan(const mfwh_time* t, Plan* p, std::string* err);
+int adjusted_params(int nf, const double* omega, double dt, double* out, std::string* err);
+int optimize_filter(int nf, const double* om, int np, int nt, int ndelta, double cdelta,
+                    double rcond, double* out, double* lmax_out, int* nlam_out,
+                    std::string* err);
+
+}  // namespace mfwh

@@ -1,0 +1,82 @@
+"""Set up one MFWH problem on the GPU from a workload description.
+
+Plans the time grid and the filter with the library's own host planner
+(mfwh_plan_time, mfwh_plan_info, mfwh_filter_adjusted, mfwh_optimize_filter),
+moves forcings and wave speed to device tensors, allocates the workspace with
+PyTorch and calls the C ABI.  Nothing here computes any part of the method.
+"""
+import numpy as np
+import torch
+
+from . import _lib as L
+
+
+class GpuProblem:
+    """``w``: workload dict from ``paper_2507_23613_amd.inputs``."""
+
+    def __init__(self, w, precision=L.MFWH_FP64, restart=30, device="cuda", filt=None,
+                 time=None):
+        self.w = w
+        self.device = torch.device(device)
+        self.shape = tuple(w["shape"])
+        self.nf = len(w["omega"])
+        self.omega = np.asarray(w["omega"], dtype=np.float64)
+        self.c = None if w["c"] is None else torch.as_tensor(
+            np.ascontiguousarray(w["c"]), dtype=torch.float64, device=self.device)
+        cmax = 1.0 if w["c"] is None else float(np.max(w["c"]))
+        self.grid = L.make_grid(self.shape, w["lengths"], w["order"], precision, self.c)
+        if time is None:
+            T, dt, nt = L.mfwh_plan_time(self.grid, cmax, float(self.omega[0]), int(w["np"]),
+                                         float(w["cfl"]))
+        else:
+            T, dt, nt = time
+        self.T, self.dt, self.nt = T, dt, nt
+        kind = w["filter"] if filt is None else filt
+        if isinstance(kind, np.ndarray):
+            params = kind
+        elif kind == "traditional":
+            params = None
+        elif kind == "adjusted":
+            params = L.mfwh_filter_adjusted(self.omega, dt)
+        elif kind == "optimised":
+            info = L.mfwh_plan_info(L.make_time(self.omega, T, dt))
+            params, _, _ = L.mfwh_optimize_filter(info["omega_tilde"], int(w["np"]), nt,
+                                                  rcond=w.get("filter_rcond", 0.0))
+        else:
+            raise ValueError(f"unknown filter {kind!r}")
+        self.params = params
+        self.time = L.make_time(self.omega, T, dt, params)
+        self.plan = L.mfwh_plan_info(self.time)
+        self.f = torch.as_tensor(np.ascontiguousarray(w["f"]), dtype=torch.float64,
+                                 device=self.device)
+        self.restart = restart
+        nbytes = L.mfwh_workspace_bytes(self.grid, self.time, restart)
+        if nbytes == 0:
+            raise L.MfwhError(-1, "invalid problem description")
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+
+    @property
+    def interior_points(self):
+        return int(np.prod([s - 2 for s in self.shape]))
+
+    def zeros(self):
+        return torch.zeros((self.nf,) + self.shape, dtype=torch.float64, device=self.device)
+
+    def apply(self, v, forcing=True, out=None):
+        out = torch.empty_like(v) if out is None else out
+        L.mfwh_apply(self.grid, self.time, self.f if forcing else None, v, out, forcing,
+                     self.ws)
+        return out
+
+    def gmres(self, v=None, restart=None, max_iter=1000, tol=1e-8, inner_tol=1e-5,
+              max_outer=20):
+        v = self.zeros() if v is None else v
+        opts = L.make_opts(restart or self.restart, max_iter, tol, inner_tol, max_outer)
+        info = L.mfwh_solve_gmres(self.grid, self.time, self.f, v, opts, self.ws)
+        return v, info
+
+    def fixed_point(self, v=None, max_iter=100, tol=1e-300):
+        v = self.zeros() if v is None else v
+        opts = L.make_opts(1, max_iter, tol)
+        info = L.mfwh_solve_fixed_point(self.grid, self.time, self.f, v, opts, self.ws)
+        return v, info

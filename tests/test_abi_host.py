@@ -1,0 +1,160 @@
+"""Host-side checks of the C ABI library (no GPU needed).
+
+* the library loads and exports every function include/mfwh.h declares;
+* the C++ planner reproduces the paper's printed numbers (recipe, N_{p,m},
+  Lambda, optimised parameters) and agrees with the oracle's planner;
+* argument validation rejects bad input before any device work.
+"""
+import ctypes
+import json
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import plan as P
+from oracle import workload
+from paper_2507_23613_amd import _lib as L
+from paper_2507_23613_amd import inputs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+GOLD = json.load(open(os.path.join(ROOT, "tests", "golden", "paper_printed.json")))
+
+
+def declared_functions():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", fn)).read()
+            txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+            names |= set(re.findall(r"\b(mfwh_\w+)\s*\(", txt))
+    return sorted(names)
+
+
+def test_library_exports_every_declared_function():
+    names = declared_functions()
+    assert len(names) >= 14
+    lib = ctypes.CDLL(L.LIB_PATH)
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def _close_4sig(x, printed):
+    e = math.floor(math.log10(abs(printed)))
+    return abs(x - printed) <= 0.5 * 10.0 ** (e - 3) * 1.01
+
+
+@pytest.mark.parametrize("case", GOLD["recipe_implicit"], ids=lambda c: f"om{c['omega']}-np{c['np']}")
+def test_planner_printed_numbers(case):
+    om = np.array(case["omega"], dtype=float)
+    T, dt, nt = L.mfwh_plan_time_implicit(om[0], om[-1], case["np"], 10)
+    assert nt == case["nt"]
+    assert round(T, case["Tf_digits"]) == pytest.approx(case["Tf"], abs=1e-12)
+    # omega~ of the trapezoid scheme (eq. omegaImplicit with alpha = 1/2)
+    om_t = np.arccos(1.0 / (1.0 + 0.5 * (om * dt) ** 2)) / dt
+    p, lmax, nlam = L.mfwh_optimize_filter(om_t, case["np"], nt)
+    assert nlam == case["n_lambda"]
+    assert lmax == pytest.approx(case["lambda_max"], abs=case["lambda_max_tol"])
+    if "p_tilde" in case:
+        for m, row in enumerate(case["p_tilde"]):
+            for k in range(3):
+                assert _close_4sig(p[m, k], row[k]), (m, k, p[m, k], row[k])
+
+
+def test_planner_explicit_square128():
+    g = GOLD["explicit_square128"]
+    grid = L.make_grid((g["cells"] + 1, g["cells"] + 1), order=4)
+    T, dt, nt = L.mfwh_plan_time(grid, 1.0, g["omega"][0], g["np"], g["cfl"])
+    info = L.mfwh_plan_info(L.make_time(g["omega"], T, dt))
+    assert list(info["npm"]) == g["npm"]
+
+
+WORKLOADS = [
+    lambda: inputs.config1(0),
+    lambda: inputs.small(seed=3, shape=(33, 29), nf=3, order=4),
+    lambda: inputs.small(seed=4, shape=(9, 10, 11), nf=5, order=2, varc=True),
+    lambda: inputs.paper_square128(),
+    lambda: dict(inputs.config2(0, n=65), f=None),
+    lambda: dict(inputs.config3(0, n=17), f=None),
+]
+
+
+@pytest.mark.parametrize("mk", WORKLOADS, ids=["cfg1", "2d", "3d-varc", "paper128", "cfg2-65", "cfg3-17"])
+def test_planner_matches_oracle(mk):
+    w = mk()
+    prob, pl = workload.setup(w)
+    cmax = 1.0 if w["c"] is None else float(np.max(w["c"]))
+    grid = L.make_grid(w["shape"], w["lengths"], w["order"])
+    T, dt, nt = L.mfwh_plan_time(grid, cmax, w["omega"][0], w["np"], w["cfl"])
+    assert nt == pl.nt
+    assert dt == pytest.approx(pl.dt, rel=1e-14)
+    assert T == pytest.approx(pl.Tf, rel=1e-14)
+    if w["filter"] == "optimised":
+        info0 = L.mfwh_plan_info(L.make_time(w["omega"], T, dt))
+        params, _, _ = L.mfwh_optimize_filter(info0["omega_tilde"], w["np"], nt,
+                                              rcond=w.get("filter_rcond", 0.0))
+        scale = max(1.0, np.abs(pl.params).max())
+        assert np.allclose(params, pl.params, rtol=1e-8, atol=1e-9 * scale)
+    elif w["filter"] == "adjusted":
+        params = L.mfwh_filter_adjusted(w["omega"], dt)
+        assert np.allclose(params, pl.params, rtol=1e-14, atol=1e-15)
+    else:
+        params = None
+    # the plan arithmetic is compared on identical filter parameters
+    tm = L.make_time(w["omega"], T, dt, None if w["filter"] == "traditional" else pl.params)
+    info = L.mfwh_plan_info(tm)
+    assert np.allclose(info["omega_tilde"], pl.omega_t, rtol=1e-14)
+    assert list(info["npm"]) == list(pl.npm)
+    assert np.allclose(info["tfm"], pl.tfm, rtol=1e-14)
+    assert np.allclose(info["B"], pl.B, rtol=1e-11, atol=1e-12)
+    assert np.allclose(info["Binv"], pl.Binv, rtol=1e-9, atol=1e-10 * np.abs(pl.Binv).max())
+    kap, phi = L.mfwh_plan_coefficients(tm)
+    # rounding of cos at arguments up to ~2 pi N_{p,m} differs in the last bits
+    assert np.allclose(kap, pl.kappa, rtol=1e-11, atol=1e-12 * np.abs(pl.kappa).max())
+    assert np.allclose(phi, pl.phi, rtol=1e-11, atol=1e-12)
+
+
+def _no_gpu():
+    import torch
+    return not torch.cuda.is_available()
+
+
+def _bad(rc_expected, **kw):
+    g = L.make_grid((17, 17), order=4)
+    om = kw.get("omega", [5.0, 9.0])
+    T, dt, nt = L.mfwh_plan_time(g, 1.0, om[0] if om[0] > 0 else 5.0, 1, 0.5)
+    t = L.make_time(om, kw.get("T", T), kw.get("dt", dt))
+    if "grid" in kw:
+        g = kw["grid"]
+    fake = ctypes.c_void_p(1 << 20)   # never dereferenced: validation fails first
+    rc = L.LIB.mfwh_apply(ctypes.byref(g), ctypes.byref(t), fake, fake, fake, 1, fake,
+                          1 << 40, None)
+    assert rc == rc_expected, (rc, L.LIB.mfwh_last_error())
+
+
+@pytest.mark.skipif(not _no_gpu(), reason="uses placeholder device pointers: host-only check")
+def test_validation_errors():
+    _bad(-2, omega=[9.0, 5.0])                 # not ascending
+    _bad(-2, omega=[5.0, 5.0])                 # not distinct
+    _bad(-2, omega=[-1.0, 5.0])                # not positive
+    g = L.make_grid((17, 17), order=4)
+    T, dt, nt = L.mfwh_plan_time(g, 1.0, 5.0, 1, 0.5)
+    _bad(-5, T=T + 0.37 * dt)                  # T/dt not an integer
+    _bad(-3, omega=[5.0, 3.0 / dt])            # omega*dt >= 2
+    bad = L.make_grid((17, 17), order=3)
+    _bad(-1, grid=bad)                         # order 3
+    bad = L.make_grid((17, 2), order=2)
+    _bad(-1, grid=bad)                         # fewer than 3 points
+    _bad(-3, dt=dt * 2.5, T=T * 2.5)           # beyond the stability limit
+    assert L.mfwh_workspace_bytes(L.make_grid((17, 17), order=3), L.make_time([1.0], 1.0, 0.1)) == 0
+
+
+def test_workspace_size_grows_with_restart():
+    g = L.make_grid((33, 33), order=4)
+    t = L.make_time([5.0, 9.0], 1.0, 0.01)
+    a, b = L.mfwh_workspace_bytes(g, t, 0), L.mfwh_workspace_bytes(g, t, 30)
+    assert b > a > 0
+    # 31 basis + 5 work vectors of nf * fs doubles
+    assert b - a >= 36 * 2 * 31 * 64 * 8

@@ -19,7 +19,7 @@ import math
 import numpy as np
 import pytest
 
-from oracle import fd, mfwh
+from oracle import fd, mfwh, workload
 from oracle import plan as P
 from paper_2507_23613_amd import inputs
 
@@ -88,20 +88,7 @@ def test_direct_vs_dst(shape, order):
 # the MFWH application
 # ----------------------------------------------------------------------------
 def _setup(w, filt=None):
-    prob = mfwh.Problem(w["shape"], w["order"], w["lengths"], w["c"])
-    cmax = 1.0 if w["c"] is None else float(np.max(w["c"]))
-    Tf, dt, nt = P.time_step_explicit(w["omega"][0], w["np"], prob.h, len(w["shape"]),
-                                      w["order"], cmax, w["cfl"])
-    om_t = P.omega_tilde(w["omega"], dt)
-    if filt is None:
-        filt = w["filter"]
-    if filt == "optimised":
-        params, _, _ = P.optimise_filter_discrete(om_t, w["np"], nt)
-    elif filt == "adjusted":
-        params = P.adjusted_traditional_params(om_t, dt)
-    else:
-        params = None
-    return prob, P.Plan(w["omega"], Tf, dt, params)
+    return workload.setup(w, filt)
 
 
 def _direct(prob, w):
