@@ -218,6 +218,15 @@ int mfwh_stats_read(long long* launches, double* total_ms, double* total_bytes);
  * planes (3D) marched per block.  bx = 0 restores the built-in heuristic. */
 int mfwh_set_launch_shape(int bx, int by, int chunk);
 
+/* Process-wide options.
+ * MFWH_OPT_GRAPHS (default 1): the fixed-point and GMRES solvers record the
+ * N_t step launches of an application into a HIP graph once per solve and
+ * replay it for every application; 0 launches every step from the host.
+ * While step timing (mfwh_stats_enable) is on, a graph replay is timed as a
+ * whole and counted as N_t launches. */
+enum { MFWH_OPT_GRAPHS = 1 };
+int mfwh_set_option(int key, long long value);
+
 #ifdef __cplusplus
 }
 #endif

@@ -90,6 +90,7 @@ def _load():
         "mfwh_stats_enable": (c_int, [c_int, c_int]),
         "mfwh_stats_read": (c_int, [ctypes.POINTER(c_longlong), P_double, P_double]),
         "mfwh_set_launch_shape": (c_int, [c_int, c_int, c_int]),
+        "mfwh_set_option": (c_int, [c_int, c_longlong]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -269,6 +270,13 @@ def mfwh_stats_read():
     n, ms, by = c_longlong(), c_double(), c_double()
     _check(LIB.mfwh_stats_read(ctypes.byref(n), ctypes.byref(ms), ctypes.byref(by)))
     return n.value, ms.value, by.value
+
+
+MFWH_OPT_GRAPHS = 1
+
+
+def mfwh_set_option(key, value):
+    _check(LIB.mfwh_set_option(int(key), int(value)))
 
 
 def mfwh_set_launch_shape(bx=0, by=1, chunk=8):

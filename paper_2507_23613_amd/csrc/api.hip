@@ -51,6 +51,7 @@ struct Stats {
   long long counter = 0;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
   std::vector<double> pending_bytes;
+  std::vector<int> pending_count;     // step launches covered by each event pair
   long long launches = 0;
   double ms = 0.0, bytes = 0.0;
 };
@@ -160,6 +161,14 @@ Workspace carve(const Geom& G, int nf, bool fp32, bool varc, int restart, char* 
 // ---------------------------------------------------------------------------
 // one problem on the device
 // ---------------------------------------------------------------------------
+// The N_t step launches of one application depend only on the problem's
+// buffers, its plan, the precision and the forcing flag, so a solver records
+// them once into a HIP graph and replays it for every application.
+struct StepGraph {
+  hipGraph_t g = nullptr;
+  hipGraphExec_t x = nullptr;
+};
+
 struct Problem {
   const mfwh_grid* grid = nullptr;
   Geom G{};
@@ -167,13 +176,23 @@ struct Problem {
   Workspace W;
   hipStream_t s = nullptr;
   bool fp32 = false, varc = false;
+  bool graphs = false;               // replay recorded step sequences
   LaunchShape shape64, shape32;
   long long point_steps = 0;
   int applies = 0;
+  StepGraph sg[2][2];                // [float32][forcing]
+  ~Problem() {
+    for (auto& a : sg)
+      for (auto& b : a) {
+        if (b.x) (void)hipGraphExecDestroy(b.x);
+        if (b.g) (void)hipGraphDestroy(b.g);
+      }
+  }
 };
 
 LaunchShape g_shape_override;   // bx == 0: use defaults
 bool g_shape_set = false;
+bool g_graphs = true;           // solvers record step sequences into graphs
 
 int setup(Problem& pr, const mfwh_grid* g, const mfwh_time* t, int restart, void* ws,
           size_t ws_bytes, void* stream) {
@@ -277,10 +296,11 @@ int apply_t(Problem& pr, const double* v, ExtLayout vl, bool forcing, const Out&
   a.g = pr.G;
   stencil_weights<T>(pr.grid, a.wx, a.wy, a.wz);
   a.force = forcing ? 1 : 0;
-  const double dt2 = P.dt * P.dt;
   const int sort = sizeof(T) == 8 ? 8 : 4;
-  Stats& st = stats();
-  for (int n = 0; n < P.nt; ++n) {
+  double bytes_all = 0.0;          // algorithmic bytes of the whole sequence
+  // one step: W^{n+1} from W^n (and W^{n-1}); launched on stream `s`
+  auto step = [&](int n, hipStream_t s, double* bytes) -> hipError_t {
+    const double dt2 = P.dt * P.dt;
     const bool first = n == 0;
     const bool even = (n & 1) == 0;
     a.wc = even ? wa : wb;
@@ -303,27 +323,80 @@ int apply_t(Problem& pr, const double* v, ExtLayout vl, bool forcing, const Out&
       }
     }
     a.mask = mask;
+    // algorithmic bytes: read W^n (and W^{n-1}), write W^{n+1}; forcing
+    // reads; read+write of every active float64 accumulator (write only on
+    // the first step); c^2
+    *bytes = ((first ? 2 : 3) * sort + (forcing ? nf * sort : 0) +
+              (first ? 1 : 2) * 8.0 * nact + (pr.varc ? sort : 0)) * (double)pr.G.npts();
+    return launch_step<T>(a, pr.grid->order, nf, *ls, s);
+  };
+  Stats& st = stats();
+  if (pr.graphs) {
+    StepGraph& sg = pr.sg[sizeof(T) == 4 ? 1 : 0][forcing ? 1 : 0];
+    if (!sg.x) {
+      hipStream_t cs;
+      HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+      hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed);
+      for (int n = 0; n < P.nt && e == hipSuccess; ++n) {
+        double b;
+        e = step(n, cs, &b);
+      }
+      hipError_t e2 = hipStreamEndCapture(cs, &sg.g);
+      (void)hipStreamDestroy(cs);
+      HIPCHK(e);
+      HIPCHK(e2);
+      HIPCHK(hipGraphInstantiate(&sg.x, sg.g, nullptr, nullptr, 0));
+    }
+    for (int n = 0; n < P.nt; ++n) {        // bytes of the sequence (host only)
+      double b = 0.0;
+      const bool first = n == 0;
+      int nact = 0;
+      for (int m = 0; m < nf; ++m)
+        if (first || P.kappa[(size_t)(n + 1) * nf + m] != 0.0) ++nact;
+      b = ((first ? 2 : 3) * sort + (forcing ? nf * sort : 0) + (first ? 1 : 2) * 8.0 * nact +
+           (pr.varc ? sort : 0)) * (double)pr.G.npts();
+      bytes_all += b;
+    }
     bool timed = false;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (st.on) {
       std::lock_guard<std::mutex> lk(st.mu);
-      if ((st.counter++ % st.every) == 0 && st.pending.size() < 2000000) {
-        if (hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess) {
-          timed = true;
-          HIPCHK(hipEventRecord(e0, pr.s));
-        }
+      if (st.pending.size() < 2000000 && hipEventCreate(&e0) == hipSuccess &&
+          hipEventCreate(&e1) == hipSuccess) {
+        timed = true;
+        HIPCHK(hipEventRecord(e0, pr.s));
       }
     }
-    HIPCHK(launch_step<T>(a, pr.grid->order, nf, *ls, pr.s));
+    HIPCHK(hipGraphLaunch(sg.x, pr.s));
     if (timed) {
       HIPCHK(hipEventRecord(e1, pr.s));
-      // algorithmic bytes: read W^n, W^{n-1}, write W^{n+1}; forcing reads;
-      // read+write of every active accumulator; c^2
-      double bpp = (first ? 2 : 3) * sort + (forcing ? nf * sort : 0) +
-                   (first ? 1 : 2) * 8.0 * nact + (pr.varc ? sort : 0);
       std::lock_guard<std::mutex> lk(st.mu);
       st.pending.emplace_back(e0, e1);
-      st.pending_bytes.push_back(bpp * (double)pr.G.npts());
+      st.pending_bytes.push_back(bytes_all);
+      st.pending_count.push_back(P.nt);
+    }
+  } else {
+    for (int n = 0; n < P.nt; ++n) {
+      bool timed = false;
+      hipEvent_t e0 = nullptr, e1 = nullptr;
+      if (st.on) {
+        std::lock_guard<std::mutex> lk(st.mu);
+        if ((st.counter++ % st.every) == 0 && st.pending.size() < 2000000) {
+          if (hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess) {
+            timed = true;
+            HIPCHK(hipEventRecord(e0, pr.s));
+          }
+        }
+      }
+      double b;
+      HIPCHK(step(n, pr.s, &b));
+      if (timed) {
+        HIPCHK(hipEventRecord(e1, pr.s));
+        std::lock_guard<std::mutex> lk(st.mu);
+        st.pending.emplace_back(e0, e1);
+        st.pending_bytes.push_back(b);
+        st.pending_count.push_back(1);
+      }
     }
   }
   HIPCHK(launch_finalize(pr.G, nf, pr.W.q, P.Binv, o.xin, o.xl, o.alpha, o.beta, o.out, o.ol,
@@ -611,6 +684,7 @@ int mfwh_solve_fixed_point(const mfwh_grid* g, const mfwh_time* t, const double*
   if (!v || !f) return fail(MFWH_EINVAL, "null array");
   mfwh_solve_opts o;
   fill_opts(opts, &o);
+  pr.graphs = g_graphs;
   CHK(prepare(pr, f));
   const ExtLayout al = abi_layout(g);
   HIPCHK(launch_zero_boundary(g->dim, g->n, t->nf, v, pr.s));
@@ -652,6 +726,7 @@ int mfwh_solve_gmres(const mfwh_grid* g, const mfwh_time* t, const double* f, do
   Problem pr;
   CHK(setup(pr, g, t, o.restart, ws, ws_bytes, stream));
   if (!v || !f) return fail(MFWH_EINVAL, "null array");
+  pr.graphs = g_graphs;
   CHK(prepare(pr, f));
   const ExtLayout al = abi_layout(g), il = int_layout(pr.G);
   const int nf = t->nf;
@@ -745,12 +820,13 @@ int mfwh_stats_read(long long* launches, double* total_ms, double* total_bytes) 
     HIPCHK(hipEventElapsedTime(&ms, pe.first, pe.second));
     st.ms += ms;
     st.bytes += st.pending_bytes[k];
-    st.launches += 1;
+    st.launches += st.pending_count[k];
     (void)hipEventDestroy(pe.first);
     (void)hipEventDestroy(pe.second);
   }
   st.pending.clear();
   st.pending_bytes.clear();
+  st.pending_count.clear();
   if (launches) *launches = st.launches;
   if (total_ms) *total_ms = st.ms;
   if (total_bytes) *total_bytes = st.bytes;
@@ -758,6 +834,16 @@ int mfwh_stats_read(long long* launches, double* total_ms, double* total_bytes) 
   st.ms = 0.0;
   st.bytes = 0.0;
   return MFWH_OK;
+}
+
+int mfwh_set_option(int key, long long value) {
+  switch (key) {
+    case MFWH_OPT_GRAPHS:
+      g_graphs = value != 0;
+      return MFWH_OK;
+    default:
+      return fail(MFWH_EINVAL, "unknown option");
+  }
 }
 
 int mfwh_set_launch_shape(int bx, int by, int chunk) {

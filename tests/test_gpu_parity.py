@@ -225,6 +225,26 @@ def test_gmres_matches_oracle_gmres_history():
     assert rel(v.cpu().numpy(), Vo) < 1e-9
 
 
+def test_graph_replay_matches_eager_launches():
+    """Solvers replay a recorded step sequence; with eager BLAS work and host
+    synchronisation between replays every result must equal the eager path."""
+    L = _L()
+    w = inputs.small(seed=3, shape=(19, 17), nf=3, order=2, varc=True)
+    res = {}
+    for graphs in (1, 0):
+        L.mfwh_set_option(L.MFWH_OPT_GRAPHS, graphs)
+        try:
+            gp = _gp(w, restart=12)
+            v, info = gp.gmres(tol=1e-12, max_iter=60)
+            vf, infof = gp.fixed_point(max_iter=5)
+            res[graphs] = (v.cpu().numpy(), info, vf.cpu().numpy())
+        finally:
+            L.mfwh_set_option(L.MFWH_OPT_GRAPHS, 1)
+    assert np.array_equal(res[0][0], res[1][0])
+    assert np.array_equal(res[0][1]["history"], res[1][1]["history"])
+    assert np.array_equal(res[0][2], res[1][2])
+
+
 def test_gmres_warm_start_at_solution():
     w = inputs.small(seed=11, shape=(21, 23), nf=2, order=4)
     gp = _gp(w)
@@ -298,7 +318,7 @@ def test_config2_full_size_helmholtz_fixed_point():
 
 def test_config2_full_size_gmres_matches_dst():
     w = inputs.config2(0)
-    gp = _gp(w, restart=30)
+    gp = _gp(w, restart=128)
     v, info = gp.gmres(tol=1e-10, max_iter=600)
     assert info["converged"], info
     prob, _ = workload.setup(dict(w, f=None), filt="traditional")
