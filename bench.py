@@ -23,6 +23,7 @@ Extra fields:
 
     python bench.py [--gpus 1] [--steps 3] [--warmup 1]
     python bench.py --mode copy      # plain copy kernel of known size (counter calibration)
+    python bench.py --mode batch     # 64 independent 2D problems solved as one batch
     python bench.py --mode apply --applies 3   # a few forcing-free float64
                                      # applications of the same workload (for
                                      # rocprofv3: the step kernel as the solver runs it)
@@ -99,12 +100,60 @@ def copy_calibration(nbytes=1 << 30, reps=5):
                       "reps": reps}))
 
 
+def batch_bench(args):
+    """64 independent 2D problems (grid 129..513, N_f 2..6, omega ~ U(10, 50),
+    order 4, least-squares filters) solved by one batched GMRES(64) call to
+    1e-8: aggregate throughput and per-problem latency."""
+    import torch
+    from paper_2507_23613_amd import _lib as L
+    from paper_2507_23613_amd import inputs
+    from paper_2507_23613_amd.problem import GpuBatch, GpuProblem
+    ws = inputs.config4(0)
+    log(f"batch of {len(ws)} problems")
+    gb = GpuBatch(ws, restart=64)
+    log(f"workspace {gb.ws.numel() / 2**30:.1f} GiB")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, infos, status = gb.gmres(max_iter=600, tol=1e-8)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ps = sum(i["point_steps"] * len(w["omega"]) for i, w in zip(infos, ws))
+    lat = np.array([i["latency_ms"] for i in infos])
+    out = {"mode": "batch", "problems": len(ws), "status": status,
+           "converged": int(sum(i["converged"] for i in infos)),
+           "wall_s": round(el, 3), "value": ps / el, "unit": "grid-point-steps/s x Nf",
+           "latency_ms_p50": float(np.percentile(lat, 50)),
+           "latency_ms_p99": float(np.percentile(lat, 99)),
+           "iterations_max": max(i["iterations"] for i in infos),
+           "iterations_median": float(np.median([i["iterations"] for i in infos]))}
+    log(json.dumps(out))
+    del gb
+    if args.sequential:
+        t0 = time.perf_counter()
+        ps1 = 0
+        for k, w in enumerate(ws):
+            gp = GpuProblem(w, restart=64)
+            _, info = gp.gmres(restart=64, max_iter=600, tol=1e-8)
+            ps1 += info["point_steps"] * len(w["omega"])
+            if k % 8 == 7:
+                log(f"sequential: {k + 1} problems done")
+            del gp
+        torch.cuda.synchronize()
+        el1 = time.perf_counter() - t0
+        out["sequential_wall_s"] = round(el1, 3)
+        out["sequential_value"] = ps1 / el1
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--mode", default="solve", choices=["solve", "copy", "apply"])
+    ap.add_argument("--mode", default="solve", choices=["solve", "copy", "apply", "batch"])
+    ap.add_argument("--no-tune", action="store_true", help="skip the launch-shape autotuner")
+    ap.add_argument("--sequential", action="store_true",
+                    help="batch mode: also solve the problems one at a time")
     ap.add_argument("--applies", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-fp32", action="store_true", help="skip the float32-stencil solve")
@@ -123,12 +172,21 @@ def main():
     from paper_2507_23613_amd import inputs
     from paper_2507_23613_amd.problem import GpuProblem
 
+    if args.mode == "batch":
+        batch_bench(args)
+        return
+
     w = inputs.config2(0, n=args.n)
     nf = len(w["omega"])
     log(f"workload {w['name']}: omega={np.round(w['omega'], 3).tolist()} N_p={w['np']}")
     RESTART = 128
     gp = GpuProblem(w, precision=L.MFWH_FP64, restart=RESTART)
     log(f"N_t={gp.nt} dt={gp.dt:.3e} interior={gp.interior_points}")
+    shape = None
+    if not args.no_tune and args.mode == "solve":
+        from paper_2507_23613_amd import autotune
+        shape, _ = autotune.tune(gp, reps=2, log=log)
+        log(f"autotuned launch shape {shape}")
 
     if args.mode == "apply":
         v = torch.randn((nf,) + tuple(w["shape"]), dtype=torch.float64, device="cuda")
@@ -203,6 +261,7 @@ def main():
         "config": {"workload": f"{w['name']}-order4-cfl0.5-gmres{RESTART}-tol1e-8",
                    "grid": list(w["shape"]), "nf": nf, "np": int(w["np"]), "nt": gp.nt,
                    "gmres_iterations": its, "wave_solves": applies,
+                   "launch_shape": list(shape) if shape else None,
                    "omega": np.round(w["omega"], 4).tolist()},
         "roofline": roof,
         "cpu_baseline": cpu,

@@ -199,6 +199,37 @@ int mfwh_solve_gmres(const mfwh_grid* g, const mfwh_time* t, const double* f, do
                      void* ws, size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------- *
+ * Batched problems
+ * ------------------------------------------------------------------------- */
+
+/* One independent problem of a batch: grid, time grid and filter as for the
+ * single-problem calls; f (device [nf][grid], read) and v (device [nf][grid]:
+ * initial guess in, solution out). */
+typedef struct mfwh_problem {
+  mfwh_grid grid;
+  mfwh_time time;
+  const double* f;
+  double* v;
+} mfwh_problem;
+
+/* Workspace bytes for mfwh_solve_gmres_batched (0 if the batch is invalid). */
+size_t mfwh_workspace_bytes_batched(int nprob, const mfwh_problem* probs, int restart);
+
+/* GMRES(m) (as mfwh_solve_gmres, float64 only) on nprob independent problems
+ * in lockstep.  Every MFWH application of the batch is ONE sequence of step
+ * launches in which each launch advances every active problem by one time
+ * step (problems with fewer steps drop out of later launches); the sequence is
+ * recorded once per solve into a HIP graph and replayed.  Problems of
+ * different grid size, N_f, frequencies and N_t may be mixed; they must share
+ * dim (2 or 3) and order.  A problem leaves the batch when its true residual
+ * meets tol.  infos: host [nprob] (may be NULL); latency_ms: host [nprob]
+ * (may be NULL): wall time from the call's start until that problem was
+ * found converged (or stopped). */
+int mfwh_solve_gmres_batched(int nprob, const mfwh_problem* probs, const mfwh_solve_opts* opts,
+                             mfwh_solve_info* infos, double* latency_ms, void* ws,
+                             size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------- *
  * Measurement hooks
  * ------------------------------------------------------------------------- */
 

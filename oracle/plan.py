@@ -41,10 +41,14 @@ def omega_tilde(omega, dt, alpha=0.0):
     """
     beta = 1.0 - 2.0 * alpha
     omega = np.asarray(omega, dtype=np.float64)
-    arg = (1.0 - 0.5 * beta * (omega * dt) ** 2) / (1.0 + alpha * (omega * dt) ** 2)
+    y2 = (omega * dt) ** 2
+    arg = (1.0 - 0.5 * beta * y2) / (1.0 + alpha * y2)
     if np.any(arg <= -1.0) or np.any(arg > 1.0):
         raise ValueError("omega*dt outside the range where omega~ is defined")
-    return np.arccos(arg) / dt
+    # acos(arg) written through 1 - cos x = 2 sin^2(x/2): with beta = 1 - 2 alpha,
+    # 1 - arg = y2 / (2 (1 + alpha y2)), so x = 2 asin(sqrt(y2 / (4 (1 + alpha y2)))).
+    # Same value, without the cancellation of acos near 1 (small omega dt).
+    return 2.0 * np.arcsin(np.sqrt(y2 / (4.0 * (1.0 + alpha * y2)))) / dt
 
 
 def lambda_tilde(lam, dt, alpha=0.0):
@@ -73,7 +77,8 @@ def _dt_for_exact_periods(omega1, np_, nt, alpha):
     """
     beta = 1.0 - 2.0 * alpha
     C = math.cos(TWO_PI * np_ / nt)
-    x2 = (1.0 - C) / (C * alpha + 0.5 * beta)
+    one_minus_C = 2.0 * math.sin(math.pi * np_ / nt) ** 2     # 1 - C without cancellation
+    x2 = one_minus_C / (C * alpha + 0.5 * beta)
     return math.sqrt(x2) / omega1
 
 
@@ -105,7 +110,7 @@ def periods(omega_t, Tf):
     """N_{p,m} = floor(T_f / T~_m) and T~_{f,m} = N_{p,m} T~_m (eq. TbarDef
     with the modified periods T~_m = 2 pi / omega~_m)."""
     omega_t = np.asarray(omega_t, dtype=np.float64)
-    npm = np.floor(Tf * omega_t / TWO_PI + 1e-12).astype(np.int64)
+    npm = np.floor(Tf * omega_t / TWO_PI + 1e-9).astype(np.int64)
     if np.any(npm < 1):
         raise ValueError("a modified period is longer than T_f")
     return npm, npm * TWO_PI / omega_t
@@ -329,7 +334,7 @@ def optimise_filter_discrete(omega, np_, nt, ndelta=20, cdelta=2.0, rcond=0.0):
     """
     om = np.asarray(omega, dtype=np.float64)
     Tm = TWO_PI / om
-    npm = np.floor(np_ * Tm[0] / Tm + 1e-12).astype(np.int64)
+    npm = np.floor(np_ * Tm[0] / Tm + 1e-9).astype(np.int64)
     tfm = npm * Tm
     Tf = float(np.max(tfm))
     dt = Tf / nt
@@ -363,7 +368,7 @@ def optimise_filter_continuous(omega, np_, ndelta=20, cdelta=2.0):
     """
     om = np.asarray(omega, dtype=np.float64)
     Tm = TWO_PI / om
-    npm = np.floor(np_ * Tm[0] / Tm + 1e-12).astype(np.int64)
+    npm = np.floor(np_ * Tm[0] / Tm + 1e-9).astype(np.int64)
     tfm = npm * Tm
 
     def I_tsin(k, T):

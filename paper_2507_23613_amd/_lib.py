@@ -55,6 +55,10 @@ class mfwh_solve_info(ctypes.Structure):
                 ("rel_residual", c_double), ("point_steps", c_longlong)]
 
 
+class mfwh_problem(ctypes.Structure):
+    _fields_ = [("grid", mfwh_grid), ("time", mfwh_time), ("f", c_void_p), ("v", c_void_p)]
+
+
 def _load():
     # PyTorch's HIP runtime must be the one in the process before the library
     # (which links against it) is loaded
@@ -87,6 +91,11 @@ def _load():
                                      c_void_p, c_void_p, ctypes.POINTER(mfwh_solve_opts),
                                      P_double, ctypes.POINTER(mfwh_solve_info), c_void_p,
                                      c_size_t, c_void_p]),
+        "mfwh_workspace_bytes_batched": (c_size_t, [c_int, ctypes.POINTER(mfwh_problem), c_int]),
+        "mfwh_solve_gmres_batched": (c_int, [c_int, ctypes.POINTER(mfwh_problem),
+                                             ctypes.POINTER(mfwh_solve_opts),
+                                             ctypes.POINTER(mfwh_solve_info), P_double, c_void_p,
+                                             c_size_t, c_void_p]),
         "mfwh_stats_enable": (c_int, [c_int, c_int]),
         "mfwh_stats_read": (c_int, [ctypes.POINTER(c_longlong), P_double, P_double]),
         "mfwh_set_launch_shape": (c_int, [c_int, c_int, c_int]),
@@ -260,6 +269,39 @@ def mfwh_solve_fixed_point(grid, time, f, v, opts, ws, stream=None):
 
 def mfwh_solve_gmres(grid, time, f, v, opts, ws, stream=None):
     return _solve(LIB.mfwh_solve_gmres, grid, time, f, v, opts, ws, stream, opts.max_iter)
+
+
+def make_problems(items):
+    """items: list of (grid, time, f tensor, v tensor) -> ctypes array of mfwh_problem."""
+    arr = (mfwh_problem * len(items))()
+    keep = []
+    for k, (g, t, f, v) in enumerate(items):
+        arr[k].grid = g
+        arr[k].time = t
+        arr[k].f = _tptr(f, "f")
+        arr[k].v = _tptr(v, "v")
+        keep.append((g, t, f, v))
+    arr._keep = keep
+    return arr
+
+
+def mfwh_workspace_bytes_batched(problems, restart=0):
+    return int(LIB.mfwh_workspace_bytes_batched(len(problems), problems, int(restart)))
+
+
+def mfwh_solve_gmres_batched(problems, opts, ws, stream=None):
+    n = len(problems)
+    infos = (mfwh_solve_info * n)()
+    lat = np.zeros(n)
+    rc = LIB.mfwh_solve_gmres_batched(n, problems, ctypes.byref(opts), infos,
+                                      lat.ctypes.data_as(P_double),
+                                      ctypes.c_void_p(ws.data_ptr()),
+                                      ws.numel() * ws.element_size(), _stream(stream))
+    _check(rc, allow_not_converged=True)
+    return [dict(converged=infos[k].rel_residual <= opts.tol, iterations=infos[k].iterations,
+                 applies=infos[k].applies, rel_residual=infos[k].rel_residual,
+                 point_steps=infos[k].point_steps, latency_ms=float(lat[k]))
+            for k in range(n)], STATUS[rc]
 
 
 def mfwh_stats_enable(on, sample_every=8):

@@ -7,6 +7,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
+#include <memory>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -552,6 +554,185 @@ int gmres_core(Vecs& V, bool use32, const double* rhs, double* x, bool xzero, do
   return MFWH_OK;
 }
 
+// ---------------------------------------------------------------------------
+// batched problems: one step launch advances every active problem
+// ---------------------------------------------------------------------------
+struct Batch {
+  int np = 0;
+  std::vector<Problem*> pr;
+  BatchProb<double>* dprobs = nullptr;   // device
+  int* dactive = nullptr;                // device
+  double* dtab = nullptr;                // device coefficient tables
+  std::vector<int> hactive;
+  int ntiles = 0, maxnt = 0, dim = 0, order = 0;
+  LaunchShape ls;
+  StepGraph sg[2];
+  hipStream_t s = nullptr;
+  ~Batch() {
+    for (auto& b : sg) {
+      if (b.x) (void)hipGraphExecDestroy(b.x);
+      if (b.g) (void)hipGraphDestroy(b.g);
+    }
+    for (auto* p : pr) delete p;
+  }
+};
+
+size_t batch_shared_bytes(int np, const size_t* ntab) {
+  size_t b = 0;
+  auto take = [&](size_t x) { b = (b + 255) / 256 * 256 + x; };
+  take((size_t)np * sizeof(BatchProb<double>));
+  take((size_t)np * sizeof(int));
+  take(*ntab * sizeof(double));
+  return (b + 255) / 256 * 256;
+}
+
+// Per-problem workspace sizes and table size; validates the batch.
+int batch_sizes(int np, const mfwh_problem* P, int restart, std::vector<size_t>* sizes,
+                size_t* ntab) {
+  if (np < 1 || !P) return fail(MFWH_EINVAL, "empty batch");
+  *ntab = 0;
+  sizes->clear();
+  for (int i = 0; i < np; ++i) {
+    Geom G;
+    CHK(make_geom(&P[i].grid, &G));
+    if (P[i].grid.dim != P[0].grid.dim || P[i].grid.order != P[0].grid.order)
+      return fail(MFWH_EINVAL, "a batch must share dim and order");
+    if (P[i].grid.precision != MFWH_FP64)
+      return fail(MFWH_EINVAL, "batched solves run in float64");
+    if (P[i].grid.dim == 1) return fail(MFWH_EINVAL, "batched solves need dim 2 or 3");
+    if (!P[i].time.omega || P[i].time.nf < 1 || P[i].time.nf > MFWH_MAX_NF)
+      return fail(MFWH_EINVAL, "bad frequency list");
+    const long long nt = std::llround(P[i].time.T / P[i].time.dt);
+    *ntab += (size_t)2 * (nt + 1) * P[i].time.nf;
+    sizes->push_back(carve(G, P[i].time.nf, false, P[i].grid.c != nullptr, restart, nullptr).bytes);
+  }
+  return MFWH_OK;
+}
+
+int batch_setup(Batch& B, int np, const mfwh_problem* P, int restart, void* ws, size_t ws_bytes,
+                void* stream) {
+  std::vector<size_t> sizes;
+  size_t ntab;
+  CHK(batch_sizes(np, P, restart, &sizes, &ntab));
+  if (!ws) return fail(MFWH_EWORKSPACE, "null workspace");
+  if (((uintptr_t)ws) % 256) return fail(MFWH_EWORKSPACE, "workspace must be 256-byte aligned");
+  size_t total = 0;
+  for (size_t b : sizes) total += b;
+  const size_t shared = batch_shared_bytes(np, &ntab);
+  if (total + shared > ws_bytes)
+    return fail(MFWH_EWORKSPACE, "workspace too small: need " + std::to_string(total + shared));
+  B.np = np;
+  B.s = (hipStream_t)stream;
+  B.dim = P[0].grid.dim;
+  B.order = P[0].grid.order;
+  char* base = (char*)ws;
+  size_t off = 0;
+  for (int i = 0; i < np; ++i) {
+    Problem* pr = new Problem();
+    B.pr.push_back(pr);
+    CHK(setup(*pr, &P[i].grid, &P[i].time, restart, base + off, sizes[i], stream));
+    if (!P[i].f || !P[i].v) return fail(MFWH_EINVAL, "null array in batch");
+    CHK(prepare(*pr, P[i].f));
+    off += sizes[i];
+  }
+  char* sh = base + off;
+  size_t so = 0;
+  auto take = [&](size_t x) -> char* {
+    so = (so + 255) / 256 * 256;
+    char* p = sh + so;
+    so += x;
+    return p;
+  };
+  B.dprobs = (BatchProb<double>*)take((size_t)np * sizeof(BatchProb<double>));
+  B.dactive = (int*)take((size_t)np * sizeof(int));
+  B.dtab = (double*)take(ntab * sizeof(double));
+  // launch shape shared by the batch: the override if set, else 64 lanes x 8 rows
+  if (g_shape_set) B.ls = g_shape_override;
+  else {
+    B.ls.bx = 64;
+    B.ls.by = B.dim == 3 ? 4 : 1;
+    B.ls.chunk = 8;
+  }
+  std::vector<BatchProb<double>> hp(np);
+  std::vector<double> tab(ntab);
+  size_t to = 0;
+  int tiles = 0;
+  for (int i = 0; i < np; ++i) {
+    Problem& pr = *B.pr[i];
+    const Plan& pl = pr.P;
+    BatchProb<double>& bp = hp[i];
+    std::memset(&bp, 0, sizeof(bp));
+    bp.a.g = pr.G;
+    bp.a.c2 = pr.varc ? pr.W.c64 : nullptr;
+    bp.a.f = pr.W.f64;
+    bp.a.q = pr.W.q;
+    stencil_weights<double>(pr.grid, bp.a.wx, bp.a.wy, bp.a.wz);
+    set_tiling(bp.a, B.ls);
+    bp.wa = pr.W.w64a;
+    bp.wb = pr.W.w64b;
+    const size_t n1 = (size_t)(pl.nt + 1) * pl.nf;
+    std::memcpy(&tab[to], pl.kappa.data(), n1 * sizeof(double));
+    std::memcpy(&tab[to + n1], pl.phi.data(), n1 * sizeof(double));
+    bp.kappa = B.dtab + to;
+    bp.phi = B.dtab + to + n1;
+    to += 2 * n1;
+    bp.dt2 = pl.dt * pl.dt;
+    bp.nt = pl.nt;
+    bp.nf = pl.nf;
+    bp.tile0 = tiles;
+    tiles += bp.a.nblocks;
+    B.maxnt = std::max(B.maxnt, pl.nt);
+  }
+  B.ntiles = tiles;
+  HIPCHK(hipMemcpyAsync(B.dprobs, hp.data(), np * sizeof(BatchProb<double>),
+                        hipMemcpyHostToDevice, B.s));
+  HIPCHK(hipMemcpyAsync(B.dtab, tab.data(), ntab * sizeof(double), hipMemcpyHostToDevice, B.s));
+  HIPCHK(hipStreamSynchronize(B.s));
+  B.hactive.assign(np, 0);
+  return MFWH_OK;
+}
+
+// One application for every problem i in `act`: v[i] (internal layout, or
+// null for V = 0) -> o[i].  The step sequence is one recorded graph per
+// forcing flag; problems outside `act` are skipped by the kernel.
+int batch_apply(Batch& B, const std::vector<int>& act, const std::vector<const double*>& v,
+                const std::vector<Out>& o, bool forcing) {
+  for (int i : act) {
+    Problem& pr = *B.pr[i];
+    if (v[i]) HIPCHK(launch_init_w0<double>(pr.G, pr.P.nf, v[i], int_layout(pr.G), pr.W.w64a, B.s));
+    else HIPCHK(launch_fill_t<double>(pr.W.w64a, pr.G.fs, 0.0, B.s));
+  }
+  std::fill(B.hactive.begin(), B.hactive.end(), 0);
+  for (int i : act) B.hactive[i] = 1;
+  HIPCHK(hipMemcpyAsync(B.dactive, B.hactive.data(), B.np * sizeof(int), hipMemcpyHostToDevice,
+                        B.s));
+  StepGraph& sg = B.sg[forcing ? 1 : 0];
+  if (!sg.x) {
+    hipStream_t cs;
+    HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed);
+    for (int n = 0; n < B.maxnt && e == hipSuccess; ++n) {
+      BatchArgs<double> ba{B.dprobs, B.dactive, B.np, B.ntiles, n, forcing ? 1 : 0};
+      e = launch_step_batched<double>(ba, B.dim, B.order, B.ls, cs);
+    }
+    hipError_t e2 = hipStreamEndCapture(cs, &sg.g);
+    (void)hipStreamDestroy(cs);
+    HIPCHK(e);
+    HIPCHK(e2);
+    HIPCHK(hipGraphInstantiate(&sg.x, sg.g, nullptr, nullptr, 0));
+  }
+  HIPCHK(hipGraphLaunch(sg.x, B.s));
+  for (int i : act) {
+    Problem& pr = *B.pr[i];
+    HIPCHK(launch_finalize(pr.G, pr.P.nf, pr.W.q, pr.P.Binv, o[i].xin, o[i].xl, o[i].alpha,
+                           o[i].beta, o[i].out, o[i].ol, o[i].partial, kRedBlocks, B.s));
+    pr.point_steps += pr.G.npts() * (long long)pr.P.nt;
+    pr.applies += 1;
+  }
+  HIPCHK(hipStreamSynchronize(B.s));     // the host flag buffer is reused
+  return MFWH_OK;
+}
+
 void fill_opts(const mfwh_solve_opts* in, mfwh_solve_opts* o) {
   o->restart = 30;
   o->max_iter = 1000;
@@ -798,6 +979,223 @@ int mfwh_solve_gmres(const mfwh_grid* g, const mfwh_time* t, const double* f, do
     info->rel_residual = relres;
     info->point_steps = pr.point_steps;
   }
+  return status;
+}
+
+size_t mfwh_workspace_bytes_batched(int nprob, const mfwh_problem* probs, int restart) {
+  std::vector<size_t> sizes;
+  size_t ntab;
+  restart = std::max(0, std::min(restart, MFWH_MAX_RESTART));
+  if (batch_sizes(nprob, probs, restart, &sizes, &ntab) != MFWH_OK) return 0;
+  size_t total = 0;
+  for (size_t b : sizes) total += b;
+  return total + batch_shared_bytes(nprob, &ntab);
+}
+
+int mfwh_solve_gmres_batched(int nprob, const mfwh_problem* probs, const mfwh_solve_opts* opts,
+                             mfwh_solve_info* infos, double* latency_ms, void* ws, size_t ws_bytes,
+                             void* stream) {
+  mfwh_solve_opts o;
+  fill_opts(opts, &o);
+  if (o.restart > MFWH_MAX_RESTART) return fail(MFWH_EINVAL, "restart too large");
+  const auto t0 = std::chrono::steady_clock::now();
+  auto ms_since = [&]() {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  };
+  Batch B;
+  CHK(batch_setup(B, nprob, probs, o.restart, ws, ws_bytes, stream));
+  const int np = nprob, m = o.restart;
+  struct St {
+    Vecs V;
+    std::vector<double> H, cs, sn, g, y, hh;
+    double bnorm = 0, res = 0;
+    int its = 0, k = 0;
+    bool xzero = true, done = false, conv = false, live = false;
+    double lat = 0;
+  };
+  std::vector<St> S(np);
+  std::vector<int> all(np);
+  for (int i = 0; i < np; ++i) {
+    all[i] = i;
+    Problem& pr = *B.pr[i];
+    S[i].V = Vecs{&pr, (long long)pr.P.nf * pr.G.fs, 0};
+    S[i].V.nb = blas_blocks(S[i].V.N);
+    S[i].H.assign((size_t)(m + 1) * m, 0.0);
+    S[i].cs.assign(m, 0.0);
+    S[i].sn.assign(m, 0.0);
+    S[i].g.assign(m + 1, 0.0);
+    S[i].y.assign(m, 0.0);
+    S[i].hh.assign(2 * (m + 1) + 1, 0.0);
+    HIPCHK(launch_fill(pr.W.vec, (long long)pr.W.nvec * S[i].V.N, 0.0, B.s));
+  }
+  auto X = [&](int i) { return S[i].V.vec(m + 2); };
+  auto Bv = [&](int i) { return S[i].V.vec(m + 3); };
+  // b = W_h(0) for every problem
+  {
+    std::vector<const double*> v(np, nullptr);
+    std::vector<Out> out(np);
+    for (int i = 0; i < np; ++i) out[i] = Out{Bv(i), int_layout(B.pr[i]->G)};
+    CHK(batch_apply(B, all, v, out, true));
+  }
+  for (int i = 0; i < np; ++i) {
+    Problem& pr = *B.pr[i];
+    CHK(norm2(S[i].V, Bv(i), &S[i].bnorm));
+    if (!(S[i].bnorm > 0)) return fail(MFWH_EINVAL, "zero right-hand side in batch");
+    HIPCHK(launch_copy_fields<double, double>(pr.G, pr.P.nf, probs[i].v, abi_layout(&probs[i].grid),
+                                              X(i), int_layout(pr.G), 0, B.s));
+    double xn;
+    CHK(norm2(S[i].V, X(i), &xn));
+    S[i].xzero = xn == 0.0;
+  }
+  while (true) {
+    std::vector<int> cyc;
+    for (int i = 0; i < np; ++i)
+      if (!S[i].done) cyc.push_back(i);
+    if (cyc.empty()) break;
+    // true residuals r = b - A x at the start of the cycle
+    std::vector<int> nz;
+    std::vector<const double*> v(np, nullptr);
+    std::vector<Out> out(np);
+    for (int i : cyc) {
+      const ExtLayout il = int_layout(B.pr[i]->G);
+      out[i] = Out{S[i].V.vec(0), il, X(i), il, 1.0, -1.0, nullptr};
+      if (!S[i].xzero) { nz.push_back(i); v[i] = X(i); }
+    }
+    if (!nz.empty()) CHK(batch_apply(B, nz, v, out, false));
+    std::vector<int> live;
+    for (int i : cyc) {
+      St& st = S[i];
+      double* v0 = st.V.vec(0);
+      if (st.xzero)
+        HIPCHK(hipMemcpyAsync(v0, Bv(i), st.V.N * sizeof(double), hipMemcpyDeviceToDevice, B.s));
+      else
+        HIPCHK(launch_axpby(1.0, Bv(i), -1.0, v0, st.V.N, B.s));
+      double beta;
+      CHK(norm2(st.V, v0, &beta));
+      if (!std::isfinite(beta)) return fail(MFWH_ENONFINITE, "non-finite residual in batch");
+      st.res = beta;
+      if (beta <= o.tol * st.bnorm || st.its >= o.max_iter) {
+        st.done = true;
+        st.conv = beta <= o.tol * st.bnorm;
+        st.lat = ms_since();
+        continue;
+      }
+      double b2 = beta * beta;
+      double* dnr = B.pr[i]->W.scal + 2 * (m + 2);
+      HIPCHK(hipMemcpyAsync(dnr, &b2, sizeof(double), hipMemcpyHostToDevice, B.s));
+      HIPCHK(launch_scale_by_rnorm(v0, dnr, v0, st.V.N, B.s));
+      HIPCHK(hipStreamSynchronize(B.s));
+      std::fill(st.H.begin(), st.H.end(), 0.0);
+      std::fill(st.g.begin(), st.g.end(), 0.0);
+      st.g[0] = beta;
+      st.k = 0;
+      live.push_back(i);
+    }
+    std::vector<int> act = live;
+    for (int j = 0; j < m && !act.empty(); ++j) {
+      std::vector<int> a2;
+      for (int i : act)
+        if (S[i].its < o.max_iter) a2.push_back(i);
+      act = a2;
+      if (act.empty()) break;
+      std::vector<const double*> vj(np, nullptr);
+      std::vector<Out> ow(np);
+      for (int i : act) {
+        const ExtLayout il = int_layout(B.pr[i]->G);
+        vj[i] = S[i].V.vec(j);
+        ow[i] = Out{S[i].V.vec(m + 1), il, S[i].V.vec(j), il, 1.0, -1.0, nullptr};
+      }
+      CHK(batch_apply(B, act, vj, ow, false));
+      for (int i : act) {
+        St& st = S[i];
+        Problem& pr = *B.pr[i];
+        const int rs = m + 2;
+        double *dh1 = pr.W.scal, *dh2 = pr.W.scal + rs, *dnr = pr.W.scal + 2 * rs;
+        double* work = st.V.vec(m + 1);
+        Vecs& V = st.V;
+        HIPCHK(launch_multidot(V.vec(0), V.N, j + 1, work, V.N, pr.W.partial, V.nb, B.s));
+        HIPCHK(launch_reduce(pr.W.partial, V.nb, j + 1, dh1, B.s));
+        HIPCHK(launch_multiaxpy(V.vec(0), V.N, j + 1, dh1, -1.0, work, V.N, nullptr, V.nb, B.s));
+        HIPCHK(launch_multidot(V.vec(0), V.N, j + 1, work, V.N, pr.W.partial, V.nb, B.s));
+        HIPCHK(launch_reduce(pr.W.partial, V.nb, j + 1, dh2, B.s));
+        HIPCHK(launch_multiaxpy(V.vec(0), V.N, j + 1, dh2, -1.0, work, V.N, pr.W.partial, V.nb,
+                                B.s));
+        HIPCHK(launch_reduce(pr.W.partial, V.nb, 1, dnr, B.s));
+        HIPCHK(hipMemcpyAsync(st.hh.data(), dh1, (j + 1) * sizeof(double),
+                              hipMemcpyDeviceToHost, B.s));
+        HIPCHK(hipMemcpyAsync(st.hh.data() + (m + 1), dh2, (j + 1) * sizeof(double),
+                              hipMemcpyDeviceToHost, B.s));
+        HIPCHK(hipMemcpyAsync(st.hh.data() + 2 * (m + 1), dnr, sizeof(double),
+                              hipMemcpyDeviceToHost, B.s));
+      }
+      HIPCHK(hipStreamSynchronize(B.s));
+      std::vector<int> keep;
+      for (int i : act) {
+        St& st = S[i];
+        Problem& pr = *B.pr[i];
+        const double hnext = std::sqrt(st.hh[2 * (m + 1)]);
+        if (!std::isfinite(hnext)) return fail(MFWH_ENONFINITE, "non-finite Arnoldi vector");
+        for (int r = 0; r <= j; ++r) st.H[(size_t)r * m + j] = st.hh[r] + st.hh[(m + 1) + r];
+        st.H[(size_t)(j + 1) * m + j] = hnext;
+        if (hnext > 0.0)
+          HIPCHK(launch_scale_by_rnorm(st.V.vec(m + 1), pr.W.scal + 2 * (m + 2), st.V.vec(j + 1),
+                                       st.V.N, B.s));
+        for (int r = 0; r < j; ++r) {
+          const double a0 = st.H[(size_t)r * m + j], a1 = st.H[(size_t)(r + 1) * m + j];
+          st.H[(size_t)r * m + j] = st.cs[r] * a0 + st.sn[r] * a1;
+          st.H[(size_t)(r + 1) * m + j] = -st.sn[r] * a0 + st.cs[r] * a1;
+        }
+        const double a0 = st.H[(size_t)j * m + j], a1 = st.H[(size_t)(j + 1) * m + j];
+        const double den = std::hypot(a0, a1);
+        st.cs[j] = den > 0 ? a0 / den : 1.0;
+        st.sn[j] = den > 0 ? a1 / den : 0.0;
+        st.H[(size_t)j * m + j] = den;
+        st.H[(size_t)(j + 1) * m + j] = 0.0;
+        st.g[j + 1] = -st.sn[j] * st.g[j];
+        st.g[j] = st.cs[j] * st.g[j];
+        ++st.its;
+        st.k = j + 1;
+        const double est = std::fabs(st.g[j + 1]);
+        if (!(est <= o.tol * st.bnorm || hnext == 0.0)) keep.push_back(i);
+      }
+      act = keep;
+    }
+    for (int i : live) {
+      St& st = S[i];
+      Problem& pr = *B.pr[i];
+      const int k = st.k;
+      for (int r = k - 1; r >= 0; --r) {
+        double sum = st.g[r];
+        for (int c = r + 1; c < k; ++c) sum -= st.H[(size_t)r * m + c] * st.y[c];
+        st.y[r] = st.H[(size_t)r * m + r] != 0.0 ? sum / st.H[(size_t)r * m + r] : 0.0;
+      }
+      if (k > 0) {
+        double* dy = pr.W.scal + 3 * (m + 2);
+        HIPCHK(hipMemcpyAsync(dy, st.y.data(), k * sizeof(double), hipMemcpyHostToDevice, B.s));
+        HIPCHK(launch_multiaxpy(st.V.vec(0), st.V.N, k, dy, 1.0, X(i), st.V.N, nullptr, st.V.nb,
+                                B.s));
+        HIPCHK(hipStreamSynchronize(B.s));
+        st.xzero = false;
+      }
+    }
+  }
+  int status = MFWH_OK;
+  for (int i = 0; i < np; ++i) {
+    Problem& pr = *B.pr[i];
+    HIPCHK(launch_copy_fields<double, double>(pr.G, pr.P.nf, X(i), int_layout(pr.G), probs[i].v,
+                                              abi_layout(&probs[i].grid), 0, B.s));
+    HIPCHK(launch_zero_boundary(probs[i].grid.dim, probs[i].grid.n, pr.P.nf, probs[i].v, B.s));
+    if (!S[i].conv) status = MFWH_NOT_CONVERGED;
+    if (infos) {
+      infos[i].iterations = S[i].its;
+      infos[i].applies = pr.applies;
+      infos[i].outer = 0;
+      infos[i].rel_residual = S[i].res / S[i].bnorm;
+      infos[i].point_steps = pr.point_steps;
+    }
+    if (latency_ms) latency_ms[i] = S[i].lat;
+  }
+  HIPCHK(hipStreamSynchronize(B.s));
   return status;
 }
 

@@ -50,6 +50,32 @@ struct StepArgs {
   int nblocks;          // logical blocks (grid is padded to a multiple of 8)
 };
 
+// One problem of a batch (device memory, built once per batched solve).  `a`
+// carries geometry, buffers, stencil weights and tiling; the step-dependent
+// fields (W pointers, coefficients) are filled in by the kernel from the
+// per-problem coefficient tables and the global step index.
+template <typename T>
+struct BatchProb {
+  StepArgs<T> a;
+  T* wa;                  // W^0, W^2, ...
+  T* wb;                  // W^1, W^3, ...
+  const double* kappa;    // device (nt+1) x nf: kappa[n][m]
+  const double* phi;      // device (nt+1) x nf: cos(omega~_m t^n)
+  double dt2;
+  int nt, nf;
+  int tile0;              // first logical tile of this problem in the batch
+};
+
+template <typename T>
+struct BatchArgs {
+  const BatchProb<T>* probs;   // device [nprob], ordered by tile0
+  const int* active;           // device [nprob]: 1 = advance this problem
+  int nprob;
+  int ntiles;                  // total logical tiles
+  int step;                    // global step n (produces W^{n+1})
+  int force;
+};
+
 struct LaunchShape {
   int bx = 64;      // threads along x per block
   int by = 1;       // threads along y per block (3D)
@@ -61,6 +87,13 @@ template <typename T>
 hipError_t launch_step(const StepArgs<T>& a, int order, int nf, const LaunchShape& ls,
                        hipStream_t s);
 LaunchShape default_shape(const Geom& g, int order, int bytes_w);
+// Tiling of one geometry for a launch shape: fills ntx, nty, nchunk, chunk,
+// nblocks of `a` (a.g must be set).
+template <typename T>
+void set_tiling(StepArgs<T>& a, const LaunchShape& ls);
+template <typename T>
+hipError_t launch_step_batched(const BatchArgs<T>& b, int dim, int order, const LaunchShape& ls,
+                               hipStream_t s);
 
 template <typename T>
 hipError_t launch_init_w0(const Geom& g, int nf, const double* v, ExtLayout vl, T* w0,

@@ -101,10 +101,7 @@ __global__ void __launch_bounds__(256) k_step1d(StepArgs<T> a) {
 // 2D: y-march, register window in y, LDS row exchange in x
 // -------------------------------------------------------------------------
 template <typename T, int R, int BX>
-__global__ void __launch_bounds__(BX) k_step2d(StepArgs<T> a) {
-  __shared__ T row[2][BX + 2 * R];
-  const int lb = xcd_remap(blockIdx.x, gridDim.x);
-  if (lb >= a.nblocks) return;
+__device__ __forceinline__ void body2d(const StepArgs<T>& a, int lb, T (*row)[BX + 2 * R]) {
   const int bx = lb / a.nchunk;
   const int by = lb - bx * a.nchunk;
   const int tid = threadIdx.x;
@@ -146,15 +143,20 @@ __global__ void __launch_bounds__(BX) k_step2d(StepArgs<T> a) {
   }
 }
 
+template <typename T, int R, int BX>
+__global__ void __launch_bounds__(BX) k_step2d(StepArgs<T> a) {
+  __shared__ T row[2][BX + 2 * R];
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  if (lb >= a.nblocks) return;
+  body2d<T, R, BX>(a, lb, row);
+}
+
 // -------------------------------------------------------------------------
 // 3D: z-march (2.5D), register window in z, LDS plane tile for x/y
 // -------------------------------------------------------------------------
 template <typename T, int R, int BX, int BY>
-__global__ void __launch_bounds__(BX * BY) k_step3d(StepArgs<T> a) {
-  constexpr int TW = BX + 2 * R, TH = BY + 2 * R;
-  __shared__ T tile[2][TH][TW];
-  const int lb = xcd_remap(blockIdx.x, gridDim.x);
-  if (lb >= a.nblocks) return;
+__device__ __forceinline__ void body3d(const StepArgs<T>& a, int lb,
+                                       T (*tile)[BY + 2 * R][BX + 2 * R]) {
   const int cz = lb % a.nchunk;
   const int t2 = lb / a.nchunk;
   const int tx = t2 % a.ntx;
@@ -222,6 +224,67 @@ __global__ void __launch_bounds__(BX * BY) k_step3d(StepArgs<T> a) {
   }
 }
 
+template <typename T, int R, int BX, int BY>
+__global__ void __launch_bounds__(BX * BY) k_step3d(StepArgs<T> a) {
+  __shared__ T tile[2][BY + 2 * R][BX + 2 * R];
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  if (lb >= a.nblocks) return;
+  body3d<T, R, BX, BY>(a, lb, tile);
+}
+
+// -------------------------------------------------------------------------
+// batched step: one launch advances every active problem of a batch by one
+// global time step; logical tiles of all problems are concatenated
+// -------------------------------------------------------------------------
+template <typename T, int R, int BX, int BY, int DIM>
+__global__ void __launch_bounds__(BX * BY) k_step_batched(BatchArgs<T> b) {
+  constexpr int TH = DIM == 2 ? 2 : BY + 2 * R;
+  __shared__ T smem[2 * TH * (BX + 2 * R)];
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  if (lb >= b.ntiles) return;
+  int lo = 0, hi = b.nprob - 1;                 // last problem with tile0 <= lb
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (b.probs[mid].tile0 <= lb) lo = mid;
+    else hi = mid - 1;
+  }
+  const BatchProb<T>& P = b.probs[lo];
+  const int n = b.step;
+  if (!b.active[lo] || n >= P.nt) return;
+  StepArgs<T> a = P.a;
+  const int nf = P.nf;
+  const bool first = n == 0;
+  const bool even = (n & 1) == 0;
+  a.wc = even ? P.wa : P.wb;
+  a.wp = even ? P.wb : P.wa;
+  a.wout = even ? P.wb : P.wa;
+  a.first = first ? 1 : 0;
+  a.cA = first ? T(1) : T(2);
+  a.cB = first ? T(0) : T(-1);
+  a.cC = (T)(first ? 0.5 * P.dt2 : P.dt2);
+  a.force = b.force;
+  int mask = 0;
+#pragma unroll
+  for (int m = 0; m < MFWH_MAX_NF; ++m) {
+    if (m < nf) {
+      a.phi[m] = b.force ? (T)P.phi[n * nf + m] : T(0);
+      a.kap[m] = P.kappa[(n + 1) * nf + m];
+      a.kap0[m] = first ? P.kappa[m] : 0.0;
+      if (first || a.kap[m] != 0.0) mask |= 1 << m;
+    } else {
+      a.phi[m] = T(0);
+      a.kap[m] = a.kap0[m] = 0.0;
+    }
+  }
+  a.mask = mask;
+  if constexpr (DIM == 2) {
+    body2d<T, R, BX>(a, lb - P.tile0, reinterpret_cast<T(*)[BX + 2 * R]>(smem));
+  } else {
+    body3d<T, R, BX, BY>(a, lb - P.tile0,
+                         reinterpret_cast<T(*)[BY + 2 * R][BX + 2 * R]>(smem));
+  }
+}
+
 template <typename T, int R>
 hipError_t launch_step_r(StepArgs<T> a, const LaunchShape& ls, hipStream_t s) {
   const Geom& g = a.g;
@@ -271,6 +334,59 @@ template hipError_t launch_step<double>(const StepArgs<double>&, int, int, const
                                         hipStream_t);
 template hipError_t launch_step<float>(const StepArgs<float>&, int, int, const LaunchShape&,
                                        hipStream_t);
+
+template <typename T>
+void set_tiling(StepArgs<T>& a, const LaunchShape& ls) {
+  const Geom& g = a.g;
+  a.chunk = std::max(1, ls.chunk);
+  a.nty = 1;
+  if (g.dim == 1) {
+    a.ntx = (g.nxi + 255) / 256;
+    a.nchunk = 1;
+    a.nblocks = a.ntx;
+  } else if (g.dim == 2) {
+    a.ntx = (g.nxi + ls.bx - 1) / ls.bx;
+    a.nchunk = (g.nyi + a.chunk - 1) / a.chunk;
+    a.nblocks = a.ntx * a.nchunk;
+  } else {
+    a.ntx = (g.nxi + ls.bx - 1) / ls.bx;
+    a.nty = (g.nyi + ls.by - 1) / ls.by;
+    a.nchunk = (g.nzi + a.chunk - 1) / a.chunk;
+    a.nblocks = a.ntx * a.nty * a.nchunk;
+  }
+}
+template void set_tiling<double>(StepArgs<double>&, const LaunchShape&);
+template void set_tiling<float>(StepArgs<float>&, const LaunchShape&);
+
+template <typename T, int R>
+static hipError_t launch_batched_r(const BatchArgs<T>& b, int dim, const LaunchShape& ls,
+                                   hipStream_t s) {
+  const int grid = pad8(b.ntiles);
+  if (dim == 2) {
+    switch (ls.bx) {
+      case 64: k_step_batched<T, R, 64, 1, 2><<<grid, 64, 0, s>>>(b); break;
+      case 128: k_step_batched<T, R, 128, 1, 2><<<grid, 128, 0, s>>>(b); break;
+      case 256: k_step_batched<T, R, 256, 1, 2><<<grid, 256, 0, s>>>(b); break;
+      default: return hipErrorInvalidValue;
+    }
+  } else if (dim == 3 && ls.bx == 64 && ls.by == 4) {
+    k_step_batched<T, R, 64, 4, 3><<<grid, dim3(64, 4), 0, s>>>(b);
+  } else {
+    return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_step_batched(const BatchArgs<T>& b, int dim, int order, const LaunchShape& ls,
+                               hipStream_t s) {
+  if (b.ntiles <= 0) return hipSuccess;
+  return order == 2 ? launch_batched_r<T, 1>(b, dim, ls, s) : launch_batched_r<T, 2>(b, dim, ls, s);
+}
+template hipError_t launch_step_batched<double>(const BatchArgs<double>&, int, int,
+                                                const LaunchShape&, hipStream_t);
+template hipError_t launch_step_batched<float>(const BatchArgs<float>&, int, int,
+                                               const LaunchShape&, hipStream_t);
 
 LaunchShape default_shape(const Geom& g, int order, int bytes_w) {
   (void)order;

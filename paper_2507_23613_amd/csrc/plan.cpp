@@ -119,7 +119,9 @@ double omega_tilde(double omega, double dt, double alpha) {
   const double x2 = omega * dt * omega * dt;
   const double c = (1.0 - 0.5 * beta * x2) / (1.0 + alpha * x2);
   if (!(c > -1.0 && c <= 1.0)) return NAN;
-  return std::acos(c) / dt;
+  // acos(c) through 1 - cos x = 2 sin^2(x/2): 1 - c = x2 / (2 (1 + alpha x2)) for
+  // beta = 1 - 2 alpha; asin keeps full precision where acos(c ~ 1) cancels
+  return 2.0 * std::asin(std::sqrt(x2 / (4.0 * (1.0 + alpha * x2)))) / dt;
 }
 
 double dt_max_explicit(int dim, const double* h, int order, double cmax) {
@@ -136,7 +138,8 @@ double dt_exact_periods(double omega1, int np, int nt, double alpha) {
   // inverting eq. omegaImplicit: (omega_1 dt)^2 = (1 - C) / (alpha C + beta/2).
   const double beta = 1.0 - 2.0 * alpha;
   const double C = std::cos(kTwoPi * np / nt);
-  return std::sqrt((1.0 - C) / (alpha * C + 0.5 * beta)) / omega1;
+  const double s = std::sin(M_PI * np / nt);
+  return std::sqrt(2.0 * s * s / (alpha * C + 0.5 * beta)) / omega1;   // 1 - C = 2 sin^2
 }
 
 void trapezoid_weights(int nt, double dt, double T, double* sigma, int stride) {
@@ -190,7 +193,7 @@ int build_plan(const mfwh_time* t, Plan* p, std::string* err) {
     p->omega_t[m] = omega_tilde(t->omega[m], t->dt, 0.0);
     // eq. TbarDef with the modified periods
     const double Tm = kTwoPi / p->omega_t[m];
-    p->npm[m] = (int)std::floor(p->T / Tm + 1e-12);
+    p->npm[m] = (int)std::floor(p->T / Tm + 1e-9);
     if (p->npm[m] < 1) { *err = "a modified period exceeds T"; return MFWH_EINVAL; }
     p->tfm[m] = p->npm[m] * Tm;
     if (t->filt) {
@@ -269,7 +272,7 @@ int optimize_filter(int nf, const double* om, int np, int nt, int ndelta, double
   double Tf = 0.0;
   for (int m = 0; m < nf; ++m) {
     const double Tm = kTwoPi / om[m];
-    npm[m] = (int)std::floor(np * (kTwoPi / om[0]) / Tm + 1e-12);
+    npm[m] = (int)std::floor(np * (kTwoPi / om[0]) / Tm + 1e-9);
     tfm[m] = npm[m] * Tm;
     Tf = std::max(Tf, tfm[m]);
   }

@@ -80,3 +80,29 @@ class GpuProblem:
         opts = L.make_opts(1, max_iter, tol)
         info = L.mfwh_solve_fixed_point(self.grid, self.time, self.f, v, opts, self.ws)
         return v, info
+
+
+class GpuBatch:
+    """A batch of independent workloads solved together by
+    mfwh_solve_gmres_batched (float64, lockstep GMRES, batched step launches)."""
+
+    def __init__(self, workloads, restart=30, device="cuda"):
+        self.items = [GpuProblem(w, restart=0, device=device) for w in workloads]
+        for gp in self.items:            # the batch brings its own workspace
+            gp.ws = None
+        self.restart = restart
+        self.device = torch.device(device)
+        self.v = [gp.zeros() for gp in self.items]
+        self.problems = L.make_problems([(gp.grid, gp.time, gp.f, v)
+                                         for gp, v in zip(self.items, self.v)])
+        nbytes = L.mfwh_workspace_bytes_batched(self.problems, restart)
+        if nbytes == 0:
+            raise L.MfwhError(-1, "invalid batch")
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+
+    def gmres(self, max_iter=1000, tol=1e-8):
+        for v in self.v:
+            v.zero_()
+        opts = L.make_opts(self.restart, max_iter, tol)
+        infos, status = L.mfwh_solve_gmres_batched(self.problems, opts, self.ws)
+        return self.v, infos, status

@@ -158,3 +158,17 @@ def test_workspace_size_grows_with_restart():
     assert b > a > 0
     # 31 basis + 5 work vectors of nf * fs doubles
     assert b - a >= 36 * 2 * 31 * 64 * 8
+
+
+def test_small_omega_dt_first_window_is_whole():
+    """With small omega dt (N_t ~ 1000 steps per period) acos(1 - (omega dt)^2/2)
+    loses ~1e-11 relative precision; both planners must still find exactly
+    N_p whole periods of the first frequency in T_f (eq. TbarDef)."""
+    for w in inputs.config4(0):
+        g = L.make_grid(w["shape"], w["lengths"], 4)
+        T, dt, nt = L.mfwh_plan_time(g, 1.0, float(w["omega"][0]), int(w["np"]), 0.5)
+        info = L.mfwh_plan_info(L.make_time(w["omega"], T, dt))
+        assert info["npm"][0] == w["np"]
+        _, pl = workload.setup(dict(w, f=None), filt="traditional")
+        assert pl.npm[0] == w["np"] and pl.nt == nt
+        assert list(pl.npm) == list(info["npm"])
