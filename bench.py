@@ -24,6 +24,7 @@ Extra fields:
     python bench.py [--gpus 1] [--steps 3] [--warmup 1]
     python bench.py --mode copy      # plain copy kernel of known size (counter calibration)
     python bench.py --mode batch     # 64 independent 2D problems solved as one batch
+    python bench.py --mode warmstart # learned warm start: data, training, evaluation
     python bench.py --mode apply --applies 3   # a few forcing-free float64
                                      # applications of the same workload (for
                                      # rocprofv3: the step kernel as the solver runs it)
@@ -102,7 +103,7 @@ def copy_calibration(nbytes=1 << 30, reps=5):
 
 def batch_bench(args):
     """64 independent 2D problems (grid 129..513, N_f 2..6, omega ~ U(10, 50),
-    order 4, least-squares filters) solved by one batched GMRES(64) call to
+    order 4, least-squares filters) solved by one batched GMRES(160) call to
     1e-8: aggregate throughput and per-problem latency."""
     import torch
     from paper_2507_23613_amd import _lib as L
@@ -110,11 +111,11 @@ def batch_bench(args):
     from paper_2507_23613_amd.problem import GpuBatch, GpuProblem
     ws = inputs.config4(0)
     log(f"batch of {len(ws)} problems")
-    gb = GpuBatch(ws, restart=64)
+    gb = GpuBatch(ws, restart=160)
     log(f"workspace {gb.ws.numel() / 2**30:.1f} GiB")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    _, infos, status = gb.gmres(max_iter=600, tol=1e-8)
+    _, infos, status = gb.gmres(max_iter=800, tol=1e-8)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     ps = sum(i["point_steps"] * len(w["omega"]) for i, w in zip(infos, ws))
@@ -132,8 +133,8 @@ def batch_bench(args):
         t0 = time.perf_counter()
         ps1 = 0
         for k, w in enumerate(ws):
-            gp = GpuProblem(w, restart=64)
-            _, info = gp.gmres(restart=64, max_iter=600, tol=1e-8)
+            gp = GpuProblem(w, restart=160)
+            _, info = gp.gmres(restart=160, max_iter=800, tol=1e-8)
             ps1 += info["point_steps"] * len(w["omega"])
             if k % 8 == 7:
                 log(f"sequential: {k + 1} problems done")
@@ -145,12 +146,81 @@ def batch_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def warmstart_bench(args):
+    """Config-5 study: 2D n^2 (default 256^2), N_f = 4, omega ~ U(20, 50),
+    Gaussian-sum forcings.  Train on float64 MFWH-GMRES solutions (1e-10) of
+    ``--train`` problems, test on ``--test`` held-out problems from a
+    disjoint seed stream: GMRES iterations (batched solver) and wall time to
+    1e-8 (single-problem solver, inference included) from the network's guess
+    with zero fallback against a zero start."""
+    import torch
+    from paper_2507_23613_amd import _lib as L
+    from paper_2507_23613_amd import inputs, warmstart
+    from paper_2507_23613_amd.problem import GpuBatch
+    n = 256 if args.n == 1025 else args.n
+    t0 = time.perf_counter()
+    tr = inputs.config5(seed=1000, count=args.train, n=n)
+    te = inputs.config5(seed=2000, count=args.test, n=n)
+    log(f"drew {len(tr)} + {len(te)} problems ({time.perf_counter() - t0:.0f} s)")
+    F, OM, U, infos = warmstart.solve_set(tr, restart=64, tol=1e-10, max_iter=400, log=log)
+    keep = torch.as_tensor([i for i, x in enumerate(infos) if x["converged"]], device=F.device)
+    F, OM, U = F[keep], OM[keep], U[keep]
+    log(f"training set: {len(keep)} converged solutions ({time.perf_counter() - t0:.0f} s)")
+    model = warmstart.WarmStart(nf=4, H=n, W=n, batch=16)
+    feats, targets = model.features(F, OM), model.targets(F, OM, U)
+    del U
+    t1 = time.perf_counter()
+    hist = model.train(feats, targets, epochs=args.epochs, lr=1e-3, log=log)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t1
+    del feats, targets
+    zero_its, warm_its, fell, init_res = [], [], 0, []
+    for s in range(0, len(te), 64):
+        part = te[s:s + 64]
+        gb = GpuBatch(part, restart=64)
+        _, i0, _ = gb.gmres(max_iter=800, tol=1e-8)
+        Fb = torch.stack([gp.f for gp in gb.items])
+        OMb = torch.stack([torch.as_tensor(gp.omega, device=gp.device) for gp in gb.items])
+        v0 = model.predict(Fb, OMb)
+        _, i1, _ = gb.gmres(max_iter=800, tol=1e-8, initial=[v0[k] for k in range(len(part))],
+                            zero_fallback=1, scale_initial=1)
+        zero_its += [x["iterations"] for x in i0]
+        warm_its += [x["iterations"] for x in i1]
+        fell += sum(x["fell_back"] for x in i1)
+        init_res += [x["initial_rel_residual"] for x in i1]
+        log(f"evaluated {min(s + 64, len(te))}/{len(te)}")
+        del gb
+    rows = warmstart.compare_solves(te[:args.compare], model, restart=64)
+    rows32 = warmstart.compare_solves(te[:min(4, args.compare)], model, restart=64,
+                                      precision=L.MFWH_FP32_STENCIL)
+    out = {"mode": "warmstart", "grid": [n, n], "train": int(len(keep)), "test": len(te),
+           "epochs": args.epochs, "train_s": round(train_s, 1),
+           "loss_first_last": [hist[0], hist[-1]],
+           "iterations_zero_mean": float(np.mean(zero_its)),
+           "iterations_warm_mean": float(np.mean(warm_its)),
+           "iterations_zero_median": float(np.median(zero_its)),
+           "iterations_warm_median": float(np.median(warm_its)),
+           "fallbacks": int(fell), "initial_rel_residual_median": float(np.median(init_res)),
+           "single_fp64_zero_s_mean": float(np.mean([r["zero_s"] for r in rows])),
+           "single_fp64_warm_s_mean": float(np.mean([r["warm_s"] for r in rows])),
+           "single_fp32_warm_s_mean": float(np.mean([r["warm_s"] for r in rows32])),
+           "single_fp32_warm_converged": int(sum(r["warm_conv"] for r in rows32)),
+           "single_compared": len(rows)}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--mode", default="solve", choices=["solve", "copy", "apply", "batch"])
+    ap.add_argument("--mode", default="solve",
+                    choices=["solve", "copy", "apply", "batch", "warmstart"])
+    ap.add_argument("--train", type=int, default=2000)
+    ap.add_argument("--test", type=int, default=200)
+    ap.add_argument("--epochs", type=int, default=20)
+    ap.add_argument("--compare", type=int, default=16,
+                    help="warmstart mode: test problems timed one at a time")
     ap.add_argument("--no-tune", action="store_true", help="skip the launch-shape autotuner")
     ap.add_argument("--sequential", action="store_true",
                     help="batch mode: also solve the problems one at a time")
@@ -174,6 +244,9 @@ def main():
 
     if args.mode == "batch":
         batch_bench(args)
+        return
+    if args.mode == "warmstart":
+        warmstart_bench(args)
         return
 
     w = inputs.config2(0, n=args.n)

@@ -95,6 +95,13 @@ typedef struct mfwh_solve_opts {
   double inner_tol;      /* MFWH_FP32_STENCIL: relative tolerance of each inner
                             GMRES solve of iterative refinement             [1e-5] */
   int max_outer;         /* MFWH_FP32_STENCIL: max refinement steps          [20]  */
+  int zero_fallback;     /* 1: if the given initial guess has a larger residual
+                            than the zero start (||b - A v0|| > ||b||), start
+                            from zero instead (warm-start safety net)      [0]   */
+  int scale_initial;     /* 1: replace a nonzero initial guess v0 by alpha v0 with
+                            alpha = <A v0, b> / <A v0, A v0>, the scaling that
+                            minimises ||b - alpha A v0|| (never worse than the
+                            zero start); costs no extra application          [0]   */
 } mfwh_solve_opts;
 
 /* Solver report (host struct filled on return). */
@@ -104,6 +111,9 @@ typedef struct mfwh_solve_info {
   int outer;               /* refinement steps (MFWH_FP32_STENCIL GMRES)          */
   double rel_residual;     /* final relative residual (see each solver)           */
   long long point_steps;   /* sum over applications of interior points x N_t      */
+  int fell_back;           /* 1 if zero_fallback rejected the initial guess         */
+  double initial_rel_residual; /* ||b - A v0|| / ||b|| of the (scaled) initial guess */
+  double initial_scale;    /* alpha applied by scale_initial (1 otherwise)          */
 } mfwh_solve_info;
 
 /* Description of the last error on the calling thread ("" if none). */
@@ -228,6 +238,63 @@ size_t mfwh_workspace_bytes_batched(int nprob, const mfwh_problem* probs, int re
 int mfwh_solve_gmres_batched(int nprob, const mfwh_problem* probs, const mfwh_solve_opts* opts,
                              mfwh_solve_info* infos, double* latency_ms, void* ws,
                              size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------- *
+ * Learned warm start (not part of the paper: an initial guess for GMRES)
+ *
+ * A 6-layer convolutional encoder-decoder (3x3 convolutions, 32-64 channels,
+ * two stride-2 encoder layers, two nearest-up-sampling decoder layers with
+ * additive skips, ReLU) maps per-problem input channels to N_f output
+ * channels.  All convolutions run as BF16 MFMA GEMMs with float32
+ * accumulation; activations, gradients and master weights are float32.
+ * Layouts: features/outputs/targets NHWC [B][H][W][C] float32 over the FULL
+ * grid (H = n[1], W = n[0], boundary included); parameters one flat float32
+ * vector, per layer W[cout][cin][3][3] then b[cout], layers in the order
+ * above.  Workspace: caller-owned device memory, 256-byte aligned.
+ * ------------------------------------------------------------------------- */
+size_t mfwh_cnn_param_count(int nf);
+size_t mfwh_cnn_workspace_bytes(int batch, int nf, int H, int W);
+const char* mfwh_cnn_last_error(void);
+
+/* Input channels (6 nf): f_m / max|f_m|, sin(omega_m x), cos(omega_m x),
+ * sin(omega_m y), cos(omega_m y), omega_m / 50.  f: device [B][nf][H][W]
+ * float64 (ABI layout); omega: device [B][nf] float64; ly, lx: domain
+ * lengths; feat: device NHWC float32. */
+int mfwh_cnn_features(int batch, int nf, int H, int W, const double* f, const double* omega,
+                      double ly, double lx, float* feat, void* ws, size_t ws_bytes,
+                      void* stream);
+
+/* Scaling between network outputs and fields: dir 0: v (float64 ABI layout,
+ * zero boundary) = out * max|f_m| / omega_m^2;  dir 1: out = v * omega_m^2 /
+ * max|f_m| (training targets). */
+int mfwh_cnn_scale(int dir, int batch, int nf, int H, int W, float* out, double* v,
+                   const double* f, const double* omega, void* ws, size_t ws_bytes,
+                   void* stream);
+
+/* Divide each of `batch` consecutive samples of per_sample floats by its
+ * root-mean-square (training targets of unit scale; the solver's
+ * scale_initial option restores the amplitude of a prediction). */
+int mfwh_cnn_normalize(int batch, long long per_sample, float* t, void* stream);
+
+/* Network output out (device NHWC [B][H][W][nf] float32). */
+int mfwh_cnn_forward(int batch, int nf, int H, int W, const float* params, const float* feat,
+                     float* out, void* ws, size_t ws_bytes, void* stream);
+
+/* Mean-squared-error loss against target (NHWC) and its gradient w.r.t. the
+ * flat parameters (device float32, overwritten); *loss (host) may be NULL. */
+int mfwh_cnn_loss_grad(int batch, int nf, int H, int W, const float* params, const float* feat,
+                       const float* target, float* grad, double* loss, void* ws,
+                       size_t ws_bytes, void* stream);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) on n parameters; step >= 1. */
+int mfwh_cnn_adam(long long n, float* params, const float* grad, float* m, float* v, int step,
+                  float lr, void* stream);
+
+/* The BF16 MFMA GEMM the convolutions use: C[M][N] (float32) = A * B with A
+ * bf16 [M][K] (atrans 0) or stored [K][M] (atrans 1), B bf16 [K][N]; part:
+ * float32 scratch of 64*M*N for long reductions (K > 8192 with atrans 1). */
+int mfwh_gemm_bf16(int atrans, const void* A, const void* B, float* C, long long M, int N,
+                   long long K, int lda, int ldb, int ldc, float* part, void* stream);
 
 /* ------------------------------------------------------------------------- *
  * Measurement hooks

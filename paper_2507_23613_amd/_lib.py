@@ -47,12 +47,14 @@ class mfwh_time(ctypes.Structure):
 
 class mfwh_solve_opts(ctypes.Structure):
     _fields_ = [("restart", c_int), ("max_iter", c_int), ("tol", c_double),
-                ("inner_tol", c_double), ("max_outer", c_int)]
+                ("inner_tol", c_double), ("max_outer", c_int), ("zero_fallback", c_int),
+                ("scale_initial", c_int)]
 
 
 class mfwh_solve_info(ctypes.Structure):
     _fields_ = [("iterations", c_int), ("applies", c_int), ("outer", c_int),
-                ("rel_residual", c_double), ("point_steps", c_longlong)]
+                ("rel_residual", c_double), ("point_steps", c_longlong), ("fell_back", c_int),
+                ("initial_rel_residual", c_double), ("initial_scale", c_double)]
 
 
 class mfwh_problem(ctypes.Structure):
@@ -96,6 +98,22 @@ def _load():
                                              ctypes.POINTER(mfwh_solve_opts),
                                              ctypes.POINTER(mfwh_solve_info), P_double, c_void_p,
                                              c_size_t, c_void_p]),
+        "mfwh_cnn_param_count": (c_size_t, [c_int]),
+        "mfwh_cnn_workspace_bytes": (c_size_t, [c_int, c_int, c_int, c_int]),
+        "mfwh_cnn_last_error": (ctypes.c_char_p, []),
+        "mfwh_cnn_features": (c_int, [c_int, c_int, c_int, c_int, c_void_p, c_void_p, c_double,
+                                      c_double, c_void_p, c_void_p, c_size_t, c_void_p]),
+        "mfwh_cnn_scale": (c_int, [c_int, c_int, c_int, c_int, c_int, c_void_p, c_void_p,
+                                   c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
+        "mfwh_cnn_normalize": (c_int, [c_int, c_longlong, c_void_p, c_void_p]),
+        "mfwh_cnn_forward": (c_int, [c_int, c_int, c_int, c_int, c_void_p, c_void_p, c_void_p,
+                                     c_void_p, c_size_t, c_void_p]),
+        "mfwh_cnn_loss_grad": (c_int, [c_int, c_int, c_int, c_int, c_void_p, c_void_p, c_void_p,
+                                       c_void_p, P_double, c_void_p, c_size_t, c_void_p]),
+        "mfwh_cnn_adam": (c_int, [c_longlong, c_void_p, c_void_p, c_void_p, c_void_p, c_int,
+                                  ctypes.c_float, c_void_p]),
+        "mfwh_gemm_bf16": (c_int, [c_int, c_void_p, c_void_p, c_void_p, c_longlong, c_int,
+                                   c_longlong, c_int, c_int, c_int, c_void_p, c_void_p]),
         "mfwh_stats_enable": (c_int, [c_int, c_int]),
         "mfwh_stats_read": (c_int, [ctypes.POINTER(c_longlong), P_double, P_double]),
         "mfwh_set_launch_shape": (c_int, [c_int, c_int, c_int]),
@@ -180,10 +198,13 @@ def make_time(omega, T, dt, filt=None):
     return t
 
 
-def make_opts(restart=30, max_iter=1000, tol=1e-8, inner_tol=1e-5, max_outer=20):
+def make_opts(restart=30, max_iter=1000, tol=1e-8, inner_tol=1e-5, max_outer=20,
+              zero_fallback=0, scale_initial=0):
     o = mfwh_solve_opts()
     o.restart, o.max_iter, o.tol = int(restart), int(max_iter), float(tol)
     o.inner_tol, o.max_outer = float(inner_tol), int(max_outer)
+    o.zero_fallback = int(zero_fallback)
+    o.scale_initial = int(scale_initial)
     return o
 
 
@@ -260,7 +281,9 @@ def _solve(fn, grid, time, f, v, opts, ws, stream, hist_len):
     _check(rc, allow_not_converged=True)
     return dict(status=STATUS[rc], converged=(rc == 0), iterations=info.iterations,
                 applies=info.applies, outer=info.outer, rel_residual=info.rel_residual,
-                point_steps=info.point_steps, history=hist[:info.iterations].copy())
+                point_steps=info.point_steps, fell_back=bool(info.fell_back),
+                initial_rel_residual=info.initial_rel_residual,
+                initial_scale=info.initial_scale, history=hist[:info.iterations].copy())
 
 
 def mfwh_solve_fixed_point(grid, time, f, v, opts, ws, stream=None):
@@ -300,7 +323,10 @@ def mfwh_solve_gmres_batched(problems, opts, ws, stream=None):
     _check(rc, allow_not_converged=True)
     return [dict(converged=infos[k].rel_residual <= opts.tol, iterations=infos[k].iterations,
                  applies=infos[k].applies, rel_residual=infos[k].rel_residual,
-                 point_steps=infos[k].point_steps, latency_ms=float(lat[k]))
+                 point_steps=infos[k].point_steps, latency_ms=float(lat[k]),
+                 fell_back=bool(infos[k].fell_back),
+                 initial_rel_residual=infos[k].initial_rel_residual,
+                 initial_scale=infos[k].initial_scale)
             for k in range(n)], STATUS[rc]
 
 
@@ -323,3 +349,89 @@ def mfwh_set_option(key, value):
 
 def mfwh_set_launch_shape(bx=0, by=1, chunk=8):
     _check(LIB.mfwh_set_launch_shape(int(bx), int(by), int(chunk)))
+
+
+# ----------------------------------------------------------------------------
+# learned warm start (network kernels)
+# ----------------------------------------------------------------------------
+def _cnn_check(rc):
+    if rc != 0:
+        raise MfwhError(rc, LIB.mfwh_cnn_last_error().decode())
+
+
+def _ptr(t, what, dtype=None):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or not t.is_contiguous():
+        raise TypeError(f"{what} must be a contiguous GPU tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{what} must be {dtype}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _wsargs(ws):
+    return ctypes.c_void_p(ws.data_ptr()), ws.numel() * ws.element_size()
+
+
+def mfwh_cnn_param_count(nf):
+    return int(LIB.mfwh_cnn_param_count(int(nf)))
+
+
+def mfwh_cnn_workspace_bytes(batch, nf, H, W):
+    return int(LIB.mfwh_cnn_workspace_bytes(batch, nf, H, W))
+
+
+def mfwh_cnn_features(f, omega, lengths, feat, ws, stream=None):
+    import torch
+    B, nf, H, W = f.shape
+    _cnn_check(LIB.mfwh_cnn_features(B, nf, H, W, _ptr(f, "f", torch.float64),
+                                     _ptr(omega, "omega", torch.float64), float(lengths[0]),
+                                     float(lengths[1]), _ptr(feat, "feat", torch.float32),
+                                     *_wsargs(ws), _stream(stream)))
+
+
+def mfwh_cnn_scale(direction, out, v, f, omega, ws, stream=None):
+    import torch
+    B, nf, H, W = f.shape
+    _cnn_check(LIB.mfwh_cnn_scale(int(direction), B, nf, H, W, _ptr(out, "out", torch.float32),
+                                  _ptr(v, "v", torch.float64), _ptr(f, "f", torch.float64),
+                                  _ptr(omega, "omega", torch.float64), *_wsargs(ws),
+                                  _stream(stream)))
+
+
+def mfwh_cnn_normalize(t, stream=None):
+    import torch
+    _cnn_check(LIB.mfwh_cnn_normalize(t.shape[0], t[0].numel(), _ptr(t, "t", torch.float32),
+                                      _stream(stream)))
+
+
+def mfwh_cnn_forward(params, feat, out, nf, ws, stream=None):
+    import torch
+    B, H, W, _ = feat.shape
+    _cnn_check(LIB.mfwh_cnn_forward(B, nf, H, W, _ptr(params, "params", torch.float32),
+                                    _ptr(feat, "feat", torch.float32),
+                                    _ptr(out, "out", torch.float32), *_wsargs(ws),
+                                    _stream(stream)))
+
+
+def mfwh_cnn_loss_grad(params, feat, target, grad, nf, ws, stream=None):
+    import torch
+    B, H, W, _ = feat.shape
+    loss = c_double()
+    _cnn_check(LIB.mfwh_cnn_loss_grad(B, nf, H, W, _ptr(params, "params", torch.float32),
+                                      _ptr(feat, "feat", torch.float32),
+                                      _ptr(target, "target", torch.float32),
+                                      _ptr(grad, "grad", torch.float32), ctypes.byref(loss),
+                                      *_wsargs(ws), _stream(stream)))
+    return loss.value
+
+
+def mfwh_cnn_adam(params, grad, m, v, step, lr, stream=None):
+    _cnn_check(LIB.mfwh_cnn_adam(params.numel(), _ptr(params, "params"), _ptr(grad, "grad"),
+                                 _ptr(m, "m"), _ptr(v, "v"), int(step), float(lr),
+                                 _stream(stream)))
+
+
+def mfwh_gemm_bf16(A, B, C, atrans, M, N, K, lda, ldb, ldc, part=None, stream=None):
+    _cnn_check(LIB.mfwh_gemm_bf16(int(atrans), _ptr(A, "A"), _ptr(B, "B"), _ptr(C, "C"),
+                                  int(M), int(N), int(K), int(lda), int(ldb), int(ldc),
+                                  None if part is None else _ptr(part, "part"), _stream(stream)))

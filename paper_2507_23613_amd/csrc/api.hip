@@ -739,7 +739,11 @@ void fill_opts(const mfwh_solve_opts* in, mfwh_solve_opts* o) {
   o->tol = 1e-8;
   o->inner_tol = 1e-5;
   o->max_outer = 20;
+  o->zero_fallback = 0;
+  o->scale_initial = 0;
   if (in) {
+    o->zero_fallback = in->zero_fallback;
+    o->scale_initial = in->scale_initial;
     if (in->restart > 0) o->restart = in->restart;
     if (in->max_iter > 0) o->max_iter = in->max_iter;
     if (in->tol > 0) o->tol = in->tol;
@@ -894,6 +898,9 @@ int mfwh_solve_fixed_point(const mfwh_grid* g, const mfwh_time* t, const double*
     info->outer = 0;
     info->rel_residual = r1 > 0 ? r / r1 : 0.0;
     info->point_steps = pr.point_steps;
+    info->fell_back = 0;
+    info->initial_rel_residual = 1.0;
+    info->initial_scale = 1.0;
   }
   return status;
 }
@@ -935,6 +942,34 @@ int mfwh_solve_gmres(const mfwh_grid* g, const mfwh_time* t, const double* f, do
   double xn;
   CHK(norm2(V, X, &xn));
   bool xzero = xn == 0.0;
+  int fell_back = 0;
+  double init_rel = 1.0;
+  double init_scale = 1.0;
+  if (!xzero) {
+    // residual of the initial guess (float64); optionally the residual-optimal
+    // scaling alpha = <A x, b>/<A x, A x>; reject the guess if worse than zero
+    Out orr{R, il, X, il, 1.0, -1.0, nullptr};
+    CHK(apply_t<double>(pr, X, il, false, orr));          // R = A x
+    double alpha = 1.0;
+    if (o.scale_initial) {
+      double d1[1], d2;
+      CHK(dots(V, R, 1, B, pr.W.scal + pr.W.nscal - 8, d1));
+      CHK(norm2(V, R, &d2));
+      alpha = d2 > 0 ? d1[0] / (d2 * d2) : 0.0;
+      HIPCHK(launch_axpby(0.0, X, alpha, X, V.N, pr.s));  // x = alpha x
+      init_scale = alpha;
+    }
+    HIPCHK(launch_axpby(1.0, B, -alpha, R, V.N, pr.s));   // R = b - alpha A x
+    double rn;
+    CHK(norm2(V, R, &rn));
+    init_rel = rn / bnorm;
+    if (o.zero_fallback && !(rn <= bnorm)) {
+      HIPCHK(launch_fill(X, V.N, 0.0, pr.s));
+      xzero = true;
+      fell_back = 1;
+      init_rel = 1.0;
+    }
+  }
   KrylovResult kr;
   int status = MFWH_NOT_CONVERGED;
   int outer = 0;
@@ -1010,8 +1045,9 @@ int mfwh_solve_gmres_batched(int nprob, const mfwh_problem* probs, const mfwh_so
     std::vector<double> H, cs, sn, g, y, hh;
     double bnorm = 0, res = 0;
     int its = 0, k = 0;
-    bool xzero = true, done = false, conv = false, live = false;
-    double lat = 0;
+    bool xzero = true, done = false, conv = false, live = false, first = true;
+    int fell_back = 0;
+    double lat = 0, init_rel = 1.0, scale = 1.0;
   };
   std::vector<St> S(np);
   std::vector<int> all(np);
@@ -1066,6 +1102,16 @@ int mfwh_solve_gmres_batched(int nprob, const mfwh_problem* probs, const mfwh_so
     for (int i : cyc) {
       St& st = S[i];
       double* v0 = st.V.vec(0);
+      if (st.first && !st.xzero && o.scale_initial) {
+        // v0 holds A x: residual-optimal scaling of the initial guess
+        double d1[1], d2;
+        CHK(dots(st.V, v0, 1, Bv(i), B.pr[i]->W.scal + B.pr[i]->W.nscal - 8, d1));
+        CHK(norm2(st.V, v0, &d2));
+        const double alpha = d2 > 0 ? d1[0] / (d2 * d2) : 0.0;
+        HIPCHK(launch_axpby(0.0, X(i), alpha, X(i), st.V.N, B.s));
+        HIPCHK(launch_axpby(0.0, v0, alpha, v0, st.V.N, B.s));
+        st.scale = alpha;
+      }
       if (st.xzero)
         HIPCHK(hipMemcpyAsync(v0, Bv(i), st.V.N * sizeof(double), hipMemcpyDeviceToDevice, B.s));
       else
@@ -1073,6 +1119,21 @@ int mfwh_solve_gmres_batched(int nprob, const mfwh_problem* probs, const mfwh_so
       double beta;
       CHK(norm2(st.V, v0, &beta));
       if (!std::isfinite(beta)) return fail(MFWH_ENONFINITE, "non-finite residual in batch");
+      if (st.first) {
+        st.first = false;
+        if (!st.xzero) {
+          st.init_rel = beta / st.bnorm;
+          if (o.zero_fallback && !(beta <= st.bnorm)) {   // warm start worse than zero
+            HIPCHK(launch_fill(X(i), st.V.N, 0.0, B.s));
+            HIPCHK(hipMemcpyAsync(v0, Bv(i), st.V.N * sizeof(double), hipMemcpyDeviceToDevice,
+                                  B.s));
+            st.xzero = true;
+            st.fell_back = 1;
+            st.init_rel = 1.0;
+            beta = st.bnorm;
+          }
+        }
+      }
       st.res = beta;
       if (beta <= o.tol * st.bnorm || st.its >= o.max_iter) {
         st.done = true;
@@ -1192,6 +1253,9 @@ int mfwh_solve_gmres_batched(int nprob, const mfwh_problem* probs, const mfwh_so
       infos[i].outer = 0;
       infos[i].rel_residual = S[i].res / S[i].bnorm;
       infos[i].point_steps = pr.point_steps;
+      infos[i].fell_back = S[i].fell_back;
+      infos[i].initial_rel_residual = S[i].init_rel;
+      infos[i].initial_scale = S[i].scale;
     }
     if (latency_ms) latency_ms[i] = S[i].lat;
   }

@@ -69,9 +69,10 @@ class GpuProblem:
         return out
 
     def gmres(self, v=None, restart=None, max_iter=1000, tol=1e-8, inner_tol=1e-5,
-              max_outer=20):
+              max_outer=20, zero_fallback=0, scale_initial=0):
         v = self.zeros() if v is None else v
-        opts = L.make_opts(restart or self.restart, max_iter, tol, inner_tol, max_outer)
+        opts = L.make_opts(restart or self.restart, max_iter, tol, inner_tol, max_outer,
+                           zero_fallback, scale_initial)
         info = L.mfwh_solve_gmres(self.grid, self.time, self.f, v, opts, self.ws)
         return v, info
 
@@ -100,9 +101,14 @@ class GpuBatch:
             raise L.MfwhError(-1, "invalid batch")
         self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
 
-    def gmres(self, max_iter=1000, tol=1e-8):
-        for v in self.v:
-            v.zero_()
-        opts = L.make_opts(self.restart, max_iter, tol)
+    def gmres(self, max_iter=1000, tol=1e-8, initial=None, zero_fallback=0, scale_initial=0):
+        """initial: optional list of device tensors (initial guesses)."""
+        for k, v in enumerate(self.v):
+            if initial is None:
+                v.zero_()
+            else:
+                v.copy_(initial[k])
+        opts = L.make_opts(self.restart, max_iter, tol, zero_fallback=zero_fallback,
+                           scale_initial=scale_initial)
         infos, status = L.mfwh_solve_gmres_batched(self.problems, opts, self.ws)
         return self.v, infos, status
