@@ -228,6 +228,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-fp32", action="store_true", help="skip the float32-stencil solve")
     ap.add_argument("--n", type=int, default=1025, help="grid points per axis")
+    ap.add_argument("--spp", type=int, default=2, choices=[0, 1, 2],
+                    help="2D step kernel: 0 general, 1 streamlined, 2 streamlined two-step")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); multi-GPU slab "
@@ -242,6 +244,7 @@ def main():
     from paper_2507_23613_amd import inputs
     from paper_2507_23613_amd.problem import GpuProblem
 
+    L.mfwh_set_option(L.MFWH_OPT_STEPS_PER_PASS, args.spp)
     if args.mode == "batch":
         batch_bench(args)
         return
@@ -265,9 +268,14 @@ def main():
         v = torch.randn((nf,) + tuple(w["shape"]), dtype=torch.float64, device="cuda")
         out = torch.empty_like(v)
         for k in range(args.applies):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
             L.mfwh_apply(gp.grid, gp.time, None, v, out, 0, gp.ws)
+            e1.record()
             torch.cuda.synchronize()
-            log(f"apply {k} done")
+            ms = e0.elapsed_time(e1)
+            log(f"apply {k}: {ms:.2f} ms, {gp.interior_points * gp.nt * nf / ms / 1e6:.3e} "
+                f"grid-point-steps/s x Nf (steps per pass {args.spp})")
         return
 
     def solve():

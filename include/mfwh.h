@@ -310,19 +310,27 @@ int mfwh_stats_enable(int on, int sample_every);
  * forcings when on, read+write every active float64 accumulator, read c^2). */
 int mfwh_stats_read(long long* launches, double* total_ms, double* total_bytes);
 
-/* Override the launch shape of the step kernel for all later calls in this
- * process (autotuning): bx threads along x (32, 64, 128 or 256), by threads
- * along y (3D: 4, 8 or 2 with bx 64/64/128; 8 with bx 32), chunk rows (2D) or
- * planes (3D) marched per block.  bx = 0 restores the built-in heuristic. */
+/* Override the launch shape of the step kernels for all later calls in this
+ * process (autotuning): bx threads along x (32, 64, 128 or 256; the
+ * streamlined 2D kernels take 64, 128 or 256), by threads along y (3D: 4, 8
+ * or 2 with bx 64/64/128; 8 with bx 32), chunk rows (2D) or planes (3D)
+ * marched per block.  bx = 0 restores the built-in heuristics. */
 int mfwh_set_launch_shape(int bx, int by, int chunk);
 
-/* Process-wide options.
+/* Process-wide options, read when a call sets up its problem.
  * MFWH_OPT_GRAPHS (default 1): the fixed-point and GMRES solvers record the
- * N_t step launches of an application into a HIP graph once per solve and
+ * step launches of an application into a HIP graph once per solve and
  * replay it for every application; 0 launches every step from the host.
  * While step timing (mfwh_stats_enable) is on, a graph replay is timed as a
- * whole and counted as N_t launches. */
-enum { MFWH_OPT_GRAPHS = 1 };
+ * whole and counted as the number of step launches it holds.
+ * MFWH_OPT_STEPS_PER_PASS (2D grids; default 2): after the first step,
+ * 0 runs every step with the general step kernel, 1 with the streamlined 2D
+ * kernel one step per launch, 2 with the streamlined kernel two steps per
+ * launch (temporal blocking: W^{n+1} is recomputed on a halo and every filter
+ * accumulator is read and written once per two steps).  All three compute
+ * the same values up to floating-point contraction; 1D and 3D grids always
+ * use the general kernel. */
+enum { MFWH_OPT_GRAPHS = 1, MFWH_OPT_STEPS_PER_PASS = 2 };
 int mfwh_set_option(int key, long long value);
 
 #ifdef __cplusplus

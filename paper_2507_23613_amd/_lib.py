@@ -341,6 +341,7 @@ def mfwh_stats_read():
 
 
 MFWH_OPT_GRAPHS = 1
+MFWH_OPT_STEPS_PER_PASS = 2
 
 
 def mfwh_set_option(key, value):

@@ -10,7 +10,7 @@ import torch
 
 from . import _lib as L
 
-CAND_2D = [(bx, 1, ch) for bx in (64, 128, 256) for ch in (2, 4, 8, 16, 32)]
+CAND_2D = [(bx, 1, ch) for bx in (64, 128, 256) for ch in (2, 4, 8, 16, 32, 64)]
 CAND_3D = [(64, 4, ch) for ch in (2, 4, 8, 16, 32)] + \
           [(64, 8, ch) for ch in (4, 8, 16)] + [(128, 2, ch) for ch in (4, 8, 16)] + \
           [(32, 8, ch) for ch in (4, 8)]

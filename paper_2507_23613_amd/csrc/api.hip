@@ -117,6 +117,8 @@ constexpr int kRedBlocks = 1024;   // reduction blocks of the finalize/BLAS kern
 struct Workspace {
   double *w64a = nullptr, *w64b = nullptr, *f64 = nullptr, *c64 = nullptr;
   float *w32a = nullptr, *w32b = nullptr, *f32 = nullptr, *c32 = nullptr;
+  double *w64c = nullptr, *w64d = nullptr;   // 2D: outputs of two-step passes
+  float *w32c = nullptr, *w32d = nullptr;
   double* q = nullptr;
   double* partial = nullptr;   // (restart+2) * kRedBlocks doubles
   double* scal = nullptr;      // device scalars: 4 (restart+2) + 16 doubles
@@ -137,13 +139,22 @@ Workspace carve(const Geom& G, int nf, bool fp32, bool varc, int restart, char* 
     return p;
   };
   const size_t fs = (size_t)G.fs;
+  const bool two = G.dim == 2;
   w.w64a = (double*)take(fs * 8);
   w.w64b = (double*)take(fs * 8);
+  if (two) {
+    w.w64c = (double*)take(fs * 8);
+    w.w64d = (double*)take(fs * 8);
+  }
   w.f64 = (double*)take(fs * 8 * nf);
   if (varc) w.c64 = (double*)take(fs * 8);
   if (fp32) {
     w.w32a = (float*)take(fs * 4);
     w.w32b = (float*)take(fs * 4);
+    if (two) {
+      w.w32c = (float*)take(fs * 4);
+      w.w32d = (float*)take(fs * 4);
+    }
     w.f32 = (float*)take(fs * 4 * nf);
     if (varc) w.c32 = (float*)take(fs * 4);
   }
@@ -179,7 +190,9 @@ struct Problem {
   hipStream_t s = nullptr;
   bool fp32 = false, varc = false;
   bool graphs = false;               // replay recorded step sequences
+  int spp = 0;                       // 2D: 0 general kernel, 1 or 2 streamlined steps per pass
   LaunchShape shape64, shape32;
+  LaunchShape leap;                  // shape of the streamlined 2D kernels
   long long point_steps = 0;
   int applies = 0;
   StepGraph sg[2][2];                // [float32][forcing]
@@ -195,6 +208,7 @@ struct Problem {
 LaunchShape g_shape_override;   // bx == 0: use defaults
 bool g_shape_set = false;
 bool g_graphs = true;           // solvers record step sequences into graphs
+int g_steps_per_pass = 2;       // 2D step kernel selection (MFWH_OPT_STEPS_PER_PASS)
 
 int setup(Problem& pr, const mfwh_grid* g, const mfwh_time* t, int restart, void* ws,
           size_t ws_bytes, void* stream) {
@@ -214,7 +228,9 @@ int setup(Problem& pr, const mfwh_grid* g, const mfwh_time* t, int restart, void
                                      " bytes, got " + std::to_string(ws_bytes));
   pr.shape64 = default_shape(pr.G, g->order, 8);
   pr.shape32 = default_shape(pr.G, g->order, 4);
-  if (g_shape_set) pr.shape64 = pr.shape32 = g_shape_override;
+  pr.spp = pr.G.dim == 2 ? g_steps_per_pass : 0;
+  pr.leap = default_leap_shape(pr.G, pr.spp);
+  if (g_shape_set) pr.shape64 = pr.shape32 = pr.leap = g_shape_override;
   // stability of explicit leapfrog for c = 1 (variable c is the caller's duty)
   double h[3];
   for (int k = 0; k < g->dim; ++k) h[k] = g->len[k] / (g->n[k] - 1);
@@ -291,6 +307,15 @@ int apply_t(Problem& pr, const double* v, ExtLayout vl, bool forcing, const Out&
   if (v) HIPCHK(launch_init_w0<T>(pr.G, nf, v, vl, wa, pr.s));
   else HIPCHK(launch_fill_t<T>(wa, pr.G.fs, T(0), pr.s));
 
+  T* wc4 = nullptr;
+  T* wd4 = nullptr;
+  if constexpr (sizeof(T) == 8) {
+    wc4 = (T*)pr.W.w64c; wd4 = (T*)pr.W.w64d;
+  } else {
+    wc4 = (T*)pr.W.w32c; wd4 = (T*)pr.W.w32d;
+  }
+  const int spp = (wc4 && wd4) ? pr.spp : 0;
+
   StepArgs<T> a{};
   a.c2 = pr.varc ? c2 : nullptr;
   a.f = forcing ? f : nullptr;
@@ -298,40 +323,127 @@ int apply_t(Problem& pr, const double* v, ExtLayout vl, bool forcing, const Out&
   a.g = pr.G;
   stencil_weights<T>(pr.grid, a.wx, a.wy, a.wz);
   a.force = forcing ? 1 : 0;
+  LeapArgs<T> la{};
+  la.c2 = a.c2;
+  la.f = a.f;
+  la.q = a.q;
+  la.g = a.g;
+  for (int k = 0; k < 3; ++k) {
+    la.wx[k] = a.wx[k];
+    la.wy[k] = a.wy[k];
+  }
+  la.force = a.force;
   const int sort = sizeof(T) == 8 ? 8 : 4;
-  double bytes_all = 0.0;          // algorithmic bytes of the whole sequence
-  // one step: W^{n+1} from W^n (and W^{n-1}); launched on stream `s`
-  auto step = [&](int n, hipStream_t s, double* bytes) -> hipError_t {
-    const double dt2 = P.dt * P.dt;
-    const bool first = n == 0;
-    const bool even = (n & 1) == 0;
-    a.wc = even ? wa : wb;
-    a.wp = even ? wb : wa;
-    a.wout = even ? wb : wa;
-    a.first = first ? 1 : 0;
-    a.cA = first ? T(1) : T(2);
-    a.cB = first ? T(0) : T(-1);
-    a.cC = (T)(first ? 0.5 * dt2 : dt2);
-    int mask = 0, nact = 0;
-    for (int m = 0; m < MFWH_MAX_NF; ++m) {
-      if (m < nf) {
-        a.phi[m] = forcing ? (T)P.phi[(size_t)n * nf + m] : T(0);
-        a.kap[m] = P.kappa[(size_t)(n + 1) * nf + m];
-        a.kap0[m] = first ? P.kappa[m] : 0.0;
-        if (first || a.kap[m] != 0.0) { mask |= 1 << m; ++nact; }
-      } else {
-        a.phi[m] = T(0);
-        a.kap[m] = a.kap0[m] = 0.0;
-      }
-    }
-    a.mask = mask;
-    // algorithmic bytes: read W^n (and W^{n-1}), write W^{n+1}; forcing
-    // reads; read+write of every active float64 accumulator (write only on
-    // the first step); c^2
-    *bytes = ((first ? 2 : 3) * sort + (forcing ? nf * sort : 0) +
-              (first ? 1 : 2) * 8.0 * nact + (pr.varc ? sort : 0)) * (double)pr.G.npts();
-    return launch_step<T>(a, pr.grid->order, nf, *ls, s);
+  const double dt2 = P.dt * P.dt;
+  const double npts = (double)pr.G.npts();
+
+  // The launch sequence of one application: the first step with the general
+  // kernel, then (2D) streamlined passes of one or two steps.  W buffers roll:
+  // a one-step pass overwrites W^{n-1} in place, a two-step pass writes the
+  // two buffers that hold neither input.
+  struct Op {
+    int n, kind;          // kind 0: general kernel, 1/2: streamlined steps
+    T *wc, *wp, *w1, *w2;
   };
+  std::vector<Op> ops;
+  {
+    T* prev = wb;
+    T* cur = wa;
+    T* spare[2] = {wc4, wd4};
+    int n = 0;
+    while (n < P.nt) {
+      const int kind = n == 0 ? 0 : spp == 2 && n + 1 < P.nt ? 2 : spp >= 1 ? 1 : 0;
+      Op op{n, kind, cur, prev, prev, nullptr};
+      if (kind == 2) {
+        op.w1 = spare[0];
+        op.w2 = spare[1];
+        spare[0] = prev;
+        spare[1] = cur;
+        prev = op.w1;
+        cur = op.w2;
+        n += 2;
+      } else {
+        prev = cur;
+        cur = op.w1;
+        n += 1;
+      }
+      ops.push_back(op);
+    }
+  }
+  // active accumulators of the step producing W^{k+1}
+  auto active = [&](int k, int m) { return k == 0 || P.kappa[(size_t)(k + 1) * nf + m] != 0.0; };
+  // algorithmic bytes of one pass: read W^n, W^{n-1} (none on the first
+  // step), write the new fields, forcing and c^2 once, read+write every
+  // accumulator active in the pass once (write only on the first step)
+  auto op_bytes = [&](const Op& op) {
+    const int ns = op.kind == 2 ? 2 : 1;
+    const bool first = op.n == 0;
+    int nact = 0;
+    for (int m = 0; m < nf; ++m) {
+      bool on = false;
+      for (int k = 0; k < ns; ++k) on = on || active(op.n + k, m);
+      nact += on ? 1 : 0;
+    }
+    return ((first ? 1 : 2) * sort + ns * sort + (forcing ? nf * sort : 0) +
+            (first ? 1 : 2) * 8.0 * nact + (pr.varc ? sort : 0)) * npts;
+  };
+  auto launch_op = [&](const Op& op, hipStream_t s) -> hipError_t {
+    const int n = op.n;
+    if (op.kind == 0) {
+      const bool first = n == 0;
+      a.wc = op.wc;
+      a.wp = op.wp;
+      a.wout = op.w1;
+      a.first = first ? 1 : 0;
+      a.cA = first ? T(1) : T(2);
+      a.cB = first ? T(0) : T(-1);
+      a.cC = (T)(first ? 0.5 * dt2 : dt2);
+      int mask = 0;
+      for (int m = 0; m < MFWH_MAX_NF; ++m) {
+        if (m < nf) {
+          a.phi[m] = forcing ? (T)P.phi[(size_t)n * nf + m] : T(0);
+          a.kap[m] = P.kappa[(size_t)(n + 1) * nf + m];
+          a.kap0[m] = first ? P.kappa[m] : 0.0;
+          if (first || a.kap[m] != 0.0) mask |= 1 << m;
+        } else {
+          a.phi[m] = T(0);
+          a.kap[m] = a.kap0[m] = 0.0;
+        }
+      }
+      a.mask = mask;
+      return launch_step<T>(a, pr.grid->order, nf, *ls, s);
+    }
+    const int ns = op.kind;
+    la.wc = op.wc;
+    la.wp = op.wp;
+    la.w1 = op.w1;
+    la.w2 = op.w2;
+    la.cA = T(2);
+    la.cB = T(-1);
+    la.cC = (T)dt2;
+    int nq = 0;
+    for (int m = 0; m < MFWH_MAX_NF; ++m) {
+      la.phi1[m] = (forcing && m < nf) ? (T)P.phi[(size_t)n * nf + m] : T(0);
+      la.phi2[m] = (forcing && m < nf && ns == 2) ? (T)P.phi[(size_t)(n + 1) * nf + m] : T(0);
+      la.k1[m] = la.k2[m] = 0.0;
+      la.qm[m] = 0;
+    }
+    for (int m = 0; m < nf; ++m) {
+      const bool on1 = active(n, m), on2 = ns == 2 && active(n + 1, m);
+      if (!on1 && !on2) continue;
+      la.qm[nq] = m;
+      la.k1[nq] = P.kappa[(size_t)(n + 1) * nf + m];
+      la.k2[nq] = ns == 2 ? P.kappa[(size_t)(n + 2) * nf + m] : 0.0;
+      ++nq;
+    }
+    la.nq = nq;
+    // unused slots repeat the last used accumulator (the kernels load every
+    // slot unconditionally and store only the first nq)
+    for (int j = nq; j < MFWH_MAX_NF; ++j) la.qm[j] = nq > 0 ? la.qm[nq - 1] : 0;
+    return launch_leap2d<T>(la, pr.grid->order, ns, pr.leap, s);
+  };
+  double bytes_all = 0.0;          // algorithmic bytes of the whole sequence
+  for (const Op& op : ops) bytes_all += op_bytes(op);
   Stats& st = stats();
   if (pr.graphs) {
     StepGraph& sg = pr.sg[sizeof(T) == 4 ? 1 : 0][forcing ? 1 : 0];
@@ -339,25 +451,12 @@ int apply_t(Problem& pr, const double* v, ExtLayout vl, bool forcing, const Out&
       hipStream_t cs;
       HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
       hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed);
-      for (int n = 0; n < P.nt && e == hipSuccess; ++n) {
-        double b;
-        e = step(n, cs, &b);
-      }
+      for (size_t k = 0; k < ops.size() && e == hipSuccess; ++k) e = launch_op(ops[k], cs);
       hipError_t e2 = hipStreamEndCapture(cs, &sg.g);
       (void)hipStreamDestroy(cs);
       HIPCHK(e);
       HIPCHK(e2);
       HIPCHK(hipGraphInstantiate(&sg.x, sg.g, nullptr, nullptr, 0));
-    }
-    for (int n = 0; n < P.nt; ++n) {        // bytes of the sequence (host only)
-      double b = 0.0;
-      const bool first = n == 0;
-      int nact = 0;
-      for (int m = 0; m < nf; ++m)
-        if (first || P.kappa[(size_t)(n + 1) * nf + m] != 0.0) ++nact;
-      b = ((first ? 2 : 3) * sort + (forcing ? nf * sort : 0) + (first ? 1 : 2) * 8.0 * nact +
-           (pr.varc ? sort : 0)) * (double)pr.G.npts();
-      bytes_all += b;
     }
     bool timed = false;
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -375,10 +474,10 @@ int apply_t(Problem& pr, const double* v, ExtLayout vl, bool forcing, const Out&
       std::lock_guard<std::mutex> lk(st.mu);
       st.pending.emplace_back(e0, e1);
       st.pending_bytes.push_back(bytes_all);
-      st.pending_count.push_back(P.nt);
+      st.pending_count.push_back((int)ops.size());
     }
   } else {
-    for (int n = 0; n < P.nt; ++n) {
+    for (const Op& op : ops) {
       bool timed = false;
       hipEvent_t e0 = nullptr, e1 = nullptr;
       if (st.on) {
@@ -390,13 +489,12 @@ int apply_t(Problem& pr, const double* v, ExtLayout vl, bool forcing, const Out&
           }
         }
       }
-      double b;
-      HIPCHK(step(n, pr.s, &b));
+      HIPCHK(launch_op(op, pr.s));
       if (timed) {
         HIPCHK(hipEventRecord(e1, pr.s));
         std::lock_guard<std::mutex> lk(st.mu);
         st.pending.emplace_back(e0, e1);
-        st.pending_bytes.push_back(b);
+        st.pending_bytes.push_back(op_bytes(op));
         st.pending_count.push_back(1);
       }
     }
@@ -1013,6 +1111,9 @@ int mfwh_solve_gmres(const mfwh_grid* g, const mfwh_time* t, const double* f, do
     info->outer = outer;
     info->rel_residual = relres;
     info->point_steps = pr.point_steps;
+    info->fell_back = fell_back;
+    info->initial_rel_residual = init_rel;
+    info->initial_scale = init_scale;
   }
   return status;
 }
@@ -1302,6 +1403,10 @@ int mfwh_set_option(int key, long long value) {
   switch (key) {
     case MFWH_OPT_GRAPHS:
       g_graphs = value != 0;
+      return MFWH_OK;
+    case MFWH_OPT_STEPS_PER_PASS:
+      if (value < 0 || value > 2) return fail(MFWH_EINVAL, "steps per pass must be 0, 1 or 2");
+      g_steps_per_pass = (int)value;
       return MFWH_OK;
     default:
       return fail(MFWH_EINVAL, "unknown option");

@@ -82,6 +82,40 @@ struct LaunchShape {
   int chunk = 8;    // rows (2D) / planes (3D) marched per block
 };
 
+// Arguments of the streamlined 2D leapfrog kernels (every step after the
+// first).  One launch advances one step (W^n, W^{n-1} -> W^{n+1}) or two
+// (-> W^{n+1}, W^{n+2}); per step
+//   W^{k+1} = cA W^k + cB W^{k-1} + cC (c^2 Delta_h W^k - sum_m phi_m f_m)
+// and, for the nq active accumulators (compact slot j -> field qm[j]),
+//   q_{qm[j]} += k1[j] W^{n+1} (+ k2[j] W^{n+2}).
+template <typename T>
+struct LeapArgs {
+  const T* wc;          // W^n
+  const T* wp;          // W^{n-1}
+  T* w1;                // W^{n+1} (may alias wp for one step, never for two)
+  T* w2;                // W^{n+2} (two steps only)
+  const T* c2;          // c^2 or nullptr
+  const T* f;           // forcing fields or nullptr
+  double* q;
+  Geom g;
+  T wx[3], wy[3];
+  T cA, cB, cC;
+  T phi1[MFWH_MAX_NF], phi2[MFWH_MAX_NF];
+  double k1[MFWH_MAX_NF], k2[MFWH_MAX_NF];
+  int qm[MFWH_MAX_NF];  // slots nq.. repeat slot nq-1 (they are loaded, never stored)
+  int nq;               // active accumulators
+  int force;
+  int chunk, nchunk, ntx, nblocks;
+};
+
+// Launch one streamlined 2D step (steps == 1) or two fused steps
+// (steps == 2) with shape ls (bx in {64, 128, 256}); fills the tiling fields.
+template <typename T>
+hipError_t launch_leap2d(LeapArgs<T>& a, int order, int steps, const LaunchShape& ls,
+                         hipStream_t s);
+// Default launch shapes of the streamlined kernels.
+LaunchShape default_leap_shape(const Geom& g, int steps);
+
 // kernels.hip
 template <typename T>
 hipError_t launch_step(const StepArgs<T>& a, int order, int nf, const LaunchShape& ls,

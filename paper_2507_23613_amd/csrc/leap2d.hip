@@ -1,0 +1,397 @@
+// Streamlined 2D leapfrog + filter kernels for every step after the first.
+//
+// Same arithmetic as the general step kernel (Section 6, eqs. WaveScheme and
+// pDefQ: W^{n+1} = 2W^n - W^{n-1} + dt^2 (c^2 Delta_h W^n - F^n), then
+// q_m += kappa_{n+1,m} W^{n+1}), organised for memory-level parallelism:
+//  * no global load sits behind a branch on loaded data: a value outside the
+//    interior is read from a clamped source index and multiplied by a sign
+//    (1 inside, -1 for the order-4 odd-reflection ghost, 0 on the Dirichlet
+//    boundary and beyond);
+//  * the operands of row y+1 are loaded before row y is computed (software
+//    pipelining one row ahead), so a wave keeps a whole row of loads in
+//    flight while it computes;
+//  * the active filter accumulators come as a compact list (slot j updates
+//    accumulator qm[j]); their number is bounded by the template parameter QM
+//    so only QM float64 values per point live in registers.
+//
+// Two-step variant (temporal blocking): one pass advances W^n -> W^{n+1} ->
+// W^{n+2}.  A block of BX lanes owns BX - 4R columns; lane l sits on column
+// x0 - 2R + l.  W^{n+1} is computed on the owned columns plus an R-wide halo
+// on each side (lanes R .. BX-R-1) and on the owned rows plus R rows beyond
+// each end of the chunk, so the second step needs nothing from other blocks.
+// Every filter accumulator is read and written once for both steps, which
+// halves the accumulator traffic (64 of the 88 bytes of a forcing-free
+// point-step with four filters).  The outputs W^{n+1}, W^{n+2} go to two
+// buffers distinct from the inputs, since neighbouring blocks read input
+// halos throughout the launch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "kernels.h"
+
+namespace mfwh {
+
+namespace {
+
+__device__ __forceinline__ int xcd_tile(int b, int grid) {
+  const int per = grid >> 3;               // grid is a multiple of 8
+  return (b & 7) * per + (b >> 3);
+}
+
+inline int pad8(int n) { return (n + 7) & ~7; }
+
+// Extended-line source of index e on an axis with n interior points: returns
+// the interior index to read and sets the factor applied to it.
+//   0 <= e < n : e, +1      e == -1 or n : 0, 0 (Dirichlet boundary)
+//   e == -2    : 0, -1      e == n+1     : n-1, -1 (odd-reflection ghost)
+//   otherwise  : 0, 0 (never used by a stencil)
+template <typename T>
+__device__ __forceinline__ int ext_src(int e, int n, T& sg) {
+  const bool in = e >= 0 && e < n;
+  const bool ghost = e == -2 || e == n + 1;
+  sg = in ? T(1) : (ghost ? T(-1) : T(0));
+  return in ? e : (e == n + 1 ? n - 1 : 0);
+}
+
+// Operands of one row, loaded one row ahead.  Rows alternate between two
+// register sets, so the wait for a set's loads falls where the set is
+// consumed, one row after it was requested, with the next row's loads
+// already in flight.
+template <typename T, int QM>
+struct Row1 {
+  T w, sw;        // new W^n value of the window and its extension factor
+  T h, sh;        // x-halo value (edge lanes) and its factor
+  T p, c, f;      // W^{n-1}, c^2, forcing
+  double q[QM];
+};
+
+template <typename T, int QM>
+struct Row2 {
+  T w, sw;        // new W^n value of the window and its extension factor
+  T p, c;         // W^{n-1} and c^2 at the first step's row
+  T f1, f2;       // forcing of both steps at the first step's row
+  double q[QM];   // accumulators at the second step's row
+};
+
+// -------------------------------------------------------------------------
+// one step
+// -------------------------------------------------------------------------
+template <typename T, int R, int BX, int QM, bool FORCE>
+__global__ void __launch_bounds__(BX) k_leap2d(LeapArgs<T> a) {
+  __shared__ T row[2][BX + 2 * R];
+  const int lb = xcd_tile(blockIdx.x, gridDim.x);
+  if (lb >= a.nblocks) return;
+  const int bx = lb / a.nchunk;
+  const int by = lb - bx * a.nchunk;
+  const int tid = threadIdx.x;
+  const int nxi = a.g.nxi, nyi = a.g.nyi;
+  const long long py = a.g.py, fs = a.g.fs;
+  const int i = bx * BX + tid;
+  const bool act = i < nxi;
+  T xs;
+  const int ix = ext_src(i, nxi, xs);
+  // lanes 0..R-1 and BX-R..BX-1 also fetch one x-halo value per row
+  const bool hal = tid < R || tid >= BX - R;
+  const int eh = tid < R ? bx * BX - R + tid : bx * BX + R + tid;
+  T hs;
+  const int ih = ext_src(eh, nxi, hs);
+  const int y0 = by * a.chunk;
+  const int y1 = min(y0 + a.chunk, nyi);
+  const T* __restrict__ wc = a.wc;
+  // raw value of W^n at (row y, column col) and its extension factor; the
+  // factor is applied when the value is consumed, so no load is waited for
+  // inside a prefetch
+  auto ldw = [&](int y, int col, T sx, T& sg) -> T {
+    T sy;
+    const int iy = ext_src(y, nyi, sy);
+    sg = sx * sy;
+    return wc[(long long)iy * py + col];
+  };
+
+  T w[2 * R + 1];                         // W^n along y, rows y-R .. y+R
+#pragma unroll
+  for (int k = 0; k < 2 * R; ++k) {
+    T sg;
+    const T v = ldw(y0 - R + k, ix, xs, sg);
+    w[k + 1] = sg * v;
+  }
+
+  // Every load of a fetch is unconditional and in bounds: lanes past the
+  // last column read their clamped column, lanes without an x-halo value
+  // re-read their own column, and unused accumulator slots re-read the last
+  // used one (the host repeats its index), so no load waits on a branch.
+  const int hcol = hal ? ih : ix;
+  const T hsx = hal ? hs : T(0);
+  const T* __restrict__ c2p = a.c2 ? a.c2 : a.wp;    // read and ignored when c = 1
+  auto fetch = [&](Row1<T, QM>& o, int y) {
+    o.w = ldw(y + R, ix, xs, o.sw);
+    o.h = ldw(y, hcol, hsx, o.sh);
+    const long long idx = (long long)y * py + ix;
+    o.p = a.wp[idx];
+    o.c = c2p[idx];
+    o.f = T(0);
+    if (FORCE) {
+#pragma unroll
+      for (int m = 0; m < MFWH_MAX_NF; ++m)
+        if (a.phi1[m] != T(0)) o.f += a.phi1[m] * a.f[m * fs + idx];
+    }
+#pragma unroll
+    for (int j = 0; j < QM; ++j) o.q[j] = a.q[a.qm[j] * fs + idx];
+  };
+  auto process = [&](int y, const Row1<T, QM>& o, T* rb) {
+#pragma unroll
+    for (int k = 0; k < 2 * R; ++k) w[k] = w[k + 1];
+    w[2 * R] = o.sw * o.w;
+    rb[R + tid] = w[R];
+    if (tid < R) rb[tid] = o.sh * o.h;
+    if (tid >= BX - R) rb[tid + 2 * R] = o.sh * o.h;
+    __syncthreads();
+    if (act) {
+      T lap = (a.wx[0] + a.wy[0]) * w[R];
+#pragma unroll
+      for (int k = 1; k <= R; ++k)
+        lap += a.wx[k] * (rb[R + tid - k] + rb[R + tid + k]) + a.wy[k] * (w[R - k] + w[R + k]);
+      const T c2v = a.c2 ? o.c : T(1);
+      const T wn = a.cA * w[R] + a.cB * o.p + a.cC * (c2v * lap - o.f);
+      const long long idx = (long long)y * py + i;
+      a.w1[idx] = wn;
+      const double wd = (double)wn;
+#pragma unroll
+      for (int j = 0; j < QM; ++j)
+        if (j < a.nq) a.q[a.qm[j] * fs + idx] = o.q[j] + a.k1[j] * wd;
+    }
+  };
+
+  // fetches past the last row re-read the last row (valid, unused), which
+  // keeps every fetch unconditional
+  Row1<T, QM> ra, rb;
+  fetch(ra, y0);
+  for (int y = y0;; y += 2) {
+    fetch(rb, min(y + 1, y1 - 1));
+    process(y, ra, row[0]);
+    if (y + 1 >= y1) break;
+    fetch(ra, min(y + 2, y1 - 1));
+    process(y + 1, rb, row[1]);
+    if (y + 2 >= y1) break;
+  }
+}
+
+// -------------------------------------------------------------------------
+// two steps per pass
+// -------------------------------------------------------------------------
+template <typename T, int R, int BX, int QM, bool FORCE>
+__global__ void __launch_bounds__(BX) k_leap2d_x2(LeapArgs<T> a) {
+  constexpr int OW = BX - 4 * R;          // owned columns per block
+  __shared__ T rn[2][BX];                 // W^n row of the first step
+  __shared__ T r1[BX];                    // W^{n+1} row of the second step
+  const int lb = xcd_tile(blockIdx.x, gridDim.x);
+  if (lb >= a.nblocks) return;
+  const int bx = lb / a.nchunk;
+  const int by = lb - bx * a.nchunk;
+  const int l = threadIdx.x;
+  const int nxi = a.g.nxi, nyi = a.g.nyi;
+  const long long py = a.g.py, fs = a.g.fs;
+  const int e = bx * OW - 2 * R + l;      // column of this lane
+  T xs;
+  const int ix = ext_src(e, nxi, xs);
+  const bool inx = e >= 0 && e < nxi;
+  const bool mid = inx && l >= R && l < BX - R;        // computes W^{n+1}
+  const bool own = inx && l >= 2 * R && l < BX - 2 * R;  // computes W^{n+2}
+  const int y0 = by * a.chunk;
+  const int y1 = min(y0 + a.chunk, nyi);
+  const T* __restrict__ wc = a.wc;
+  // raw W^n at row y of this lane's column and its extension factor
+  auto ldw = [&](int y, T& sg) -> T {
+    T sy;
+    const int iy = ext_src(y, nyi, sy);
+    sg = xs * sy;
+    return wc[(long long)iy * py + ix];
+  };
+
+  T wn[2 * R + 1];     // W^n along y: rows r .. r+2R at iteration r
+  T w1[2 * R + 1];     // W^{n+1} along y: rows r-R .. r+R at iteration r
+  T cw[R + 1];         // c^2 of rows r .. r+R
+  T fw[R + 1];         // second-step forcing of rows r .. r+R
+#pragma unroll
+  for (int k = 0; k < 2 * R; ++k) {
+    T sg;
+    const T v = ldw(y0 - 2 * R + k, sg);
+    wn[k + 1] = sg * v;
+  }
+#pragma unroll
+  for (int k = 0; k <= 2 * R; ++k) w1[k] = T(0);
+#pragma unroll
+  for (int k = 0; k <= R; ++k) {
+    cw[k] = T(1);
+    fw[k] = T(0);
+  }
+
+  // Every load of a fetch is unconditional and in bounds: rows and columns
+  // are clamped (lanes and rows whose values are unused re-read a nearby
+  // point of this block), and unused accumulator slots re-read the last used
+  // one (the host repeats its index), so no load waits on a branch.
+  const int x0 = bx * OW;
+  const int qcol = min(max(e, x0), min(x0 + OW, nxi) - 1);   // an owned column
+  const T* __restrict__ c2p = a.c2 ? a.c2 : a.wp;            // read and ignored when c = 1
+  auto fetch = [&](Row2<T, QM>& o, int r) {
+    o.w = ldw(r + 2 * R, o.sw);
+    const int ey = min(max(r + R, 0), nyi - 1);   // row of the first step, clamped
+    const long long i1 = (long long)ey * py + ix;
+    o.p = a.wp[i1];
+    o.c = c2p[i1];
+    o.f1 = o.f2 = T(0);
+    if (FORCE) {
+#pragma unroll
+      for (int m = 0; m < MFWH_MAX_NF; ++m) {
+        if (a.phi1[m] != T(0) || a.phi2[m] != T(0)) {
+          const T fv = a.f[m * fs + i1];
+          if (a.phi1[m] != T(0)) o.f1 += a.phi1[m] * fv;
+          if (a.phi2[m] != T(0)) o.f2 += a.phi2[m] * fv;
+        }
+      }
+    }
+    const long long i2 = (long long)max(r, y0) * py + qcol;
+#pragma unroll
+    for (int j = 0; j < QM; ++j) o.q[j] = a.q[a.qm[j] * fs + i2];
+  };
+  auto process = [&](int r, const Row2<T, QM>& o, T* rb) {
+#pragma unroll
+    for (int k = 0; k < 2 * R; ++k) wn[k] = wn[k + 1];
+    wn[2 * R] = o.sw * o.w;
+#pragma unroll
+    for (int k = 0; k < 2 * R; ++k) w1[k] = w1[k + 1];
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      cw[k] = cw[k + 1];
+      fw[k] = fw[k + 1];
+    }
+    // first step: W^{n+1} on row ey = r + R
+    const int ey = r + R;
+    rb[l] = wn[R];
+    __syncthreads();
+    T v = T(0);
+    if (mid && ey >= 0 && ey < nyi) {
+      T lap = (a.wx[0] + a.wy[0]) * wn[R];
+#pragma unroll
+      for (int k = 1; k <= R; ++k)
+        lap += a.wx[k] * (rb[l - k] + rb[l + k]) + a.wy[k] * (wn[R - k] + wn[R + k]);
+      const T c2v = a.c2 ? o.c : T(1);
+      v = a.cA * wn[R] + a.cB * o.p + a.cC * (c2v * lap - o.f1);
+    }
+    if (R == 2 && ey == nyi + 1) v = -w1[2 * R - 2];   // ghost row: reflects row nyi-1
+    w1[2 * R] = v;
+    if (R == 2 && ey == 0) w1[2 * R - 2] = -v;         // ghost row -2 reflects row 0
+    cw[R] = a.c2 ? o.c : T(1);
+    fw[R] = o.f2;
+
+    // second step: W^{n+2} on row r
+    if (r >= y0) {
+      if (!(R == 2 && (e == -2 || e == nxi + 1))) r1[l] = w1[R];
+      if (R == 2 && e == 0) r1[l - 2] = -w1[R];
+      if (R == 2 && e == nxi - 1 && l + 2 < BX) r1[l + 2] = -w1[R];
+      __syncthreads();
+      if (own) {
+        T lap = (a.wx[0] + a.wy[0]) * w1[R];
+#pragma unroll
+        for (int k = 1; k <= R; ++k)
+          lap += a.wx[k] * (r1[l - k] + r1[l + k]) + a.wy[k] * (w1[R - k] + w1[R + k]);
+        const T v2 = a.cA * w1[R] + a.cB * wn[0] + a.cC * (cw[0] * lap - fw[0]);
+        const long long idx = (long long)r * py + e;
+        a.w1[idx] = w1[R];
+        a.w2[idx] = v2;
+        const double d1 = (double)w1[R], d2 = (double)v2;
+#pragma unroll
+        for (int j = 0; j < QM; ++j)
+          if (j < a.nq) a.q[a.qm[j] * fs + idx] = (o.q[j] + a.k1[j] * d1) + a.k2[j] * d2;
+      }
+    }
+  };
+
+  // fetches past the last row re-read the last row (valid, unused), which
+  // keeps every fetch unconditional
+  Row2<T, QM> ra, rb;
+  fetch(ra, y0 - 2 * R);
+  for (int r = y0 - 2 * R;; r += 2) {
+    fetch(rb, min(r + 1, y1 - 1));
+    process(r, ra, rn[0]);
+    if (r + 1 >= y1) break;
+    fetch(ra, min(r + 2, y1 - 1));
+    process(r + 1, rb, rn[1]);
+    if (r + 2 >= y1) break;
+  }
+}
+
+template <typename T, int R, int BX>
+hipError_t launch_bx(LeapArgs<T>& a, int steps, hipStream_t s) {
+  const Geom& g = a.g;
+  const int ow = steps == 2 ? BX - 4 * R : BX;
+  a.ntx = (g.nxi + ow - 1) / ow;
+  a.nchunk = (g.nyi + a.chunk - 1) / a.chunk;
+  a.nblocks = a.ntx * a.nchunk;
+  const int grid = pad8(a.nblocks);
+  const bool q4 = a.nq <= 4;
+  const bool fo = a.force != 0;
+  if (steps == 2) {
+    if (q4) {
+      if (fo) k_leap2d_x2<T, R, BX, 4, true><<<grid, BX, 0, s>>>(a);
+      else k_leap2d_x2<T, R, BX, 4, false><<<grid, BX, 0, s>>>(a);
+    } else {
+      if (fo) k_leap2d_x2<T, R, BX, 8, true><<<grid, BX, 0, s>>>(a);
+      else k_leap2d_x2<T, R, BX, 8, false><<<grid, BX, 0, s>>>(a);
+    }
+  } else {
+    if (q4) {
+      if (fo) k_leap2d<T, R, BX, 4, true><<<grid, BX, 0, s>>>(a);
+      else k_leap2d<T, R, BX, 4, false><<<grid, BX, 0, s>>>(a);
+    } else {
+      if (fo) k_leap2d<T, R, BX, 8, true><<<grid, BX, 0, s>>>(a);
+      else k_leap2d<T, R, BX, 8, false><<<grid, BX, 0, s>>>(a);
+    }
+  }
+  return hipGetLastError();
+}
+
+template <typename T, int R>
+hipError_t launch_r(LeapArgs<T>& a, int steps, const LaunchShape& ls, hipStream_t s) {
+  switch (ls.bx) {
+    case 64: return launch_bx<T, R, 64>(a, steps, s);
+    case 128: return launch_bx<T, R, 128>(a, steps, s);
+    case 256: return launch_bx<T, R, 256>(a, steps, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+template <typename T>
+hipError_t launch_leap2d(LeapArgs<T>& a, int order, int steps, const LaunchShape& ls,
+                         hipStream_t s) {
+  if (a.g.dim != 2 || (steps != 1 && steps != 2) || a.nq < 0 || a.nq > MFWH_MAX_NF)
+    return hipErrorInvalidValue;
+  if (steps == 2 && (a.w1 == a.wc || a.w1 == a.wp || a.w2 == a.wc || a.w2 == a.wp ||
+                     a.w1 == a.w2 || !a.w2))
+    return hipErrorInvalidValue;
+  a.chunk = std::max(1, ls.chunk);
+  return order == 2 ? launch_r<T, 1>(a, steps, ls, s) : launch_r<T, 2>(a, steps, ls, s);
+}
+template hipError_t launch_leap2d<double>(LeapArgs<double>&, int, int, const LaunchShape&,
+                                          hipStream_t);
+template hipError_t launch_leap2d<float>(LeapArgs<float>&, int, int, const LaunchShape&,
+                                         hipStream_t);
+
+LaunchShape default_leap_shape(const Geom& g, int steps) {
+  LaunchShape ls;
+  ls.by = 1;
+  ls.bx = g.nxi > 512 ? 128 : 64;
+  const int ow = steps == 2 ? ls.bx - 8 : ls.bx;
+  const long long strips = (g.nxi + ow - 1) / ow;
+  const long long waves_per_row = strips * (ls.bx / 64);
+  const long long target_waves = 256LL * 16;
+  long long ch = waves_per_row * g.nyi / target_waves;
+  const long long lo = steps == 2 ? 8 : 4;
+  ls.chunk = (int)std::min<long long>(std::max<long long>(ch, lo), 64);
+  return ls;
+}
+
+}  // namespace mfwh

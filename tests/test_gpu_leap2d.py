@@ -1,0 +1,173 @@
+"""GPU checks of the streamlined 2D step kernels (one step per launch and two
+fused steps per launch) through the C ABI.
+
+Every 2D application runs its first step with the general step kernel and
+the remaining N_t - 1 steps with the kernel MFWH_OPT_STEPS_PER_PASS selects
+(0 general, 1 streamlined, 2 streamlined two-step).  The three evaluate the
+same expressions in the same order, but the compiler fuses multiply-adds
+differently in each kernel, so results differ in the last bits per step
+(measured 1e-14 .. 1.3e-13 relative in float64 after N_t steps and B^{-1};
+about 1e-5 in float32).  Kernel against kernel and each against the oracle
+are therefore held to the parity suite's bars, 1e-12 max(1, cond(B)/10) in
+float64 and max(1e-5, 4 eps32 N_t max(1, cond(B))) in float32; an indexing,
+halo or boundary mistake shows up as an O(1) difference.  Cases cover one
+interior column or row, widths below, at and just past one tile, ragged last
+tiles and chunks, N_t - 1 odd and even (a trailing single step after the
+two-step passes), orders 2 and 4, 1 to 8 filters, variable c, forcing on and
+off, and both precisions.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+from oracle import fd, mfwh as omf, workload  # noqa: E402
+from paper_2507_23613_amd import inputs  # noqa: E402
+
+
+@pytest.fixture(autouse=True)
+def _announce(request):
+    print(f"\n[gpu-case] {request.node.nodeid}", flush=True)
+    sys.stdout.flush()
+    yield
+
+
+def _L():
+    from paper_2507_23613_amd import _lib
+    return _lib
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def rand_v(shape, nf, seed):
+    rng = np.random.default_rng(seed)
+    V = rng.standard_normal((nf,) + tuple(shape))
+    for m in range(nf):
+        fd.zero_boundary(V[m])
+    return V
+
+
+def _apply(w, V, forcing, spp, precision=0, shape=None):
+    from paper_2507_23613_amd.problem import GpuProblem
+    L = _L()
+    try:
+        L.mfwh_set_option(L.MFWH_OPT_STEPS_PER_PASS, spp)
+        if shape:
+            L.mfwh_set_launch_shape(*shape)
+        gp = GpuProblem(w, precision=precision)
+        out = gp.apply(torch.as_tensor(V, device="cuda"), forcing=forcing).cpu().numpy()
+    finally:
+        L.mfwh_set_option(L.MFWH_OPT_STEPS_PER_PASS, 2)
+        L.mfwh_set_launch_shape(0)
+    return out, gp.nt
+
+
+CASES = [
+    dict(seed=2, shape=(3, 3), nf=1, order=4),               # one interior point
+    dict(seed=3, shape=(3, 40), nf=2, order=4),              # one interior row
+    dict(seed=4, shape=(40, 3), nf=2, order=2),              # one interior column
+    dict(seed=5, shape=(30, 58), nf=3, order=4, varc=True),  # 56 columns: one 64-lane two-step tile
+    dict(seed=6, shape=(17, 59), nf=4, order=4),             # 57 columns: two tiles, last holds 1
+    dict(seed=7, shape=(21, 123), nf=5, order=2),            # 121 columns: ragged 128-lane tiles
+    dict(seed=8, shape=(37, 269), nf=8, order=4, varc=True),
+    dict(seed=9, shape=(66, 130), nf=6, order=2, varc=True),
+]
+
+
+def _id(c):
+    return f"{c['shape'][0]}x{c['shape'][1]}-nf{c['nf']}-o{c['order']}{'-varc' if c.get('varc') else ''}"
+
+
+@pytest.mark.parametrize("forcing", [True, False], ids=["forced", "free"])
+@pytest.mark.parametrize("case", CASES, ids=_id)
+def test_steps_per_pass_agree_fp64(case, forcing):
+    w = inputs.small(**case)
+    prob, pl = workload.setup(w)
+    V = rand_v(w["shape"], case["nf"], 31)
+    ref = omf.apply(prob, pl, w["f"], V, forcing)
+    out = {spp: _apply(w, V, forcing, spp)[0] for spp in (0, 1, 2)}
+    bar = 1e-12 * max(1.0, np.linalg.cond(pl.B) / 10)
+    for spp in (1, 2):
+        print(f"steps per pass {spp}: vs general {rel(out[spp], out[0]):.2e}, "
+              f"vs oracle {rel(out[spp], ref):.2e}, bar {bar:.1e}")
+        assert rel(out[spp], out[0]) < bar, spp
+        assert rel(out[spp], ref) < bar, spp
+        for m in range(case["nf"]):
+            assert np.all(out[spp][m] - fd.zero_boundary(out[spp][m].copy()) == 0)
+
+
+@pytest.mark.parametrize("case", CASES[3:6], ids=_id)
+def test_steps_per_pass_agree_fp32(case):
+    w = inputs.small(**case)
+    prob, pl = workload.setup(w)
+    V = rand_v(w["shape"], case["nf"], 32)
+    ref = omf.apply(prob, pl, w["f"], V, True)
+    out = {spp: _apply(w, V, True, spp, precision=1)[0] for spp in (0, 1, 2)}
+    bar = max(1e-5, 4 * 2.0 ** -24 * pl.nt * max(1.0, np.linalg.cond(pl.B)))
+    for spp in (1, 2):
+        print(f"steps per pass {spp}: vs general {rel(out[spp], out[0]):.2e}, "
+              f"vs oracle {rel(out[spp], ref):.2e}, bar {bar:.1e}")
+        assert rel(out[spp], out[0]) < bar, spp
+        assert rel(out[spp], ref) < bar, spp
+
+
+def test_trailing_single_step_both_parities():
+    """N_t - 1 even (only two-step passes) and odd (one trailing single step)."""
+    seen = set()
+    for seed in range(40):
+        w = inputs.small(seed=seed, shape=(19, 70), nf=2, order=4)
+        prob, pl = workload.setup(w)
+        par = (pl.nt - 1) % 2
+        if par in seen:
+            continue
+        seen.add(par)
+        V = rand_v(w["shape"], 2, seed)
+        ref = omf.apply(prob, pl, w["f"], V, False)
+        out, nt = _apply(w, V, False, 2)
+        assert nt == pl.nt
+        assert rel(out, ref) < 1e-12 * max(1.0, np.linalg.cond(pl.B) / 10)
+        if len(seen) == 2:
+            break
+    assert seen == {0, 1}
+
+
+SHAPES = [(64, 1, 1), (64, 1, 2), (64, 1, 7), (128, 1, 3), (128, 1, 16), (256, 1, 5),
+          (256, 1, 1000)]
+
+
+@pytest.mark.parametrize("spp", [1, 2])
+@pytest.mark.parametrize("shape", SHAPES, ids=lambda s: f"bx{s[0]}-c{s[2]}")
+def test_streamlined_launch_shapes(shape, spp):
+    w = inputs.small(seed=5, shape=(37, 269), nf=3, order=4, varc=True)
+    prob, pl = workload.setup(w)
+    V = rand_v(w["shape"], 3, 7)
+    ref = omf.apply(prob, pl, w["f"], V, True)
+    out, _ = _apply(w, V, True, spp, shape=shape)
+    assert rel(out, ref) < 1e-12 * max(1.0, np.linalg.cond(pl.B) / 10)
+
+
+def test_two_step_gmres_matches_general_kernel():
+    """A whole GMRES solve (graph-replayed applications) with two-step passes
+    takes the same iterations and reaches the same solution as with the
+    general kernel."""
+    from paper_2507_23613_amd.problem import GpuProblem
+    L = _L()
+    w = inputs.small(seed=11, shape=(45, 51), nf=3, order=4)
+    res = {}
+    for spp in (0, 2):
+        try:
+            L.mfwh_set_option(L.MFWH_OPT_STEPS_PER_PASS, spp)
+            gp = GpuProblem(w, restart=40)
+            v, info = gp.gmres(max_iter=300, tol=1e-11)
+        finally:
+            L.mfwh_set_option(L.MFWH_OPT_STEPS_PER_PASS, 2)
+        res[spp] = (v.cpu().numpy(), info)
+    assert res[0][1]["converged"] and res[2][1]["converged"]
+    assert abs(res[0][1]["iterations"] - res[2][1]["iterations"]) <= 1
+    assert rel(res[2][0], res[0][0]) < 1e-9

@@ -64,4 +64,5 @@ def test_warm_start_gains_and_falls_back():
     _, a = gp.gmres(max_iter=600, tol=1e-8)
     bad = 1e3 * torch.randn((4, n, n), dtype=torch.float64, device="cuda")
     _, b = gp.gmres(v=bad, max_iter=600, tol=1e-8, zero_fallback=1)
+    print(f"zero start {a}\nrejected guess {b}")
     assert b["fell_back"] and b["converged"] and b["iterations"] == a["iterations"]
