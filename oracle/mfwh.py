@@ -15,8 +15,21 @@ the explicit scheme alpha = 0, beta = 1):
 
 The result on boundary points is zero.  "forcing off" drops F (the linear
 part S of the affine map, Section 7).
+
+Implicit scheme (plan.alpha > 0; the trapezoid method alpha = 1/2,
+beta = 1 - 2 alpha = 0), eq. WaveSchemeA solved for W^{n+1}:
+
+  M W^{n+1} = 2 W^n - W^{n-1} + dt^2 (beta L W^n + alpha L W^{n-1} - F^n)
+  M W^1     = W^0 + (beta/2) dt^2 L W^0 - (dt^2/2) F^0   (eq. implicitFirstStep)
+  M = I - alpha dt^2 L_ph on the interior unknowns (Dirichlet, g = 0)
+  F^n = sum_m f_m cos(omega~_m t^n) (beta + 2 alpha cos(omega~_m dt))
+                                                   (eq. WaveSchemeForcing)
+
+Each M-solve is a sparse LU solve (one factorisation per plan).
 """
 import numpy as np
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
 
 from . import fd
 
@@ -37,8 +50,53 @@ class Problem:
         return lap if self.c2 is None else self.c2 * lap
 
 
+def implicit_solver(prob, plan):
+    """Solver for M x = r, M = I - alpha dt^2 L_ph on the interior unknowns:
+    takes and returns full-grid arrays (boundary of the result zero)."""
+    L = fd.laplacian_matrix(prob.shape, prob.h, prob.order)
+    if prob.c2 is not None:
+        L = sp.diags(fd.interior(prob.c2).ravel()) @ L
+    M = sp.identity(L.shape[0], format="csc") - plan.alpha * plan.dt ** 2 * L
+    lu = spla.splu(M.tocsc())
+    ni = [s - 2 for s in prob.shape]
+
+    def solve(r):
+        x = lu.solve(fd.interior(r).ravel())
+        return fd.embed(x.reshape(ni), prob.shape)
+    return solve
+
+
+def _implicit_history(prob, plan, f, V, forcing):
+    """W^0 .. W^{N_t} of the implicit scheme (module doc)."""
+    alpha = plan.alpha
+    beta = 1.0 - 2.0 * alpha
+    dt2 = plan.dt ** 2
+    solve = implicit_solver(prob, plan)
+    W0 = fd.zero_boundary(np.sum(np.asarray(V, dtype=np.float64), axis=0))
+    f = np.asarray(f, dtype=np.float64)
+    fac = beta + 2.0 * alpha * np.cos(plan.omega_t * plan.dt)
+
+    def F(n):
+        if not forcing:
+            return 0.0
+        return np.tensordot(plan.phi[n] * fac, f, axes=(0, 0))
+
+    yield W0
+    W1 = solve(W0 + 0.5 * beta * dt2 * prob.L(W0) - 0.5 * dt2 * F(0))
+    yield W1
+    for n in range(1, plan.nt):
+        rhs = 2.0 * W1 - W0 + dt2 * (beta * prob.L(W1) + alpha * prob.L(W0) - F(n))
+        W2 = solve(rhs)
+        yield W2
+        W0, W1 = W1, W2
+
+
 def wave_history(prob, plan, f, V, forcing=True):
-    """Yield W^0, W^1, ..., W^{N_t} of the explicit scheme (see module doc)."""
+    """Yield W^0, W^1, ..., W^{N_t} of the scheme the plan was made for
+    (explicit leapfrog when plan.alpha == 0; see module doc)."""
+    if getattr(plan, "alpha", 0.0) > 0.0:
+        yield from _implicit_history(prob, plan, f, V, forcing)
+        return
     dt2 = plan.dt ** 2
     W0 = fd.zero_boundary(np.sum(np.asarray(V, dtype=np.float64), axis=0))
     f = np.asarray(f, dtype=np.float64)
