@@ -77,7 +77,7 @@ struct Row2 {
 // -------------------------------------------------------------------------
 // one step
 // -------------------------------------------------------------------------
-template <typename T, int R, int BX, int QM, bool FORCE>
+template <typename T, int R, int BX, int QM, bool FORCE, int PD>
 __global__ void __launch_bounds__(BX) k_leap2d(LeapArgs<T> a) {
   __shared__ T row[2][BX + 2 * R];
   const int lb = xcd_tile(blockIdx.x, gridDim.x);
@@ -163,28 +163,31 @@ __global__ void __launch_bounds__(BX) k_leap2d(LeapArgs<T> a) {
     }
   };
 
-  // fetches past the last row re-read the last row (valid, unused), which
-  // keeps every fetch unconditional
-  Row1<T, QM> ra, rb;
-  fetch(ra, y0);
-  for (int y = y0;; y += 2) {
-    fetch(rb, min(y + 1, y1 - 1));
-    process(y, ra, row[0]);
-    if (y + 1 >= y1) break;
-    fetch(ra, min(y + 2, y1 - 1));
-    process(y + 1, rb, row[1]);
-    if (y + 2 >= y1) break;
+  // PD register sets rotate: the operands of row y + PD - 1 are requested
+  // before row y is computed.  Fetches past the last row re-read the last
+  // row (valid, unused), which keeps every fetch unconditional.  PD is even,
+  // so a row's LDS buffer parity is that of its set.
+  Row1<T, QM> rs[PD];
+#pragma unroll
+  for (int u = 0; u < PD - 1; ++u) fetch(rs[u], min(y0 + u, y1 - 1));
+  for (int y = y0; y < y1; y += PD) {
+#pragma unroll
+    for (int u = 0; u < PD; ++u) {
+      if (y + u >= y1) break;
+      fetch(rs[(u + PD - 1) % PD], min(y + u + PD - 1, y1 - 1));
+      process(y + u, rs[u], row[u & 1]);
+    }
   }
 }
 
 // -------------------------------------------------------------------------
 // two steps per pass
 // -------------------------------------------------------------------------
-template <typename T, int R, int BX, int QM, bool FORCE>
+template <typename T, int R, int BX, int QM, bool FORCE, int PD, int CH>
 __global__ void __launch_bounds__(BX) k_leap2d_x2(LeapArgs<T> a) {
   constexpr int OW = BX - 4 * R;          // owned columns per block
   __shared__ T rn[2][BX];                 // W^n row of the first step
-  __shared__ T r1[BX];                    // W^{n+1} row of the second step
+  __shared__ T r1[2][BX];                 // W^{n+1} row of the second step
   const int lb = xcd_tile(blockIdx.x, gridDim.x);
   if (lb >= a.nblocks) return;
   const int bx = lb / a.nchunk;
@@ -255,7 +258,11 @@ __global__ void __launch_bounds__(BX) k_leap2d_x2(LeapArgs<T> a) {
 #pragma unroll
     for (int j = 0; j < QM; ++j) o.q[j] = a.q[a.qm[j] * fs + i2];
   };
-  auto process = [&](int r, const Row2<T, QM>& o, T* rb) {
+  // One iteration: the first step on row r + R, the second on row r.  Both
+  // x-neighbour rows are known when the iteration starts (W^n row r + R
+  // arrived with the window, W^{n+1} row r was computed R iterations ago),
+  // so both go to LDS before the iteration's single barrier.
+  auto process = [&](int r, const Row2<T, QM>& o, T* rb, T* r1b) {
 #pragma unroll
     for (int k = 0; k < 2 * R; ++k) wn[k] = wn[k + 1];
     wn[2 * R] = o.sw * o.w;
@@ -266,10 +273,15 @@ __global__ void __launch_bounds__(BX) k_leap2d_x2(LeapArgs<T> a) {
       cw[k] = cw[k + 1];
       fw[k] = fw[k + 1];
     }
+    rb[l] = wn[R];
+    // W^{n+1} row r with its x-extension: 0 on the boundary columns, the
+    // odd-reflection ghost columns written by the lanes they mirror
+    if (!(R == 2 && (e == -2 || e == nxi + 1))) r1b[l] = w1[R];
+    if (R == 2 && e == 0) r1b[l - 2] = -w1[R];
+    if (R == 2 && e == nxi - 1 && l + 2 < BX) r1b[l + 2] = -w1[R];
+    __syncthreads();
     // first step: W^{n+1} on row ey = r + R
     const int ey = r + R;
-    rb[l] = wn[R];
-    __syncthreads();
     T v = T(0);
     if (mid && ey >= 0 && ey < nyi) {
       T lap = (a.wx[0] + a.wy[0]) * wn[R];
@@ -286,78 +298,113 @@ __global__ void __launch_bounds__(BX) k_leap2d_x2(LeapArgs<T> a) {
     fw[R] = o.f2;
 
     // second step: W^{n+2} on row r
-    if (r >= y0) {
-      if (!(R == 2 && (e == -2 || e == nxi + 1))) r1[l] = w1[R];
-      if (R == 2 && e == 0) r1[l - 2] = -w1[R];
-      if (R == 2 && e == nxi - 1 && l + 2 < BX) r1[l + 2] = -w1[R];
-      __syncthreads();
-      if (own) {
-        T lap = (a.wx[0] + a.wy[0]) * w1[R];
+    if (r >= y0 && own) {
+      T lap = (a.wx[0] + a.wy[0]) * w1[R];
 #pragma unroll
-        for (int k = 1; k <= R; ++k)
-          lap += a.wx[k] * (r1[l - k] + r1[l + k]) + a.wy[k] * (w1[R - k] + w1[R + k]);
-        const T v2 = a.cA * w1[R] + a.cB * wn[0] + a.cC * (cw[0] * lap - fw[0]);
-        const long long idx = (long long)r * py + e;
-        a.w1[idx] = w1[R];
-        a.w2[idx] = v2;
-        const double d1 = (double)w1[R], d2 = (double)v2;
+      for (int k = 1; k <= R; ++k)
+        lap += a.wx[k] * (r1b[l - k] + r1b[l + k]) + a.wy[k] * (w1[R - k] + w1[R + k]);
+      const T v2 = a.cA * w1[R] + a.cB * wn[0] + a.cC * (cw[0] * lap - fw[0]);
+      const long long idx = (long long)r * py + e;
+      a.w1[idx] = w1[R];
+      a.w2[idx] = v2;
+      const double d1 = (double)w1[R], d2 = (double)v2;
 #pragma unroll
-        for (int j = 0; j < QM; ++j)
-          if (j < a.nq) a.q[a.qm[j] * fs + idx] = (o.q[j] + a.k1[j] * d1) + a.k2[j] * d2;
-      }
+      for (int j = 0; j < QM; ++j)
+        if (j < a.nq) a.q[a.qm[j] * fs + idx] = (o.q[j] + a.k1[j] * d1) + a.k2[j] * d2;
     }
   };
 
-  // fetches past the last row re-read the last row (valid, unused), which
-  // keeps every fetch unconditional
-  Row2<T, QM> ra, rb;
-  fetch(ra, y0 - 2 * R);
-  for (int r = y0 - 2 * R;; r += 2) {
-    fetch(rb, min(r + 1, y1 - 1));
-    process(r, ra, rn[0]);
-    if (r + 1 >= y1) break;
-    fetch(ra, min(r + 2, y1 - 1));
-    process(r + 1, rb, rn[1]);
-    if (r + 2 >= y1) break;
+  // PD register sets rotate: the operands of row r + PD - 1 are requested
+  // before row r is computed.  Fetches past the last row re-read the last
+  // row (valid, unused), which keeps every fetch unconditional.  PD is even,
+  // so a row's LDS buffer parity is that of its set.
+  const int r0 = y0 - 2 * R;
+  Row2<T, QM> rs[PD];
+#pragma unroll
+  for (int u = 0; u < PD - 1; ++u) fetch(rs[u], min(r0 + u, y1 - 1));
+  if constexpr (CH > 0) {
+    // chunk fixed at compile time: the whole march is straight-line code,
+    // so no loop back-edge forces the in-flight prefetches to complete
+#pragma unroll
+    for (int it = 0; it < CH + 2 * R; ++it) {
+      if (r0 + it >= y1) break;
+      fetch(rs[(it + PD - 1) % PD], min(r0 + it + PD - 1, y1 - 1));
+      process(r0 + it, rs[it % PD], rn[it & 1], r1[it & 1]);
+    }
+  } else {
+    for (int r = r0; r < y1; r += PD) {
+#pragma unroll
+      for (int u = 0; u < PD; ++u) {
+        if (r + u >= y1) break;
+        fetch(rs[(u + PD - 1) % PD], min(r + u + PD - 1, y1 - 1));
+        process(r + u, rs[u], rn[u & 1], r1[u & 1]);
+      }
+    }
   }
 }
 
+template <typename T, int R, int BX, int PD>
+hipError_t launch_pd(LeapArgs<T>& a, int steps, int grid, hipStream_t s) {
+  const bool q4 = a.nq <= 4;
+  const bool fo = a.force != 0;
+  if (steps == 2) {
+    // forcing-free passes (every matvec) with a chunk of 4, 8 or 16 rows run
+    // the fully unrolled march
+    if constexpr (PD == 4 && BX <= 128) {
+      if (!fo && (a.chunk == 4 || a.chunk == 8 || a.chunk == 16)) {
+        if (q4) {
+          if (a.chunk == 4) k_leap2d_x2<T, R, BX, 4, false, PD, 4><<<grid, BX, 0, s>>>(a);
+          else if (a.chunk == 8) k_leap2d_x2<T, R, BX, 4, false, PD, 8><<<grid, BX, 0, s>>>(a);
+          else k_leap2d_x2<T, R, BX, 4, false, PD, 16><<<grid, BX, 0, s>>>(a);
+        } else {
+          if (a.chunk == 4) k_leap2d_x2<T, R, BX, 8, false, PD, 4><<<grid, BX, 0, s>>>(a);
+          else if (a.chunk == 8) k_leap2d_x2<T, R, BX, 8, false, PD, 8><<<grid, BX, 0, s>>>(a);
+          else k_leap2d_x2<T, R, BX, 8, false, PD, 16><<<grid, BX, 0, s>>>(a);
+        }
+        return hipGetLastError();
+      }
+    }
+    if (q4) {
+      if (fo) k_leap2d_x2<T, R, BX, 4, true, PD, 0><<<grid, BX, 0, s>>>(a);
+      else k_leap2d_x2<T, R, BX, 4, false, PD, 0><<<grid, BX, 0, s>>>(a);
+    } else {
+      if (fo) k_leap2d_x2<T, R, BX, 8, true, PD, 0><<<grid, BX, 0, s>>>(a);
+      else k_leap2d_x2<T, R, BX, 8, false, PD, 0><<<grid, BX, 0, s>>>(a);
+    }
+  } else {
+    if (q4) {
+      if (fo) k_leap2d<T, R, BX, 4, true, PD><<<grid, BX, 0, s>>>(a);
+      else k_leap2d<T, R, BX, 4, false, PD><<<grid, BX, 0, s>>>(a);
+    } else {
+      if (fo) k_leap2d<T, R, BX, 8, true, PD><<<grid, BX, 0, s>>>(a);
+      else k_leap2d<T, R, BX, 8, false, PD><<<grid, BX, 0, s>>>(a);
+    }
+  }
+  return hipGetLastError();
+}
+
 template <typename T, int R, int BX>
-hipError_t launch_bx(LeapArgs<T>& a, int steps, hipStream_t s) {
+hipError_t launch_bx(LeapArgs<T>& a, int steps, int depth, hipStream_t s) {
   const Geom& g = a.g;
   const int ow = steps == 2 ? BX - 4 * R : BX;
   a.ntx = (g.nxi + ow - 1) / ow;
   a.nchunk = (g.nyi + a.chunk - 1) / a.chunk;
   a.nblocks = a.ntx * a.nchunk;
   const int grid = pad8(a.nblocks);
-  const bool q4 = a.nq <= 4;
-  const bool fo = a.force != 0;
-  if (steps == 2) {
-    if (q4) {
-      if (fo) k_leap2d_x2<T, R, BX, 4, true><<<grid, BX, 0, s>>>(a);
-      else k_leap2d_x2<T, R, BX, 4, false><<<grid, BX, 0, s>>>(a);
-    } else {
-      if (fo) k_leap2d_x2<T, R, BX, 8, true><<<grid, BX, 0, s>>>(a);
-      else k_leap2d_x2<T, R, BX, 8, false><<<grid, BX, 0, s>>>(a);
-    }
-  } else {
-    if (q4) {
-      if (fo) k_leap2d<T, R, BX, 4, true><<<grid, BX, 0, s>>>(a);
-      else k_leap2d<T, R, BX, 4, false><<<grid, BX, 0, s>>>(a);
-    } else {
-      if (fo) k_leap2d<T, R, BX, 8, true><<<grid, BX, 0, s>>>(a);
-      else k_leap2d<T, R, BX, 8, false><<<grid, BX, 0, s>>>(a);
-    }
+  switch (depth) {
+    case 2: return launch_pd<T, R, BX, 2>(a, steps, grid, s);
+    case 4: return launch_pd<T, R, BX, 4>(a, steps, grid, s);
+    default: return hipErrorInvalidValue;
   }
-  return hipGetLastError();
 }
 
 template <typename T, int R>
-hipError_t launch_r(LeapArgs<T>& a, int steps, const LaunchShape& ls, hipStream_t s) {
+hipError_t launch_r(LeapArgs<T>& a, int steps, int depth, const LaunchShape& ls,
+                    hipStream_t s) {
   switch (ls.bx) {
-    case 64: return launch_bx<T, R, 64>(a, steps, s);
-    case 128: return launch_bx<T, R, 128>(a, steps, s);
-    case 256: return launch_bx<T, R, 256>(a, steps, s);
+    case 64: return launch_bx<T, R, 64>(a, steps, depth, s);
+    case 128: return launch_bx<T, R, 128>(a, steps, depth, s);
+    case 256: return launch_bx<T, R, 256>(a, steps, depth, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -365,7 +412,7 @@ hipError_t launch_r(LeapArgs<T>& a, int steps, const LaunchShape& ls, hipStream_
 }  // namespace
 
 template <typename T>
-hipError_t launch_leap2d(LeapArgs<T>& a, int order, int steps, const LaunchShape& ls,
+hipError_t launch_leap2d(LeapArgs<T>& a, int order, int steps, int depth, const LaunchShape& ls,
                          hipStream_t s) {
   if (a.g.dim != 2 || (steps != 1 && steps != 2) || a.nq < 0 || a.nq > MFWH_MAX_NF)
     return hipErrorInvalidValue;
@@ -373,11 +420,12 @@ hipError_t launch_leap2d(LeapArgs<T>& a, int order, int steps, const LaunchShape
                      a.w1 == a.w2 || !a.w2))
     return hipErrorInvalidValue;
   a.chunk = std::max(1, ls.chunk);
-  return order == 2 ? launch_r<T, 1>(a, steps, ls, s) : launch_r<T, 2>(a, steps, ls, s);
+  return order == 2 ? launch_r<T, 1>(a, steps, depth, ls, s)
+                    : launch_r<T, 2>(a, steps, depth, ls, s);
 }
-template hipError_t launch_leap2d<double>(LeapArgs<double>&, int, int, const LaunchShape&,
+template hipError_t launch_leap2d<double>(LeapArgs<double>&, int, int, int, const LaunchShape&,
                                           hipStream_t);
-template hipError_t launch_leap2d<float>(LeapArgs<float>&, int, int, const LaunchShape&,
+template hipError_t launch_leap2d<float>(LeapArgs<float>&, int, int, int, const LaunchShape&,
                                          hipStream_t);
 
 LaunchShape default_leap_shape(const Geom& g, int steps) {
@@ -389,8 +437,7 @@ LaunchShape default_leap_shape(const Geom& g, int steps) {
   const long long waves_per_row = strips * (ls.bx / 64);
   const long long target_waves = 256LL * 16;
   long long ch = waves_per_row * g.nyi / target_waves;
-  const long long lo = steps == 2 ? 8 : 4;
-  ls.chunk = (int)std::min<long long>(std::max<long long>(ch, lo), 64);
+  ls.chunk = (int)std::min<long long>(std::max<long long>(ch, 4), 64);
   return ls;
 }
 

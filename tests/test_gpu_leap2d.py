@@ -53,17 +53,19 @@ def rand_v(shape, nf, seed):
     return V
 
 
-def _apply(w, V, forcing, spp, precision=0, shape=None):
+def _apply(w, V, forcing, spp, precision=0, shape=None, depth=4):
     from paper_2507_23613_amd.problem import GpuProblem
     L = _L()
     try:
         L.mfwh_set_option(L.MFWH_OPT_STEPS_PER_PASS, spp)
+        L.mfwh_set_option(L.MFWH_OPT_PREFETCH_DEPTH, depth)
         if shape:
             L.mfwh_set_launch_shape(*shape)
         gp = GpuProblem(w, precision=precision)
         out = gp.apply(torch.as_tensor(V, device="cuda"), forcing=forcing).cpu().numpy()
     finally:
         L.mfwh_set_option(L.MFWH_OPT_STEPS_PER_PASS, 2)
+        L.mfwh_set_option(L.MFWH_OPT_PREFETCH_DEPTH, 4)
         L.mfwh_set_launch_shape(0)
     return out, gp.nt
 
@@ -137,18 +139,22 @@ def test_trailing_single_step_both_parities():
     assert seen == {0, 1}
 
 
-SHAPES = [(64, 1, 1), (64, 1, 2), (64, 1, 7), (128, 1, 3), (128, 1, 16), (256, 1, 5),
-          (256, 1, 1000)]
+# chunks 4, 8 and 16 with bx <= 128 and depth 4 select the fully unrolled
+# two-step march for forcing-free passes; the others the looped one
+SHAPES = [(64, 1, 1), (64, 1, 2), (64, 1, 4), (64, 1, 7), (64, 1, 8), (128, 1, 3),
+          (128, 1, 8), (128, 1, 16), (256, 1, 5), (256, 1, 1000)]
 
 
+@pytest.mark.parametrize("forcing", [True, False], ids=["forced", "free"])
+@pytest.mark.parametrize("depth", [2, 4])
 @pytest.mark.parametrize("spp", [1, 2])
 @pytest.mark.parametrize("shape", SHAPES, ids=lambda s: f"bx{s[0]}-c{s[2]}")
-def test_streamlined_launch_shapes(shape, spp):
+def test_streamlined_launch_shapes(shape, spp, depth, forcing):
     w = inputs.small(seed=5, shape=(37, 269), nf=3, order=4, varc=True)
     prob, pl = workload.setup(w)
     V = rand_v(w["shape"], 3, 7)
-    ref = omf.apply(prob, pl, w["f"], V, True)
-    out, _ = _apply(w, V, True, spp, shape=shape)
+    ref = omf.apply(prob, pl, w["f"], V, forcing)
+    out, _ = _apply(w, V, forcing, spp, shape=shape, depth=depth)
     assert rel(out, ref) < 1e-12 * max(1.0, np.linalg.cond(pl.B) / 10)
 
 
