@@ -25,6 +25,7 @@ Extra fields:
     python bench.py --mode copy      # plain copy kernel of known size (counter calibration)
     python bench.py --mode batch     # 64 independent 2D problems solved as one batch
     python bench.py --mode warmstart # learned warm start: data, training, evaluation
+    python bench.py --mode implicit  # implicit scheme + multigrid: O(N) grid study
     python bench.py --mode apply --applies 3   # a few forcing-free float64
                                      # applications of the same workload (for
                                      # rocprofv3: the step kernel as the solver runs it)
@@ -209,13 +210,48 @@ def warmstart_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def implicit_bench(args):
+    """O(N) study of the implicit path: the paper's three-frequency square
+    (omega = 5.1, 10.1, 15.1, N_p = 2, Gaussian sources of eq. Nf3parameters,
+    adjusted traditional filter), order 4, trapezoid stepping with 10 steps
+    per shortest period, multigrid step solves to 1e-10, on grids of 64 to
+    2048 cells per side.  For each grid: FPI wave solves to a residual
+    1e-10 times the first, average V-cycles per step solve, GPU time, and the
+    time ratio to the previous grid (4 for O(N))."""
+    import torch
+    from paper_2507_23613_amd import _lib as L
+    from paper_2507_23613_amd import inputs
+    from paper_2507_23613_amd.problem import GpuProblem
+    rows, prev = [], None
+    for n in (65, 129, 257, 513, 1025, 2049):
+        w = inputs.paper_square128(n)
+        gp = GpuProblem(w, scheme=L.MFWH_IMPLICIT, imp_tol=1e-10, restart=0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, info = gp.fixed_point(max_iter=200, tol=1e-10)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        row = {"cells": n - 1, "points": n * n, "nt": gp.nt, "wave_solves": info["applies"],
+               "fpi_iterations": info["iterations"], "rel_residual": info["rel_residual"],
+               "mg_cycles_per_step": round(info["mg_cycles"] / max(1, info["implicit_solves"]), 2),
+               "gpu_s": round(el, 3), "ratio": round(el / prev, 2) if prev else None,
+               "us_per_point_per_wave_solve": round(1e6 * el / (n * n * info["applies"]), 4)}
+        prev = el
+        rows.append(row)
+        log(json.dumps(row))
+        del gp
+        torch.cuda.empty_cache()
+    print(json.dumps({"mode": "implicit", "scheme": "trapezoid + multigrid V(2,2)",
+                      "rows": rows}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--mode", default="solve",
-                    choices=["solve", "copy", "apply", "batch", "warmstart"])
+                    choices=["solve", "copy", "apply", "batch", "warmstart", "implicit"])
     ap.add_argument("--train", type=int, default=2000)
     ap.add_argument("--test", type=int, default=200)
     ap.add_argument("--epochs", type=int, default=20)
@@ -250,6 +286,9 @@ def main():
         return
     if args.mode == "warmstart":
         warmstart_bench(args)
+        return
+    if args.mode == "implicit":
+        implicit_bench(args)
         return
 
     w = inputs.config2(0, n=args.n)

@@ -54,7 +54,9 @@ typedef enum {
   MFWH_ENT = -5,            /* T/dt is not an integer number of steps >= 2       */
   MFWH_EHIP = -6,           /* a HIP runtime call failed                          */
   MFWH_EWORKSPACE = -7,     /* workspace too small or misaligned                  */
-  MFWH_ENONFINITE = -8      /* a NaN/Inf appeared in a residual                   */
+  MFWH_ENONFINITE = -8,     /* a NaN/Inf appeared in a residual                   */
+  MFWH_ENOTCONV_MG = -9     /* an implicit step's multigrid solve reached
+                               imp_max_cycles above imp_tol                       */
 } mfwh_status;
 
 enum { MFWH_FP64 = 0,          /* wave field, forcing and c^2 in float64            */
@@ -75,6 +77,13 @@ typedef struct mfwh_grid {
   const double* c;    /* device, wave speed at every grid point, or NULL (c = 1)   */
 } mfwh_grid;
 
+/* Time-stepping schemes of Section 6 (eq. WaveSchemeA). */
+enum { MFWH_EXPLICIT = 0,      /* leapfrog, alpha = 0, beta = 1                     */
+       MFWH_IMPLICIT = 1       /* trapezoid, alpha = 1/2, beta = 0: every step solves
+                                  (I - dt^2/2 L_ph) W^{n+1} = rhs with a geometric
+                                  multigrid solver (2D grids, MFWH_FP64 only)       */
+};
+
 /* Frequencies, filter and time grid (Sections 2, 3, 6). */
 typedef struct mfwh_time {
   int nf;                /* number of frequencies, 1..MFWH_MAX_NF                  */
@@ -83,8 +92,15 @@ typedef struct mfwh_time {
                             K(tau) = a + c cos(tau) + s sin(tau) (eq. newFilterKernel),
                             or NULL for the traditional p_0 = (-1/4, 1, 0)          */
   double T;              /* final time T_f of each wave solve                     */
-  double dt;             /* time step; N_t = T/dt must be an integer >= 2 (to 1e-9)
-                            and omega_nf * dt < 2                                   */
+  double dt;             /* time step; N_t = T/dt must be an integer >= 2 (to 1e-9);
+                            explicit: omega_nf * dt < 2 and dt within the leapfrog
+                            stability limit                                         */
+  int scheme;            /* MFWH_EXPLICIT (0) or MFWH_IMPLICIT; omega~ follows the
+                            scheme (eq. omegaImplicit)                              */
+  double imp_tol;        /* MFWH_IMPLICIT: multigrid V-cycles of each step stop when
+                            ||rhs - M W^{n+1}||_2 <= imp_tol ||rhs||_2  [1e-10 if 0] */
+  int imp_max_cycles;    /* MFWH_IMPLICIT: V-cycle limit per step; reaching it
+                            fails the call with MFWH_ENOTCONV_MG      [100 if 0]  */
 } mfwh_time;
 
 /* Solver controls.  A NULL pointer selects the defaults in brackets. */
@@ -114,6 +130,8 @@ typedef struct mfwh_solve_info {
   int fell_back;           /* 1 if zero_fallback rejected the initial guess         */
   double initial_rel_residual; /* ||b - A v0|| / ||b|| of the (scaled) initial guess */
   double initial_scale;    /* alpha applied by scale_initial (1 otherwise)          */
+  long long implicit_solves; /* MFWH_IMPLICIT: step-matrix solves performed          */
+  long long mg_cycles;     /* MFWH_IMPLICIT: multigrid V-cycles over those solves    */
 } mfwh_solve_info;
 
 /* Description of the last error on the calling thread ("" if none). */
@@ -138,7 +156,7 @@ int mfwh_plan_time(const mfwh_grid* g, double cmax, double omega1, int np, doubl
 int mfwh_plan_time_implicit(double omega1, double omega_last, int np, int steps_per_period,
                             double* T, double* dt, int* nt);
 
-/* The plan of one problem (explicit scheme): modified frequencies omega~_m
+/* The plan of one problem (for t->scheme): modified frequencies omega~_m
  * (eq. omegaImplicit), N_{p,m} and T~_{f,m} (eq. TbarDef with omega~), the
  * matrix B[m][j] = beta_{d,m}(omega~_j) (eq. filterA with eq. betadDefA) and
  * its inverse, all row-major.  Any output pointer may be NULL. */
@@ -146,14 +164,17 @@ int mfwh_plan_info(const mfwh_time* t, double* omega_tilde, int* npm, double* tf
                    double* B, double* Binv);
 
 /* Per-step coefficients: kappa[n][m] = (2/T~_{f,m}) sigma_{n,m} K(omega~_m t^n; p_m)
- * (eq. pDefQ with the quadrature of eq. DefNI) and phi[n][m] = cos(omega~_m t^n)
- * (eq. WaveSchemeForcing), n = 0..N_t, host arrays of (N_t+1)*nf doubles. */
+ * (eq. pDefQ with the quadrature of eq. DefNI) and the forcing factor
+ * phi[n][m] = cos(omega~_m t^n) (beta + 2 alpha cos(omega~_m dt)) of eq.
+ * WaveSchemeForcing (= cos(omega~_m t^n) for the explicit scheme), n = 0..N_t,
+ * host arrays of (N_t+1)*nf doubles. */
 int mfwh_plan_coefficients(const mfwh_time* t, double* kappa, double* phi);
 
 /* Traditional parameters adjusted for time discretisation: (a_m, 1, 0) with
- * a_m = -tan(omega~ dt/2) / (2 tan(omega~ dt)) (eq. origParamAdjust).
+ * a_m = -tan(omega~ dt/2) / (2 tan(omega~ dt)) (eq. origParamAdjust), omega~
+ * of `scheme` (MFWH_EXPLICIT or MFWH_IMPLICIT, eq. omegaImplicit).
  * omega: physical frequencies [nf]; filt_out: host [nf][3]. */
-int mfwh_filter_adjusted(int nf, const double* omega, double dt, double* filt_out);
+int mfwh_filter_adjusted(int nf, const double* omega, double dt, int scheme, double* filt_out);
 
 /* Least-squares filter parameters (Section 5, Algorithm 2, with the discrete
  * time quadrature used for the computations of Section 8).  omega_in: the
@@ -329,8 +350,11 @@ int mfwh_set_launch_shape(int bx, int by, int chunk);
  * launch (temporal blocking: W^{n+1} is recomputed on a halo and every filter
  * accumulator is read and written once per two steps).  All three compute
  * the same values up to floating-point contraction; 1D and 3D grids always
- * use the general kernel. */
-enum { MFWH_OPT_GRAPHS = 1, MFWH_OPT_STEPS_PER_PASS = 2 };
+ * use the general kernel.
+ * MFWH_OPT_PREFETCH_DEPTH (2 or 4; default 4): register sets of row operands
+ * a wave of the streamlined 2D kernels rotates through, i.e. it requests the
+ * operands of row y + depth - 1 before computing row y. */
+enum { MFWH_OPT_GRAPHS = 1, MFWH_OPT_STEPS_PER_PASS = 2, MFWH_OPT_PREFETCH_DEPTH = 3 };
 int mfwh_set_option(int key, long long value);
 
 #ifdef __cplusplus

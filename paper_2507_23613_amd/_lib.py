@@ -26,7 +26,8 @@ MFWH_MAX_NF = 8
 MFWH_MAX_RESTART = 512
 STATUS = {0: "MFWH_OK", 1: "MFWH_NOT_CONVERGED", -1: "MFWH_EINVAL", -2: "MFWH_EUNSORTED",
           -3: "MFWH_ECFL", -4: "MFWH_ESINGULAR", -5: "MFWH_ENT", -6: "MFWH_EHIP",
-          -7: "MFWH_EWORKSPACE", -8: "MFWH_ENONFINITE"}
+          -7: "MFWH_EWORKSPACE", -8: "MFWH_ENONFINITE",
+          -9: "MFWH_ENOTCONV_MG"}
 
 
 class MfwhError(RuntimeError):
@@ -42,7 +43,8 @@ class mfwh_grid(ctypes.Structure):
 
 class mfwh_time(ctypes.Structure):
     _fields_ = [("nf", c_int), ("omega", P_double), ("filt", P_double), ("T", c_double),
-                ("dt", c_double)]
+                ("dt", c_double), ("scheme", c_int), ("imp_tol", c_double),
+                ("imp_max_cycles", c_int)]
 
 
 class mfwh_solve_opts(ctypes.Structure):
@@ -54,7 +56,8 @@ class mfwh_solve_opts(ctypes.Structure):
 class mfwh_solve_info(ctypes.Structure):
     _fields_ = [("iterations", c_int), ("applies", c_int), ("outer", c_int),
                 ("rel_residual", c_double), ("point_steps", c_longlong), ("fell_back", c_int),
-                ("initial_rel_residual", c_double), ("initial_scale", c_double)]
+                ("initial_rel_residual", c_double), ("initial_scale", c_double),
+                ("implicit_solves", c_longlong), ("mg_cycles", c_longlong)]
 
 
 class mfwh_problem(ctypes.Structure):
@@ -78,7 +81,7 @@ def _load():
         "mfwh_plan_info": (c_int, [ctypes.POINTER(mfwh_time), P_double, P_int, P_double,
                                    P_double, P_double]),
         "mfwh_plan_coefficients": (c_int, [ctypes.POINTER(mfwh_time), P_double, P_double]),
-        "mfwh_filter_adjusted": (c_int, [c_int, P_double, c_double, P_double]),
+        "mfwh_filter_adjusted": (c_int, [c_int, P_double, c_double, c_int, P_double]),
         "mfwh_optimize_filter": (c_int, [c_int, P_double, c_int, c_int, c_int, c_double,
                                          c_double, P_double, P_double, P_int]),
         "mfwh_workspace_bytes": (c_size_t, [ctypes.POINTER(mfwh_grid),
@@ -181,8 +184,15 @@ def make_grid(shape, lengths=None, order=4, precision=MFWH_FP64, c=None):
     return g
 
 
-def make_time(omega, T, dt, filt=None):
+MFWH_EXPLICIT = 0
+MFWH_IMPLICIT = 1
+
+
+def make_time(omega, T, dt, filt=None, scheme=MFWH_EXPLICIT, imp_tol=0.0, imp_max_cycles=0):
     t = mfwh_time()
+    t.scheme = int(scheme)
+    t.imp_tol = float(imp_tol)
+    t.imp_max_cycles = int(imp_max_cycles)
     om, p = _dptr(omega)
     t.nf = om.size
     t.omega = p
@@ -244,10 +254,10 @@ def mfwh_plan_coefficients(time):
     return kap, phi
 
 
-def mfwh_filter_adjusted(omega, dt):
+def mfwh_filter_adjusted(omega, dt, scheme=0):
     om, p = _dptr(omega)
     out = np.zeros((om.size, 3))
-    _check(LIB.mfwh_filter_adjusted(om.size, p, dt, out.ctypes.data_as(P_double)))
+    _check(LIB.mfwh_filter_adjusted(om.size, p, dt, int(scheme), out.ctypes.data_as(P_double)))
     return out
 
 
@@ -283,7 +293,8 @@ def _solve(fn, grid, time, f, v, opts, ws, stream, hist_len):
                 applies=info.applies, outer=info.outer, rel_residual=info.rel_residual,
                 point_steps=info.point_steps, fell_back=bool(info.fell_back),
                 initial_rel_residual=info.initial_rel_residual,
-                initial_scale=info.initial_scale, history=hist[:info.iterations].copy())
+                initial_scale=info.initial_scale, implicit_solves=info.implicit_solves,
+                mg_cycles=info.mg_cycles, history=hist[:info.iterations].copy())
 
 
 def mfwh_solve_fixed_point(grid, time, f, v, opts, ws, stream=None):
@@ -342,6 +353,7 @@ def mfwh_stats_read():
 
 MFWH_OPT_GRAPHS = 1
 MFWH_OPT_STEPS_PER_PASS = 2
+MFWH_OPT_PREFETCH_DEPTH = 3
 
 
 def mfwh_set_option(key, value):

@@ -113,6 +113,7 @@ ExtLayout int_layout(const Geom& G) {
 }
 
 constexpr int kRedBlocks = 1024;   // reduction blocks of the finalize/BLAS kernels
+constexpr int kMaxLev = 16;        // multigrid levels at most
 
 struct Workspace {
   double *w64a = nullptr, *w64b = nullptr, *f64 = nullptr, *c64 = nullptr;
@@ -125,11 +126,45 @@ struct Workspace {
   double* vec = nullptr;       // nvec vectors of nf*fs doubles
   int nvec = 0;
   int nscal = 0;
+  // implicit scheme: multigrid levels (level 0 uses w64c/w64d/... as x and b)
+  int nlev = 0;
+  MgLevel lev[kMaxLev] = {};
+  double *mx[kMaxLev] = {}, *mb[kMaxLev] = {}, *mt[kMaxLev] = {}, *mr[kMaxLev] = {};
+  double* mc2[kMaxLev] = {};
   size_t bytes = 0;
 };
 
-// Carve the workspace (base may be null to only compute the size).
-Workspace carve(const Geom& G, int nf, bool fp32, bool varc, int restart, char* base) {
+// Multigrid hierarchy of a 2D interior grid for the implicit step matrix
+// M = I - alpha dt^2 c^2 Delta_h: (2n+1) -> n points per axis while both
+// counts are odd and >= 3; spacing doubles per level.
+int mg_hierarchy(const Geom& G, const mfwh_grid* g, double alpha, double dt, MgLevel* lev) {
+  const double hx = g->len[0] / (g->n[0] - 1), hy = g->len[1] / (g->n[1] - 1);
+  lev[0].nx = G.nxi;
+  lev[0].ny = G.nyi;
+  lev[0].py = G.py;
+  lev[0].kx = alpha * dt * dt / (hx * hx);
+  lev[0].ky = alpha * dt * dt / (hy * hy);
+  lev[0].c2 = nullptr;
+  int n = 1;
+  while (n < kMaxLev) {
+    const MgLevel& L = lev[n - 1];
+    if (L.nx < 3 || L.ny < 3 || !(L.nx & 1) || !(L.ny & 1)) break;
+    MgLevel& C = lev[n];
+    C.nx = (L.nx - 1) / 2;
+    C.ny = (L.ny - 1) / 2;
+    C.py = ((long long)C.nx + 63) / 64 * 64;
+    C.kx = L.kx * 0.25;
+    C.ky = L.ky * 0.25;
+    C.c2 = nullptr;
+    ++n;
+  }
+  return n;
+}
+
+// Carve the workspace (base may be null to only compute the size).  `mg`:
+// hierarchy of the implicit scheme (nullptr for the explicit one).
+Workspace carve(const Geom& G, int nf, bool fp32, bool varc, int restart, char* base,
+                const MgLevel* mg = nullptr, int nlev = 0) {
   Workspace w;
   size_t off = 0;
   auto take = [&](size_t bytes) -> char* {
@@ -167,6 +202,20 @@ Workspace carve(const Geom& G, int nf, bool fp32, bool varc, int restart, char* 
     w.nvec = restart + 1 + 5;
     w.vec = (double*)take((size_t)w.nvec * fs * nf * 8);
   }
+  if (mg) {
+    w.nlev = nlev;
+    for (int l = 0; l < nlev; ++l) {
+      w.lev[l] = mg[l];
+      const size_t fl = (size_t)mg[l].py * mg[l].ny;
+      if (l > 0) {
+        w.mx[l] = (double*)take(fl * 8);
+        w.mb[l] = (double*)take(fl * 8);
+        if (varc) w.mc2[l] = (double*)take(fl * 8);
+      }
+      w.mt[l] = (double*)take(fl * 8);
+      w.mr[l] = (double*)take(fl * 8);
+    }
+  }
   w.bytes = (off + 255) / 256 * 256;
   return w;
 }
@@ -191,10 +240,13 @@ struct Problem {
   bool fp32 = false, varc = false;
   bool graphs = false;               // replay recorded step sequences
   int spp = 0;                       // 2D: 0 general kernel, 1 or 2 streamlined steps per pass
+  int depth = 4;                     // rows of operands in flight (streamlined kernels)
   LaunchShape shape64, shape32;
   LaunchShape leap;                  // shape of the streamlined 2D kernels
   long long point_steps = 0;
   int applies = 0;
+  bool implicit = false;             // trapezoid scheme with multigrid step solves
+  long long imp_solves = 0, mg_cycles = 0;
   StepGraph sg[2][2];                // [float32][forcing]
   ~Problem() {
     for (auto& a : sg)
@@ -209,6 +261,7 @@ LaunchShape g_shape_override;   // bx == 0: use defaults
 bool g_shape_set = false;
 bool g_graphs = true;           // solvers record step sequences into graphs
 int g_steps_per_pass = 2;       // 2D step kernel selection (MFWH_OPT_STEPS_PER_PASS)
+int g_depth = 4;                // prefetch depth of the streamlined kernels (MFWH_OPT_PREFETCH_DEPTH)
 
 int setup(Problem& pr, const mfwh_grid* g, const mfwh_time* t, int restart, void* ws,
           size_t ws_bytes, void* stream) {
@@ -220,17 +273,33 @@ int setup(Problem& pr, const mfwh_grid* g, const mfwh_time* t, int restart, void
   pr.fp32 = g->precision == MFWH_FP32_STENCIL;
   pr.varc = g->c != nullptr;
   pr.s = (hipStream_t)stream;
+  pr.implicit = pr.P.scheme == MFWH_IMPLICIT;
+  MgLevel mg[kMaxLev];
+  int nlev = 0;
+  if (pr.implicit) {
+    if (g->dim != 2) return fail(MFWH_EINVAL, "the implicit scheme is implemented for 2D grids");
+    if (pr.fp32) return fail(MFWH_EINVAL, "the implicit scheme runs in float64 only");
+    nlev = mg_hierarchy(pr.G, g, pr.P.alpha, pr.P.dt, mg);
+  }
   if (!ws) return fail(MFWH_EWORKSPACE, "null workspace");
   if (((uintptr_t)ws) % 256) return fail(MFWH_EWORKSPACE, "workspace must be 256-byte aligned");
-  pr.W = carve(pr.G, t->nf, pr.fp32, pr.varc, restart, (char*)ws);
+  pr.W = carve(pr.G, t->nf, pr.fp32, pr.varc, restart, (char*)ws, pr.implicit ? mg : nullptr,
+               nlev);
   if (pr.W.bytes > ws_bytes)
     return fail(MFWH_EWORKSPACE, "workspace too small: need " + std::to_string(pr.W.bytes) +
                                      " bytes, got " + std::to_string(ws_bytes));
   pr.shape64 = default_shape(pr.G, g->order, 8);
   pr.shape32 = default_shape(pr.G, g->order, 4);
   pr.spp = pr.G.dim == 2 ? g_steps_per_pass : 0;
+  pr.depth = g_depth;
   pr.leap = default_leap_shape(pr.G, pr.spp);
   if (g_shape_set) pr.shape64 = pr.shape32 = pr.leap = g_shape_override;
+  if (pr.implicit) {
+    pr.W.lev[0].c2 = pr.varc ? pr.W.c64 : nullptr;
+    pr.W.mx[0] = nullptr;   // level 0 solves in place in the W buffers
+    for (int l = 1; l < pr.W.nlev; ++l) pr.W.lev[l].c2 = pr.W.mc2[l];
+    return MFWH_OK;        // trapezoid stepping has no step restriction
+  }
   // stability of explicit leapfrog for c = 1 (variable c is the caller's duty)
   double h[3];
   for (int k = 0; k < g->dim; ++k) h[k] = g->len[k] / (g->n[k] - 1);
@@ -254,6 +323,10 @@ int prepare(Problem& pr, const double* f) {
     HIPCHK(launch_copy_fields<double, double>(pr.G, 1, pr.grid->c, cl, pr.W.c64, ci, 1, pr.s));
     if (pr.fp32)
       HIPCHK(launch_copy_fields<double, float>(pr.G, 1, pr.grid->c, cl, pr.W.c32, ci, 1, pr.s));
+    if (pr.implicit)
+      for (int l = 1; l < pr.W.nlev; ++l)
+        HIPCHK(launch_mg_inject(pr.W.lev[l - 1], pr.W.lev[l - 1].c2, pr.W.lev[l], pr.W.mc2[l],
+                                pr.s));
   }
   return MFWH_OK;
 }
@@ -286,6 +359,130 @@ struct Out {
   double alpha = 0.0, beta = 1.0;
   double* partial = nullptr;     // FPI residual partial sums
 };
+
+// ---------------------------------------------------------------------------
+// implicit trapezoid scheme: multigrid solves of M W^{n+1} = rhs
+// ---------------------------------------------------------------------------
+constexpr int kPre = 2, kPost = 2;   // Jacobi sweeps before / after the coarse correction
+
+double jacobi_weight(int order) { return order == 4 ? 10.0 / 13.0 : 0.8; }
+
+// One V-cycle on level l for M_l x = b (x updated in place; level 0 uses the
+// caller's x and b, coarser levels the workspace).
+int vcycle(Problem& pr, int l, double* x, const double* b) {
+  Workspace& W = pr.W;
+  const MgLevel& L = W.lev[l];
+  const int order = l == 0 ? pr.grid->order : 2;
+  const double w = jacobi_weight(order);
+  double* t = W.mt[l];
+  if (l == W.nlev - 1) {
+    // coarsest level: a fixed even number of sweeps
+    const int sweeps = (int)std::min<long long>(64, 2 * ((std::max(L.nx, L.ny) + 1) / 2) + 8);
+    for (int k = 0; k < sweeps; k += 2) {
+      HIPCHK(launch_mg_jacobi(L, order, x, b, t, w, pr.s));
+      HIPCHK(launch_mg_jacobi(L, order, t, b, x, w, pr.s));
+    }
+    return MFWH_OK;
+  }
+  for (int k = 0; k < kPre; k += 2) {
+    HIPCHK(launch_mg_jacobi(L, order, x, b, t, w, pr.s));
+    HIPCHK(launch_mg_jacobi(L, order, t, b, x, w, pr.s));
+  }
+  HIPCHK(launch_mg_resid(L, order, x, b, W.mr[l], nullptr, 0, nullptr, pr.s));
+  HIPCHK(launch_mg_restrict(L, W.mr[l], W.lev[l + 1], W.mb[l + 1], W.mx[l + 1], pr.s));
+  CHK(vcycle(pr, l + 1, W.mx[l + 1], W.mb[l + 1]));
+  HIPCHK(launch_mg_prolong(W.lev[l + 1], W.mx[l + 1], L, x, pr.s));
+  for (int k = 0; k < kPost; k += 2) {
+    HIPCHK(launch_mg_jacobi(L, order, x, b, t, w, pr.s));
+    HIPCHK(launch_mg_jacobi(L, order, t, b, x, w, pr.s));
+  }
+  return MFWH_OK;
+}
+
+// V-cycles on M x = b from the guess in x until ||b - M x|| <= tol ||b||.
+int mg_solve(Problem& pr, double* x, const double* b) {
+  Workspace& W = pr.W;
+  const MgLevel& L = W.lev[0];
+  double* out2 = W.scal + W.nscal - 16;
+  const double tol = pr.P.imp_tol;
+  for (int cyc = 1;; ++cyc) {
+    CHK(vcycle(pr, 0, x, b));
+    HIPCHK(launch_mg_resid(L, pr.grid->order, x, b, nullptr, W.partial, kRedBlocks, out2, pr.s));
+    double h2[2];
+    HIPCHK(hipMemcpyAsync(h2, out2, 2 * sizeof(double), hipMemcpyDeviceToHost, pr.s));
+    HIPCHK(hipStreamSynchronize(pr.s));
+    pr.mg_cycles += 1;
+    if (!std::isfinite(h2[0]) || !std::isfinite(h2[1]))
+      return fail(MFWH_ENONFINITE, "non-finite residual in an implicit step");
+    if (h2[1] == 0.0) {                       // zero right-hand side: x = 0
+      HIPCHK(launch_fill_t<double>(x, (long long)L.py * L.ny, 0.0, pr.s));
+      break;
+    }
+    if (h2[0] <= tol * tol * h2[1]) break;
+    if (cyc >= pr.P.imp_max_cycles)
+      return fail(MFWH_ENOTCONV_MG, "multigrid did not reach imp_tol in imp_max_cycles V-cycles");
+  }
+  pr.imp_solves += 1;
+  return MFWH_OK;
+}
+
+// One application with the implicit scheme (float64): W^0 from V, N_t
+// trapezoid steps (eq. WaveSchemeA, first step eq. implicitFirstStep), the
+// filter accumulation after each step, then the finalize of B^{-1} q.
+int apply_implicit(Problem& pr, const double* v, ExtLayout vl, bool forcing, const Out& o) {
+  const Plan& P = pr.P;
+  const int nf = P.nf;
+  double* bufs[3] = {pr.W.w64a, pr.W.w64b, pr.W.w64c};
+  double* rhs = pr.W.w64d;
+  if (v) HIPCHK(launch_init_w0<double>(pr.G, nf, v, vl, bufs[0], pr.s));
+  else HIPCHK(launch_fill_t<double>(bufs[0], pr.G.fs, 0.0, pr.s));
+  ImpArgs ia{};
+  ia.lev = pr.W.lev[0];
+  ia.f = forcing ? pr.W.f64 : nullptr;
+  ia.fs = pr.G.fs;
+  ia.alpha = P.alpha;
+  ia.beta = P.beta;
+  ia.dt2 = P.dt * P.dt;
+  ia.nf = nf;
+  ImpAccum ac{};
+  ac.nx = pr.G.nxi;
+  ac.ny = pr.G.nyi;
+  ac.py = pr.G.py;
+  ac.fs = pr.G.fs;
+  ac.q = pr.W.q;
+  ac.nf = nf;
+  int ip = -1, ic = 0;
+  for (int n = 0; n < P.nt; ++n) {
+    const int in = (ip != 1 && ic != 1) ? 1 : (ip != 2 && ic != 2) ? 2 : 0;
+    ia.first = n == 0 ? 1 : 0;
+    ia.w = bufs[ic];
+    ia.wp = ip >= 0 ? bufs[ip] : nullptr;
+    ia.b = rhs;
+    ia.x = bufs[in];
+    for (int m = 0; m < MFWH_MAX_NF; ++m)
+      ia.phi[m] = (forcing && m < nf) ? P.phi[(size_t)n * nf + m] * P.ffac[m] : 0.0;
+    HIPCHK(launch_imp_rhs(ia, pr.grid->order, pr.s));
+    CHK(mg_solve(pr, bufs[in], rhs));
+    ac.first = n == 0 ? 1 : 0;
+    ac.w = bufs[in];
+    ac.w0 = bufs[ic];
+    int mask = 0;
+    for (int m = 0; m < MFWH_MAX_NF; ++m) {
+      ac.kap[m] = m < nf ? P.kappa[(size_t)(n + 1) * nf + m] : 0.0;
+      ac.kap0[m] = (m < nf && n == 0) ? P.kappa[m] : 0.0;
+      if (m < nf && (n == 0 || ac.kap[m] != 0.0)) mask |= 1 << m;
+    }
+    ac.mask = mask;
+    HIPCHK(launch_imp_accum(ac, pr.s));
+    ip = ic;
+    ic = in;
+  }
+  HIPCHK(launch_finalize(pr.G, nf, pr.W.q, P.Binv, o.xin, o.xl, o.alpha, o.beta, o.out, o.ol,
+                         o.partial, kRedBlocks, pr.s));
+  pr.point_steps += pr.G.npts() * (long long)P.nt;
+  pr.applies += 1;
+  return MFWH_OK;
+}
 
 // One MFWH application in precision T.  v == nullptr means V = 0.
 template <typename T>
@@ -440,7 +637,7 @@ int apply_t(Problem& pr, const double* v, ExtLayout vl, bool forcing, const Out&
     // unused slots repeat the last used accumulator (the kernels load every
     // slot unconditionally and store only the first nq)
     for (int j = nq; j < MFWH_MAX_NF; ++j) la.qm[j] = nq > 0 ? la.qm[nq - 1] : 0;
-    return launch_leap2d<T>(la, pr.grid->order, ns, pr.leap, s);
+    return launch_leap2d<T>(la, pr.grid->order, ns, pr.depth, pr.leap, s);
   };
   double bytes_all = 0.0;          // algorithmic bytes of the whole sequence
   for (const Op& op : ops) bytes_all += op_bytes(op);
@@ -508,6 +705,7 @@ int apply_t(Problem& pr, const double* v, ExtLayout vl, bool forcing, const Out&
 
 int apply_any(Problem& pr, bool use32, const double* v, ExtLayout vl, bool forcing,
               const Out& o) {
+  if (pr.implicit) return apply_implicit(pr, v, vl, forcing, o);
   return use32 ? apply_t<float>(pr, v, vl, forcing, o) : apply_t<double>(pr, v, vl, forcing, o);
 }
 
@@ -698,6 +896,8 @@ int batch_sizes(int np, const mfwh_problem* P, int restart, std::vector<size_t>*
     if (P[i].grid.precision != MFWH_FP64)
       return fail(MFWH_EINVAL, "batched solves run in float64");
     if (P[i].grid.dim == 1) return fail(MFWH_EINVAL, "batched solves need dim 2 or 3");
+    if (P[i].time.scheme != MFWH_EXPLICIT)
+      return fail(MFWH_EINVAL, "batched solves use the explicit scheme");
     if (!P[i].time.omega || P[i].time.nf < 1 || P[i].time.nf > MFWH_MAX_NF)
       return fail(MFWH_EINVAL, "bad frequency list");
     const long long nt = std::llround(P[i].time.T / P[i].time.dt);
@@ -916,15 +1116,18 @@ int mfwh_plan_coefficients(const mfwh_time* t, double* kappa, double* phi) {
   int rc = build_plan(t, &P, &err);
   if (rc != MFWH_OK) return fail(rc, err);
   if (kappa) std::memcpy(kappa, P.kappa.data(), P.kappa.size() * sizeof(double));
-  if (phi) std::memcpy(phi, P.phi.data(), P.phi.size() * sizeof(double));
+  if (phi) {
+    for (size_t k = 0; k < P.phi.size(); ++k) phi[k] = P.phi[k] * P.ffac[k % P.nf];
+  }
   return MFWH_OK;
 }
 
-int mfwh_filter_adjusted(int nf, const double* omega, double dt, double* filt_out) {
-  if (nf < 1 || nf > MFWH_MAX_NF || !omega || !filt_out || !(dt > 0))
+int mfwh_filter_adjusted(int nf, const double* omega, double dt, int scheme, double* filt_out) {
+  if (nf < 1 || nf > MFWH_MAX_NF || !omega || !filt_out || !(dt > 0) ||
+      (scheme != MFWH_EXPLICIT && scheme != MFWH_IMPLICIT))
     return fail(MFWH_EINVAL, "bad filter_adjusted arguments");
   std::string err;
-  int rc = adjusted_params(nf, omega, dt, filt_out, &err);
+  int rc = adjusted_params(nf, omega, dt, scheme == MFWH_IMPLICIT ? 0.5 : 0.0, filt_out, &err);
   return rc == MFWH_OK ? rc : fail(rc, err);
 }
 
@@ -942,7 +1145,14 @@ size_t mfwh_workspace_bytes(const mfwh_grid* g, const mfwh_time* t, int restart)
   Geom G;
   if (make_geom(g, &G) != MFWH_OK || !t || t->nf < 1 || t->nf > MFWH_MAX_NF) return 0;
   restart = std::max(0, std::min(restart, MFWH_MAX_RESTART));
-  return carve(G, t->nf, g->precision == MFWH_FP32_STENCIL, g->c != nullptr, restart, nullptr)
+  MgLevel mg[kMaxLev];
+  int nlev = 0;
+  if (t->scheme == MFWH_IMPLICIT) {
+    if (g->dim != 2 || !(t->dt > 0.0)) return 0;
+    nlev = mg_hierarchy(G, g, 0.5, t->dt, mg);
+  }
+  return carve(G, t->nf, g->precision == MFWH_FP32_STENCIL, g->c != nullptr, restart, nullptr,
+               nlev ? mg : nullptr, nlev)
       .bytes;
 }
 
@@ -999,6 +1209,8 @@ int mfwh_solve_fixed_point(const mfwh_grid* g, const mfwh_time* t, const double*
     info->fell_back = 0;
     info->initial_rel_residual = 1.0;
     info->initial_scale = 1.0;
+    info->implicit_solves = pr.imp_solves;
+    info->mg_cycles = pr.mg_cycles;
   }
   return status;
 }
@@ -1030,7 +1242,7 @@ int mfwh_solve_gmres(const mfwh_grid* g, const mfwh_time* t, const double* f, do
   // b = W_h(0) in float64 (Section 7)
   {
     Out ob{B, il};
-    CHK(apply_t<double>(pr, nullptr, il, true, ob));
+    CHK(apply_any(pr, false, nullptr, il, true, ob));
   }
   double bnorm;
   CHK(norm2(V, B, &bnorm));
@@ -1047,7 +1259,7 @@ int mfwh_solve_gmres(const mfwh_grid* g, const mfwh_time* t, const double* f, do
     // residual of the initial guess (float64); optionally the residual-optimal
     // scaling alpha = <A x, b>/<A x, A x>; reject the guess if worse than zero
     Out orr{R, il, X, il, 1.0, -1.0, nullptr};
-    CHK(apply_t<double>(pr, X, il, false, orr));          // R = A x
+    CHK(apply_any(pr, false, X, il, false, orr));          // R = A x
     double alpha = 1.0;
     if (o.scale_initial) {
       double d1[1], d2;
@@ -1083,7 +1295,7 @@ int mfwh_solve_gmres(const mfwh_grid* g, const mfwh_time* t, const double* f, do
         HIPCHK(hipMemcpyAsync(R, B, V.N * sizeof(double), hipMemcpyDeviceToDevice, pr.s));
       } else {
         Out orr{R, il, X, il, 1.0, -1.0, nullptr};
-        CHK(apply_t<double>(pr, X, il, false, orr));
+        CHK(apply_any(pr, false, X, il, false, orr));
         HIPCHK(launch_axpby(1.0, B, -1.0, R, V.N, pr.s));
       }
       double rn;
@@ -1114,6 +1326,8 @@ int mfwh_solve_gmres(const mfwh_grid* g, const mfwh_time* t, const double* f, do
     info->fell_back = fell_back;
     info->initial_rel_residual = init_rel;
     info->initial_scale = init_scale;
+    info->implicit_solves = pr.imp_solves;
+    info->mg_cycles = pr.mg_cycles;
   }
   return status;
 }
@@ -1355,6 +1569,8 @@ int mfwh_solve_gmres_batched(int nprob, const mfwh_problem* probs, const mfwh_so
       infos[i].rel_residual = S[i].res / S[i].bnorm;
       infos[i].point_steps = pr.point_steps;
       infos[i].fell_back = S[i].fell_back;
+      infos[i].implicit_solves = 0;
+      infos[i].mg_cycles = 0;
       infos[i].initial_rel_residual = S[i].init_rel;
       infos[i].initial_scale = S[i].scale;
     }
@@ -1407,6 +1623,10 @@ int mfwh_set_option(int key, long long value) {
     case MFWH_OPT_STEPS_PER_PASS:
       if (value < 0 || value > 2) return fail(MFWH_EINVAL, "steps per pass must be 0, 1 or 2");
       g_steps_per_pass = (int)value;
+      return MFWH_OK;
+    case MFWH_OPT_PREFETCH_DEPTH:
+      if (value != 2 && value != 4) return fail(MFWH_EINVAL, "prefetch depth must be 2 or 4");
+      g_depth = (int)value;
       return MFWH_OK;
     default:
       return fail(MFWH_EINVAL, "unknown option");

@@ -109,12 +109,66 @@ struct LeapArgs {
 };
 
 // Launch one streamlined 2D step (steps == 1) or two fused steps
-// (steps == 2) with shape ls (bx in {64, 128, 256}); fills the tiling fields.
+// (steps == 2) with shape ls (bx in {64, 128, 256}) and `depth` rows of
+// operands in flight per wave (2 or 4); fills the tiling fields.
 template <typename T>
-hipError_t launch_leap2d(LeapArgs<T>& a, int order, int steps, const LaunchShape& ls,
+hipError_t launch_leap2d(LeapArgs<T>& a, int order, int steps, int depth, const LaunchShape& ls,
                          hipStream_t s);
 // Default launch shapes of the streamlined kernels.
 LaunchShape default_leap_shape(const Geom& g, int steps);
+
+// mg2d.hip: implicit trapezoid steps and their multigrid solver (2D, float64)
+// One multigrid level: interior nx x ny points at row pitch py; the operator
+// is M x = x - c^2 (kx D_xx x + ky D_yy x) with D the unscaled second
+// difference (order 4 on the finest level when the grid is order 4, order 2
+// elsewhere), kx = alpha dt^2 / hx^2, ky = alpha dt^2 / hy^2.
+struct MgLevel {
+  int nx, ny;
+  long long py;
+  double kx, ky;
+  const double* c2;     // c^2 at this level or nullptr (c = 1)
+};
+
+// Right-hand side of one implicit step (see k_imp_rhs).
+struct ImpArgs {
+  MgLevel lev;          // finest level
+  const double* w;      // W^n (W^0 on the first step)
+  const double* wp;     // W^{n-1} (unused on the first step)
+  const double* f;      // forcing fields or nullptr
+  long long fs;
+  double* b;            // right-hand side (out)
+  double* x;            // initial guess of W^{n+1} (out)
+  double alpha, beta, dt2;
+  double phi[MFWH_MAX_NF];   // cos(omega~_m t^n) (beta + 2 alpha cos(omega~_m dt))
+  int nf;
+  int first;
+};
+
+// Filter accumulation after an implicit step.
+struct ImpAccum {
+  int nx, ny;
+  long long py, fs;
+  const double* w;      // W^{n+1}
+  const double* w0;     // W^0 (first step only)
+  double* q;
+  double kap[MFWH_MAX_NF], kap0[MFWH_MAX_NF];
+  int nf, mask, first;
+};
+
+hipError_t launch_mg_jacobi(const MgLevel& L, int order, const double* x, const double* b,
+                            double* y, double w, hipStream_t s);
+// r = b - M x (r may be null); with `partial` (2*nred doubles) also
+// out2[0] = |r|^2, out2[1] = |b|^2 (device)
+hipError_t launch_mg_resid(const MgLevel& L, int order, const double* x, const double* b,
+                           double* r, double* partial, int nred, double* out2, hipStream_t s);
+hipError_t launch_mg_restrict(const MgLevel& F, const double* rf, const MgLevel& C, double* bc,
+                              double* xc, hipStream_t s);
+hipError_t launch_mg_prolong(const MgLevel& C, const double* ec, const MgLevel& F, double* xf,
+                             hipStream_t s);
+hipError_t launch_mg_inject(const MgLevel& F, const double* cf, const MgLevel& C, double* cc,
+                            hipStream_t s);
+hipError_t launch_imp_rhs(const ImpArgs& a, int order, hipStream_t s);
+hipError_t launch_imp_accum(const ImpAccum& a, hipStream_t s);
 
 // kernels.hip
 template <typename T>

@@ -180,17 +180,33 @@ int build_plan(const mfwh_time* t, Plan* p, std::string* err) {
     *err = "T/dt must be an integer number of steps >= 2";
     return MFWH_ENT;
   }
+  if (t->scheme != MFWH_EXPLICIT && t->scheme != MFWH_IMPLICIT) {
+    *err = "scheme must be MFWH_EXPLICIT or MFWH_IMPLICIT";
+    return MFWH_EINVAL;
+  }
+  if (t->scheme == MFWH_IMPLICIT) {
+    if (!(t->imp_tol >= 0.0) || t->imp_max_cycles < 0) {
+      *err = "imp_tol and imp_max_cycles must be non-negative";
+      return MFWH_EINVAL;
+    }
+    p->imp_tol = t->imp_tol > 0.0 ? t->imp_tol : 1e-10;
+    p->imp_max_cycles = t->imp_max_cycles > 0 ? t->imp_max_cycles : 100;
+  }
+  p->scheme = t->scheme;
+  p->alpha = t->scheme == MFWH_IMPLICIT ? 0.5 : 0.0;   // trapezoid / leapfrog (Section 6)
+  p->beta = 1.0 - 2.0 * p->alpha;
   p->nf = nf;
   p->nt = (int)nt;
   p->dt = t->dt;
   p->T = nt * t->dt;
   for (int m = 0; m < nf; ++m) {
     p->omega[m] = t->omega[m];
-    if (!(t->omega[m] * t->dt < 2.0)) {
+    if (p->scheme == MFWH_EXPLICIT && !(t->omega[m] * t->dt < 2.0)) {
       *err = "omega*dt >= 2: no modified frequency for explicit leapfrog";
       return MFWH_ECFL;
     }
-    p->omega_t[m] = omega_tilde(t->omega[m], t->dt, 0.0);
+    p->omega_t[m] = omega_tilde(t->omega[m], t->dt, p->alpha);
+    p->ffac[m] = p->beta + 2.0 * p->alpha * std::cos(p->omega_t[m] * t->dt);
     // eq. TbarDef with the modified periods
     const double Tm = kTwoPi / p->omega_t[m];
     p->npm[m] = (int)std::floor(p->T / Tm + 1e-9);
@@ -242,10 +258,11 @@ int build_plan(const mfwh_time* t, Plan* p, std::string* err) {
   return MFWH_OK;
 }
 
-int adjusted_params(int nf, const double* omega, double dt, double* out, std::string* err) {
+int adjusted_params(int nf, const double* omega, double dt, double alpha, double* out,
+                    std::string* err) {
   for (int m = 0; m < nf; ++m) {
-    if (!(omega[m] * dt < 2.0)) { *err = "omega*dt >= 2"; return MFWH_ECFL; }
-    const double w = omega_tilde(omega[m], dt, 0.0) * dt;
+    if (alpha == 0.0 && !(omega[m] * dt < 2.0)) { *err = "omega*dt >= 2"; return MFWH_ECFL; }
+    const double w = omega_tilde(omega[m], dt, alpha) * dt;
     out[3 * m + 0] = -std::tan(0.5 * w) / (2.0 * std::tan(w));   // eq. origParamAdjust
     out[3 * m + 1] = 1.0;
     out[3 * m + 2] = 0.0;

@@ -13,7 +13,12 @@ struct Plan {
   int nt = 0;                       // number of time steps N_t
   double dt = 0.0, T = 0.0;         // T = N_t dt
   double omega[MFWH_MAX_NF] = {};   // physical frequencies
-  double omega_t[MFWH_MAX_NF] = {}; // modified frequencies (explicit scheme)
+  int scheme = MFWH_EXPLICIT;
+  double alpha = 0.0, beta = 1.0;   // scheme weights of eq. WaveSchemeA
+  double omega_t[MFWH_MAX_NF] = {}; // modified frequencies of the scheme (eq. omegaImplicit)
+  double ffac[MFWH_MAX_NF] = {};    // beta + 2 alpha cos(omega~_m dt) (eq. WaveSchemeForcing)
+  double imp_tol = 1e-10;           // implicit: relative residual of each step solve
+  int imp_max_cycles = 100;         // implicit: V-cycle limit per step
   int npm[MFWH_MAX_NF] = {};        // N_{p,m}
   double tfm[MFWH_MAX_NF] = {};     // T~_{f,m}
   double params[MFWH_MAX_NF][3] = {};
@@ -29,7 +34,8 @@ double dt_max_explicit(int dim, const double* h, int order, double cmax);
 double dt_exact_periods(double omega1, int np, int nt, double alpha);
 void trapezoid_weights(int nt, double dt, double T, double* sigma, int stride);
 int build_plan(const mfwh_time* t, Plan* p, std::string* err);
-int adjusted_params(int nf, const double* omega, double dt, double* out, std::string* err);
+int adjusted_params(int nf, const double* omega, double dt, double alpha, double* out,
+                    std::string* err);
 int optimize_filter(int nf, const double* om, int np, int nt, int ndelta, double cdelta,
                     double rcond, double* out, double* lmax_out, int* nlam_out,
                     std::string* err);

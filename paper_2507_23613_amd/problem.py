@@ -15,7 +15,10 @@ class GpuProblem:
     """``w``: workload dict from ``paper_2507_23613_amd.inputs``."""
 
     def __init__(self, w, precision=L.MFWH_FP64, restart=30, device="cuda", filt=None,
-                 time=None):
+                 time=None, scheme=L.MFWH_EXPLICIT, steps_per_period=10, imp_tol=0.0,
+                 imp_max_cycles=0):
+        """scheme MFWH_IMPLICIT plans with the implicit recipe
+        (``steps_per_period`` steps over the shortest nominal period)."""
         self.w = w
         self.device = torch.device(device)
         self.shape = tuple(w["shape"])
@@ -25,27 +28,34 @@ class GpuProblem:
             np.ascontiguousarray(w["c"]), dtype=torch.float64, device=self.device)
         cmax = 1.0 if w["c"] is None else float(np.max(w["c"]))
         self.grid = L.make_grid(self.shape, w["lengths"], w["order"], precision, self.c)
-        if time is None:
+        self.scheme = scheme
+        if time is not None:
+            T, dt, nt = time
+        elif scheme == L.MFWH_IMPLICIT:
+            T, dt, nt = L.mfwh_plan_time_implicit(float(self.omega[0]), float(self.omega[-1]),
+                                                  int(w["np"]), int(steps_per_period))
+        else:
             T, dt, nt = L.mfwh_plan_time(self.grid, cmax, float(self.omega[0]), int(w["np"]),
                                          float(w["cfl"]))
-        else:
-            T, dt, nt = time
         self.T, self.dt, self.nt = T, dt, nt
+
+        def mk(params):
+            return L.make_time(self.omega, T, dt, params, scheme, imp_tol, imp_max_cycles)
         kind = w["filter"] if filt is None else filt
         if isinstance(kind, np.ndarray):
             params = kind
         elif kind == "traditional":
             params = None
         elif kind == "adjusted":
-            params = L.mfwh_filter_adjusted(self.omega, dt)
+            params = L.mfwh_filter_adjusted(self.omega, dt, scheme)
         elif kind == "optimised":
-            info = L.mfwh_plan_info(L.make_time(self.omega, T, dt))
+            info = L.mfwh_plan_info(mk(None))
             params, _, _ = L.mfwh_optimize_filter(info["omega_tilde"], int(w["np"]), nt,
                                                   rcond=w.get("filter_rcond", 0.0))
         else:
             raise ValueError(f"unknown filter {kind!r}")
         self.params = params
-        self.time = L.make_time(self.omega, T, dt, params)
+        self.time = mk(params)
         self.plan = L.mfwh_plan_info(self.time)
         self.f = torch.as_tensor(np.ascontiguousarray(w["f"]), dtype=torch.float64,
                                  device=self.device)

@@ -116,6 +116,49 @@ def test_planner_matches_oracle(mk):
     assert np.allclose(phi, pl.phi, rtol=1e-11, atol=1e-12)
 
 
+IMPLICIT_WORKLOADS = [
+    lambda: inputs.small(seed=3, shape=(33, 29), nf=3, order=4),
+    lambda: inputs.small(seed=5, shape=(21, 25), nf=4, order=2, filter="traditional"),
+    lambda: inputs.paper_square128(),
+]
+
+
+@pytest.mark.parametrize("mk", IMPLICIT_WORKLOADS, ids=["2d", "2d-trad", "paper128"])
+def test_implicit_planner_matches_oracle(mk):
+    """The library's plan for the trapezoid scheme (omega~ of eq. omegaImplicit
+    with alpha = 1/2, kappa, B, and the forcing factor of eq.
+    WaveSchemeForcing) against the oracle's."""
+    w = mk()
+    prob, pl = workload.setup_implicit(w)
+    T, dt, nt = L.mfwh_plan_time_implicit(float(w["omega"][0]), float(w["omega"][-1]),
+                                          int(w["np"]), 10)
+    assert nt == pl.nt and dt == pytest.approx(pl.dt, rel=1e-14)
+    filt = None if w["filter"] == "traditional" else pl.params
+    if w["filter"] == "optimised":
+        info0 = L.mfwh_plan_info(L.make_time(w["omega"], T, dt, scheme=L.MFWH_IMPLICIT))
+        assert np.allclose(info0["omega_tilde"], pl.omega_t, rtol=1e-14)
+        params, _, _ = L.mfwh_optimize_filter(info0["omega_tilde"], w["np"], nt)
+        scale = max(1.0, np.abs(pl.params).max())
+        assert np.allclose(params, pl.params, rtol=1e-8, atol=1e-9 * scale)
+    if w["filter"] == "adjusted":
+        params = L.mfwh_filter_adjusted(w["omega"], dt, L.MFWH_IMPLICIT)
+        assert np.allclose(params, pl.params, rtol=1e-14, atol=1e-15)
+    tm = L.make_time(w["omega"], T, dt, filt, scheme=L.MFWH_IMPLICIT)
+    info = L.mfwh_plan_info(tm)
+    assert np.allclose(info["omega_tilde"], pl.omega_t, rtol=1e-14)
+    assert list(info["npm"]) == list(pl.npm)
+    assert np.allclose(info["B"], pl.B, rtol=1e-11, atol=1e-12)
+    kap, phi = L.mfwh_plan_coefficients(tm)
+    assert np.allclose(kap, pl.kappa, rtol=1e-11, atol=1e-12 * np.abs(pl.kappa).max())
+    fac = np.cos(pl.omega_t * pl.dt)             # beta + 2 alpha cos(omega~ dt), beta = 0
+    assert np.allclose(phi, pl.phi * fac, rtol=1e-11, atol=1e-12)
+    # the trapezoid scheme has no step limit: omega dt >= 2 is accepted
+    big = L.make_time(np.array([3.0, 5.0]), 20 * 0.9, 0.9, scheme=L.MFWH_IMPLICIT)
+    L.mfwh_plan_info(big)
+    with pytest.raises(L.MfwhError):
+        L.mfwh_plan_info(L.make_time(np.array([3.0, 5.0]), 20 * 0.9, 0.9))
+
+
 def _no_gpu():
     import torch
     return not torch.cuda.is_available()

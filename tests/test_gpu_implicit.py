@@ -1,0 +1,146 @@
+"""GPU parity of the implicit (trapezoid) scheme with multigrid step solves,
+through the C ABI, against the oracle's sparse-LU implicit stepping.
+
+Bars.  Each step solve stops at a relative residual tau (imp_tol).  For
+c = 1, M = I - dt^2/2 c^2 Delta_h has eigenvalues >= 1, so the step error is
+at most tau ||rhs|| <= tau cond(M) ||W^{n+1}||; the trapezoid scheme does not
+amplify errors, so after N_t steps the application error is at most
+N_t tau cond(M), with cond(M) = 1 + dt^2/2 c_max^2 lambda_max(-Delta_h) from
+the stencil symbol.  B^{-1} amplifies it like the float64 rounding of the
+parity suite (factor max(1, cond(B)/10)); 1e-12 is the rounding floor.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+from oracle import fd, mfwh as omf, workload  # noqa: E402
+from paper_2507_23613_amd import inputs  # noqa: E402
+
+
+@pytest.fixture(autouse=True)
+def _announce(request):
+    print(f"\n[gpu-case] {request.node.nodeid}", flush=True)
+    sys.stdout.flush()
+    yield
+
+
+def _L():
+    from paper_2507_23613_amd import _lib
+    return _lib
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def rand_v(shape, nf, seed):
+    rng = np.random.default_rng(seed)
+    V = rng.standard_normal((nf,) + tuple(shape))
+    for m in range(nf):
+        fd.zero_boundary(V[m])
+    return V
+
+
+TAU = 1e-13
+
+
+def bar(w, prob, pl, tau=TAU):
+    lam = sum((4.0 if w["order"] == 2 else 16.0 / 3.0) / h ** 2 for h in prob.h)
+    cmax = 1.0 if w["c"] is None else float(np.max(w["c"]))
+    cond_m = 1.0 + 0.5 * pl.dt ** 2 * cmax ** 2 * lam
+    return max(1e-12, pl.nt * tau * cond_m) * max(1.0, np.linalg.cond(pl.B) / 10)
+
+
+def _gp(w, **kw):
+    from paper_2507_23613_amd.problem import GpuProblem
+    L = _L()
+    return GpuProblem(w, scheme=L.MFWH_IMPLICIT, **kw)
+
+
+CASES = [
+    dict(seed=3, shape=(33, 33), nf=3, order=4),             # full hierarchy 31 -> 15 -> 7 -> 3 -> 1
+    dict(seed=4, shape=(65, 33), nf=2, order=2),             # anisotropic sizes
+    dict(seed=5, shape=(17, 17), nf=4, order=4, varc=True),  # variable c, injected on coarse grids
+    dict(seed=6, shape=(21, 26), nf=2, order=4),             # ragged: no coarsening at all
+    dict(seed=7, shape=(3, 3), nf=1, order=2),               # one interior point
+    dict(seed=8, shape=(37, 45), nf=3, order=2, varc=True),  # ragged, two levels
+]
+
+
+def _id(c):
+    return f"{c['shape'][0]}x{c['shape'][1]}-nf{c['nf']}-o{c['order']}{'-varc' if c.get('varc') else ''}"
+
+
+@pytest.mark.parametrize("forcing", [True, False], ids=["forced", "free"])
+@pytest.mark.parametrize("case", CASES, ids=_id)
+def test_implicit_apply_matches_oracle(case, forcing):
+    w = inputs.small(**case)
+    prob, pl = workload.setup_implicit(w)
+    gp = _gp(w, imp_tol=TAU)
+    assert gp.nt == pl.nt and abs(gp.dt - pl.dt) < 1e-15 * pl.dt
+    V = rand_v(w["shape"], case["nf"], 40)
+    out = gp.apply(torch.as_tensor(V, device="cuda"), forcing=forcing).cpu().numpy()
+    ref = omf.apply(prob, pl, w["f"], V, forcing)
+    e, b = rel(out, ref), bar(w, prob, pl)
+    print(f"implicit apply: N_t={pl.nt} rel={e:.2e} bar={b:.1e}")
+    assert e < b
+    for m in range(case["nf"]):
+        assert np.all(out[m] - fd.zero_boundary(out[m].copy()) == 0)
+
+
+def test_implicit_gmres_reaches_direct_solution_and_reports_cycles():
+    w = inputs.small(seed=12, shape=(65, 65), nf=3, order=4)
+    prob, pl = workload.setup_implicit(w)
+    gp = _gp(w, restart=40, imp_tol=1e-12)
+    v, info = gp.gmres(tol=1e-11, max_iter=300)
+    assert info["converged"], info
+    U = np.stack([fd.helmholtz_direct(w["f"][m], w["omega"][m], prob.h, 4) for m in range(3)])
+    e = rel(v.cpu().numpy(), U)
+    cyc = info["mg_cycles"] / info["implicit_solves"]
+    print(f"implicit GMRES: its={info['iterations']} applies={info['applies']} err={e:.2e} "
+          f"V-cycles per step {cyc:.2f}")
+    assert e < 1e-8
+    assert info["implicit_solves"] == info["applies"] * pl.nt
+    assert 1.0 <= cyc <= 20.0          # 63^2 interior, full hierarchy, tolerance 1e-12
+
+
+def test_implicit_fixed_point_history_matches_oracle():
+    w = inputs.small(seed=13, shape=(33, 33), nf=2, order=2)
+    prob, pl = workload.setup_implicit(w)
+    gp = _gp(w, imp_tol=TAU)
+    v, info = gp.fixed_point(max_iter=6)
+    Vr, r = omf.fixed_point(prob, pl, w["f"], 6)
+    assert rel(v.cpu().numpy(), Vr) < 6 * bar(w, prob, pl)
+    assert np.allclose(info["history"], r, rtol=1e-8)
+
+
+def test_implicit_multigrid_cycle_limit_is_reported():
+    L = _L()
+    w = inputs.small(seed=3, shape=(33, 33), nf=2, order=4)
+    gp = _gp(w, imp_tol=1e-15, imp_max_cycles=1)
+    V = torch.as_tensor(rand_v(w["shape"], 2, 1), device="cuda")
+    with pytest.raises(L.MfwhError) as ei:
+        gp.apply(V, forcing=True)
+    assert ei.value.code == -9
+
+
+def test_implicit_full_size_helmholtz_fixed_point():
+    """1025^2, order 4, the config-2 frequencies with 10 implicit steps per
+    shortest period: the DST-I discrete Helmholtz solution is mapped to itself
+    through all N_t multigrid-solved steps (a property at any size)."""
+    w = inputs.config2(0)
+    gp = _gp(w, filt="traditional", imp_tol=1e-12)
+    prob, _ = workload.setup(dict(w, f=None), filt="traditional")
+    U = np.stack([fd.helmholtz_dst(w["f"][m], w["omega"][m], prob.h, 4) for m in range(4)])
+    out = gp.apply(torch.as_tensor(U, device="cuda"), True).cpu().numpy()
+    e = rel(out, U)
+    # N_t tau cond(M) with cond(M) = 1 + dt^2/2 * 2 * 16/(3 h^2) ~ 7e2 here
+    lam = 2 * 16.0 / 3.0 / prob.h[0] ** 2
+    b = gp.nt * 1e-12 * (1 + 0.5 * gp.dt ** 2 * lam)
+    print(f"implicit 1025^2 fixed point: N_t={gp.nt} rel={e:.2e} bar={b:.1e}")
+    assert e < b
