@@ -43,21 +43,25 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
-# HBM traffic of the step kernel per launch from two rocprofv3 --pmc runs
-# (FETCH_SIZE, WRITE_SIZE), each scaled by the same counter on a plain 1 GiB
-# copy (profiles/k_step2d_fp64_2d-n1025-nf4.md).  Valid only for the kernel
-# source it was measured on: reported as null once kernels.hip changes.
-TRAFFIC = {"kernels_sha256_16": "990a9fd8587189b8", "fetch_bytes": 26278.9 * 1024 * 2.0,
-           "write_bytes": 40481.6 * 1024 * 1.0}
+# HBM traffic per launch of the dominant step kernel, from two rocprofv3
+# --pmc runs (FETCH_SIZE, WRITE_SIZE) on `python bench.py --mode apply`, each
+# scaled by the same counter on a plain 1 GiB copy (factors 2.0 and 1.0;
+# profiles/k_leap2d_x2_fp64_2d-n1025-nf4.md).  Keyed by (steps per pass, bx,
+# chunk) and valid only for the kernel source it was measured on: reported
+# as null for another configuration or once leap2d.hip changes.
+TRAFFIC = {"leap2d_sha256_16": None,
+           "bytes": {(2, 128, 4): 30911.5 * 1024 * 2.0 + 48668.0 * 1024 * 1.0}}
 
 
-def measured_traffic():
+def measured_traffic(cfg):
     import hashlib
-    src = os.path.join(ROOT, "paper_2507_23613_amd", "csrc", "kernels.hip")
+    src = os.path.join(ROOT, "paper_2507_23613_amd", "csrc", "leap2d.hip")
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
-    if sha != TRAFFIC["kernels_sha256_16"]:
+    if sha != TRAFFIC["leap2d_sha256_16"] or cfg not in TRAFFIC["bytes"]:
         return None
-    return round(TRAFFIC["fetch_bytes"] + TRAFFIC["write_bytes"])
+    return round(TRAFFIC["bytes"][cfg])
+
+
 METRIC = "grid-point-steps/s ×Nf filters (%HBM peak); time-to-1e-8 residual vs plain"
 
 
@@ -215,8 +219,8 @@ def implicit_bench(args):
     (omega = 5.1, 10.1, 15.1, N_p = 2, Gaussian sources of eq. Nf3parameters,
     adjusted traditional filter), order 4, trapezoid stepping with 10 steps
     per shortest period, multigrid step solves to 1e-10, on grids of 64 to
-    2048 cells per side.  For each grid: FPI wave solves to a residual
-    1e-10 times the first, average V-cycles per step solve, GPU time, and the
+    2048 cells per side.  For each grid: GMRES(30) wave solves to a relative
+    residual of 1e-10, average V-cycles per step solve, GPU time, and the
     time ratio to the previous grid (4 for O(N))."""
     import torch
     from paper_2507_23613_amd import _lib as L
@@ -225,14 +229,14 @@ def implicit_bench(args):
     rows, prev = [], None
     for n in (65, 129, 257, 513, 1025, 2049):
         w = inputs.paper_square128(n)
-        gp = GpuProblem(w, scheme=L.MFWH_IMPLICIT, imp_tol=1e-10, restart=0)
+        gp = GpuProblem(w, scheme=L.MFWH_IMPLICIT, imp_tol=1e-10, restart=30)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        _, info = gp.fixed_point(max_iter=200, tol=1e-10)
+        _, info = gp.gmres(max_iter=300, tol=1e-10)
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         row = {"cells": n - 1, "points": n * n, "nt": gp.nt, "wave_solves": info["applies"],
-               "fpi_iterations": info["iterations"], "rel_residual": info["rel_residual"],
+               "gmres_iterations": info["iterations"], "rel_residual": info["rel_residual"],
                "mg_cycles_per_step": round(info["mg_cycles"] / max(1, info["implicit_solves"]), 2),
                "gpu_s": round(el, 3), "ratio": round(el / prev, 2) if prev else None,
                "us_per_point_per_wave_solve": round(1e6 * el / (n * n * info["applies"]), 4)}
@@ -297,11 +301,11 @@ def main():
     RESTART = 128
     gp = GpuProblem(w, precision=L.MFWH_FP64, restart=RESTART)
     log(f"N_t={gp.nt} dt={gp.dt:.3e} interior={gp.interior_points}")
-    shape = None
+    spp, shape = args.spp, None
     if not args.no_tune and args.mode == "solve":
         from paper_2507_23613_amd import autotune
-        shape, _ = autotune.tune(gp, reps=2, log=log)
-        log(f"autotuned launch shape {shape}")
+        (spp, shape), _ = autotune.tune(gp, reps=2, log=log)
+        log(f"autotuned: {spp} steps per pass, launch shape {shape}")
 
     if args.mode == "apply":
         v = torch.randn((nf,) + tuple(w["shape"]), dtype=torch.float64, device="cuda")
@@ -346,11 +350,18 @@ def main():
     avg_us = 1e3 * kms / max(1, launches)
     bytes_per_launch = kbytes / max(1, launches)
     achieved = kbytes / (kms * 1e6) if kms > 0 else 0.0
+    bx, ch = (shape[0], shape[2]) if shape else (None, None)
+    kname = ("k_leap2d_x2" if spp == 2 else f"k_leap2d_xk (KS={spp})" if spp >= 3 else
+             "k_leap2d" if spp == 1 else "k_step2d")
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
-            "kernel": "k_step2d<double,2,128> (fused leapfrog + 4 filter updates)",
-            "timing": "HIP events around each replay of the recorded N_t-step sequence on "
-                      "the solver's stream, divided by N_t",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": measured_traffic((spp, bx, ch)),
+            "kernel": f"{kname}<double, order 4, bx {bx}, chunk {ch}>: {spp} fused leapfrog "
+                      f"steps + 4 filter updates per launch (forcing-free passes)",
+            "bytes_per_unit": "algorithmic per launch: interior points x (2 reads + 2 writes of "
+                              "W + read and write of each active float64 accumulator once)",
+            "timing": "HIP events around each replay of the recorded step sequence on the "
+                      "solver's stream, divided by its launches (first step and tail included)",
             "avg_launch_us": round(avg_us, 3), "bytes_per_launch": round(bytes_per_launch),
             "timed_launches": launches}
 
@@ -381,6 +392,7 @@ def main():
         "config": {"workload": f"{w['name']}-order4-cfl0.5-gmres{RESTART}-tol1e-8",
                    "grid": list(w["shape"]), "nf": nf, "np": int(w["np"]), "nt": gp.nt,
                    "gmres_iterations": its, "wave_solves": applies,
+                   "steps_per_pass": spp,
                    "launch_shape": list(shape) if shape else None,
                    "omega": np.round(w["omega"], 4).tolist()},
         "roofline": roof,

@@ -348,9 +348,10 @@ int mfwh_set_launch_shape(int bx, int by, int chunk);
  * 0 runs every step with the general step kernel, 1 with the streamlined 2D
  * kernel one step per launch, 2 with the streamlined kernel two steps per
  * launch (temporal blocking: W^{n+1} is recomputed on a halo and every filter
- * accumulator is read and written once per two steps).  All three compute
- * the same values up to floating-point contraction; 1D and 3D grids always
- * use the general kernel.
+ * accumulator is read and written once per two steps), 3 or 4 that many
+ * steps per launch for applications without forcing (with forcing: two).
+ * All compute the same values up to floating-point contraction; 1D and 3D
+ * grids always use the general kernel.
  * MFWH_OPT_PREFETCH_DEPTH (2 or 4; default 4): register sets of row operands
  * a wave of the streamlined 2D kernels rotates through, i.e. it requests the
  * operands of row y + depth - 1 before computing row y. */

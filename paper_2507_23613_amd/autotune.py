@@ -1,16 +1,24 @@
-"""Launch-shape autotuner for the fused step kernel.
+"""Launch-shape autotuner for the fused step kernels.
 
-Times one forcing-free application (N_t step launches, i.e. exactly the work
-of one GMRES matvec) of a problem for every candidate launch shape (threads
-along x, threads along y in 3D, rows/planes marched per block), keeps the
-fastest and installs it process-wide with ``mfwh_set_launch_shape``.  The
-sweep only changes how the grid is tiled, never the arithmetic.
+Times one forcing-free application (the work of one GMRES matvec) of a
+problem for every candidate configuration, keeps the fastest and installs it
+process-wide.  The candidates are:
+- the launch shape (threads along x, threads along y in 3D, rows or planes
+  marched per block), set with ``mfwh_set_launch_shape``;
+- in 2D, also the steps fused per launch, set with ``MFWH_OPT_STEPS_PER_PASS``.
+
+The sweep changes how the work is tiled and fused, never the arithmetic.
 """
 import torch
 
 from . import _lib as L
 
 CAND_2D = [(bx, 1, ch) for bx in (64, 128, 256) for ch in (2, 4, 8, 16, 32, 64)]
+# (steps per pass, shape): two-step passes over the 2D shapes, three and four
+# steps with 128 lanes and short chunks (the pass recomputes 2 (steps-1) R rows
+# per chunk, so long chunks starve small grids of blocks)
+CAND_2D_PASS = [(2, (bx, 1, ch)) for bx in (64, 128) for ch in (2, 4, 8, 16)] + \
+               [(k, (128, 1, ch)) for k in (3, 4) for ch in (4, 6, 8, 12, 16)]
 CAND_3D = [(64, 4, ch) for ch in (2, 4, 8, 16, 32)] + \
           [(64, 8, ch) for ch in (4, 8, 16)] + [(128, 2, ch) for ch in (4, 8, 16)] + \
           [(32, 8, ch) for ch in (4, 8)]
@@ -29,24 +37,34 @@ def _time_apply(gp, v, out, reps):
 
 
 def tune(gp, reps=2, candidates=None, log=None):
-    """Returns (best_shape, {shape: ms per application}) and installs the best.
+    """Returns (best, {candidate: ms per application}) and installs the best.
 
-    ``gp``: a GpuProblem (its workspace and time grid are used).  mfwh_apply
-    runs on the current torch stream, so torch events time it."""
+    ``gp``: a GpuProblem (its workspace and time grid are used).  In 2D a
+    candidate is (steps per pass, shape), elsewhere a shape.  mfwh_apply runs
+    on the current torch stream, so torch events time it."""
     dim = len(gp.shape)
     if candidates is None:
-        candidates = CAND_2D if dim == 2 else CAND_3D if dim == 3 else [(64, 1, 1)]
+        candidates = CAND_2D_PASS if dim == 2 else CAND_3D if dim == 3 else [(64, 1, 1)]
     v = torch.randn((gp.nf,) + gp.shape, dtype=torch.float64, device=gp.device)
     out = torch.empty_like(v)
     times = {}
+
+    def install(c):
+        if dim == 2:
+            L.mfwh_set_option(L.MFWH_OPT_STEPS_PER_PASS, c[0])
+            L.mfwh_set_launch_shape(*c[1])
+        else:
+            L.mfwh_set_launch_shape(*c)
+
     try:
-        for shp in candidates:
-            L.mfwh_set_launch_shape(*shp)
-            times[shp] = _time_apply(gp, v, out, reps)
+        for c in candidates:
+            install(c)
+            times[c] = _time_apply(gp, v, out, reps)
             if log:
-                log(f"autotune {shp}: {times[shp]:.3f} ms per application")
+                log(f"autotune {c}: {times[c]:.3f} ms per application")
     finally:
         L.mfwh_set_launch_shape(0)
+        L.mfwh_set_option(L.MFWH_OPT_STEPS_PER_PASS, 2)
     best = min(times, key=times.get)
-    L.mfwh_set_launch_shape(*best)
+    install(best)
     return best, times

@@ -113,7 +113,7 @@ ExtLayout int_layout(const Geom& G) {
 }
 
 constexpr int kRedBlocks = 1024;   // reduction blocks of the finalize/BLAS kernels
-constexpr int kMaxLev = 16;        // multigrid levels at most
+constexpr int kMaxLev = kMgMaxLev;  // multigrid levels at most
 
 struct Workspace {
   double *w64a = nullptr, *w64b = nullptr, *f64 = nullptr, *c64 = nullptr;
@@ -247,6 +247,7 @@ struct Problem {
   int applies = 0;
   bool implicit = false;             // trapezoid scheme with multigrid step solves
   long long imp_solves = 0, mg_cycles = 0;
+  int mg_prev = 0;                   // V-cycles the previous step solve needed
   StepGraph sg[2][2];                // [float32][forcing]
   ~Problem() {
     for (auto& a : sg)
@@ -369,15 +370,39 @@ double jacobi_weight(int order) { return order == 4 ? 10.0 / 13.0 : 0.8; }
 
 // One V-cycle on level l for M_l x = b (x updated in place; level 0 uses the
 // caller's x and b, coarser levels the workspace).
+int coarse_sweeps(const MgLevel& L) {
+  // coarsest level: a fixed even number of Jacobi sweeps
+  return (int)std::min<long long>(64, 2 * ((std::max(L.nx, L.ny) + 1) / 2) + 8);
+}
+
 int vcycle(Problem& pr, int l, double* x, const double* b) {
   Workspace& W = pr.W;
   const MgLevel& L = W.lev[l];
   const int order = l == 0 ? pr.grid->order : 2;
   const double w = jacobi_weight(order);
   double* t = W.mt[l];
+  if ((long long)L.nx * L.ny <= kMgCoarseMax && l < W.nlev - 1) {
+    // this level and every coarser one: one single-workgroup launch
+    MgCoarse mc{};
+    for (int k = l; k < W.nlev; ++k) {
+      mc.lev[k] = W.lev[k];
+      mc.x[k] = k == l ? x : W.mx[k];
+      mc.b[k] = k == l ? const_cast<double*>(b) : W.mb[k];
+      mc.t[k] = W.mt[k];
+      mc.r[k] = W.mr[k];
+      mc.order[k] = k == 0 ? pr.grid->order : 2;
+      mc.w[k] = jacobi_weight(mc.order[k]);
+    }
+    mc.lc = l;
+    mc.nlev = W.nlev;
+    mc.pre = kPre;
+    mc.post = kPost;
+    mc.coarse_sweeps = coarse_sweeps(W.lev[W.nlev - 1]);
+    HIPCHK(launch_mg_coarse(mc, pr.s));
+    return MFWH_OK;
+  }
   if (l == W.nlev - 1) {
-    // coarsest level: a fixed even number of sweeps
-    const int sweeps = (int)std::min<long long>(64, 2 * ((std::max(L.nx, L.ny) + 1) / 2) + 8);
+    const int sweeps = coarse_sweeps(L);
     for (int k = 0; k < sweeps; k += 2) {
       HIPCHK(launch_mg_jacobi(L, order, x, b, t, w, pr.s));
       HIPCHK(launch_mg_jacobi(L, order, t, b, x, w, pr.s));
@@ -405,7 +430,12 @@ int mg_solve(Problem& pr, double* x, const double* b) {
   const MgLevel& L = W.lev[0];
   double* out2 = W.scal + W.nscal - 16;
   const double tol = pr.P.imp_tol;
-  for (int cyc = 1;; ++cyc) {
+  // the cycles the previous step needed, less one, run without a check (one
+  // host synchronisation per step in the steady state)
+  const int blind = std::max(0, std::min(pr.mg_prev - 1, pr.P.imp_max_cycles - 1));
+  for (int k = 0; k < blind; ++k) CHK(vcycle(pr, 0, x, b));
+  pr.mg_cycles += blind;
+  for (int cyc = blind + 1;; ++cyc) {
     CHK(vcycle(pr, 0, x, b));
     HIPCHK(launch_mg_resid(L, pr.grid->order, x, b, nullptr, W.partial, kRedBlocks, out2, pr.s));
     double h2[2];
@@ -418,7 +448,10 @@ int mg_solve(Problem& pr, double* x, const double* b) {
       HIPCHK(launch_fill_t<double>(x, (long long)L.py * L.ny, 0.0, pr.s));
       break;
     }
-    if (h2[0] <= tol * tol * h2[1]) break;
+    if (h2[0] <= tol * tol * h2[1]) {
+      pr.mg_prev = cyc;
+      break;
+    }
     if (cyc >= pr.P.imp_max_cycles)
       return fail(MFWH_ENOTCONV_MG, "multigrid did not reach imp_tol in imp_max_cycles V-cycles");
   }
@@ -549,16 +582,21 @@ int apply_t(Problem& pr, const double* v, ExtLayout vl, bool forcing, const Out&
     T* spare[2] = {wc4, wd4};
     int n = 0;
     while (n < P.nt) {
-      const int kind = n == 0 ? 0 : spp == 2 && n + 1 < P.nt ? 2 : spp >= 1 ? 1 : 0;
+      // passes of three or four steps run without forcing only
+      const int kind = n == 0                                       ? 0
+                       : (spp >= 3 && !forcing && n + spp <= P.nt) ? spp
+                       : (spp >= 2 && n + 1 < P.nt)                 ? 2
+                       : spp >= 1                                   ? 1
+                                                                    : 0;
       Op op{n, kind, cur, prev, prev, nullptr};
-      if (kind == 2) {
+      if (kind >= 2) {
         op.w1 = spare[0];
         op.w2 = spare[1];
         spare[0] = prev;
         spare[1] = cur;
         prev = op.w1;
         cur = op.w2;
-        n += 2;
+        n += kind;
       } else {
         prev = cur;
         cur = op.w1;
@@ -573,7 +611,7 @@ int apply_t(Problem& pr, const double* v, ExtLayout vl, bool forcing, const Out&
   // step), write the new fields, forcing and c^2 once, read+write every
   // accumulator active in the pass once (write only on the first step)
   auto op_bytes = [&](const Op& op) {
-    const int ns = op.kind == 2 ? 2 : 1;
+    const int ns = op.kind >= 2 ? op.kind : 1;
     const bool first = op.n == 0;
     int nact = 0;
     for (int m = 0; m < nf; ++m) {
@@ -581,7 +619,7 @@ int apply_t(Problem& pr, const double* v, ExtLayout vl, bool forcing, const Out&
       for (int k = 0; k < ns; ++k) on = on || active(op.n + k, m);
       nact += on ? 1 : 0;
     }
-    return ((first ? 1 : 2) * sort + ns * sort + (forcing ? nf * sort : 0) +
+    return ((first ? 1 : 2) * sort + std::min(ns, 2) * sort + (forcing ? nf * sort : 0) +
             (first ? 1 : 2) * 8.0 * nact + (pr.varc ? sort : 0)) * npts;
   };
   auto launch_op = [&](const Op& op, hipStream_t s) -> hipError_t {
@@ -622,15 +660,15 @@ int apply_t(Problem& pr, const double* v, ExtLayout vl, bool forcing, const Out&
     for (int m = 0; m < MFWH_MAX_NF; ++m) {
       la.phi1[m] = (forcing && m < nf) ? (T)P.phi[(size_t)n * nf + m] : T(0);
       la.phi2[m] = (forcing && m < nf && ns == 2) ? (T)P.phi[(size_t)(n + 1) * nf + m] : T(0);
-      la.k1[m] = la.k2[m] = 0.0;
+      for (int k = 0; k < 4; ++k) la.kk[k][m] = 0.0;
       la.qm[m] = 0;
     }
     for (int m = 0; m < nf; ++m) {
-      const bool on1 = active(n, m), on2 = ns == 2 && active(n + 1, m);
-      if (!on1 && !on2) continue;
+      bool on = false;
+      for (int k = 0; k < ns; ++k) on = on || active(n + k, m);
+      if (!on) continue;
       la.qm[nq] = m;
-      la.k1[nq] = P.kappa[(size_t)(n + 1) * nf + m];
-      la.k2[nq] = ns == 2 ? P.kappa[(size_t)(n + 2) * nf + m] : 0.0;
+      for (int k = 0; k < ns; ++k) la.kk[k][nq] = P.kappa[(size_t)(n + 1 + k) * nf + m];
       ++nq;
     }
     la.nq = nq;
@@ -1621,7 +1659,7 @@ int mfwh_set_option(int key, long long value) {
       g_graphs = value != 0;
       return MFWH_OK;
     case MFWH_OPT_STEPS_PER_PASS:
-      if (value < 0 || value > 2) return fail(MFWH_EINVAL, "steps per pass must be 0, 1 or 2");
+      if (value < 0 || value > 4) return fail(MFWH_EINVAL, "steps per pass must be 0 .. 4");
       g_steps_per_pass = (int)value;
       return MFWH_OK;
     case MFWH_OPT_PREFETCH_DEPTH:

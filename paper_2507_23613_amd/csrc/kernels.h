@@ -83,11 +83,12 @@ struct LaunchShape {
 };
 
 // Arguments of the streamlined 2D leapfrog kernels (every step after the
-// first).  One launch advances one step (W^n, W^{n-1} -> W^{n+1}) or two
-// (-> W^{n+1}, W^{n+2}); per step
+// first).  One launch advances KS = 1..4 steps (W^n, W^{n-1} -> W^{n+1} ..
+// W^{n+KS}; three and four only without forcing); per step
 //   W^{k+1} = cA W^k + cB W^{k-1} + cC (c^2 Delta_h W^k - sum_m phi_m f_m)
 // and, for the nq active accumulators (compact slot j -> field qm[j]),
-//   q_{qm[j]} += k1[j] W^{n+1} (+ k2[j] W^{n+2}).
+//   q_{qm[j]} += kk[0][j] W^{n+1} + ... + kk[KS-1][j] W^{n+KS}.
+// w1/w2 receive the last two fields (W^{n+1}, W^{n+2} for KS = 2).
 template <typename T>
 struct LeapArgs {
   const T* wc;          // W^n
@@ -101,16 +102,17 @@ struct LeapArgs {
   T wx[3], wy[3];
   T cA, cB, cC;
   T phi1[MFWH_MAX_NF], phi2[MFWH_MAX_NF];
-  double k1[MFWH_MAX_NF], k2[MFWH_MAX_NF];
+  double kk[4][MFWH_MAX_NF];
   int qm[MFWH_MAX_NF];  // slots nq.. repeat slot nq-1 (they are loaded, never stored)
   int nq;               // active accumulators
   int force;
   int chunk, nchunk, ntx, nblocks;
 };
 
-// Launch one streamlined 2D step (steps == 1) or two fused steps
-// (steps == 2) with shape ls (bx in {64, 128, 256}) and `depth` rows of
-// operands in flight per wave (2 or 4); fills the tiling fields.
+// Launch one streamlined 2D pass of `steps` fused steps (1, 2; 3 or 4
+// without forcing) with shape ls (bx in {64, 128, 256}; 128 or 256 for 3 and
+// 4 steps) and `depth` rows of operands in flight per wave (2 or 4; 4 for 3
+// and 4 steps); fills the tiling fields.
 template <typename T>
 hipError_t launch_leap2d(LeapArgs<T>& a, int order, int steps, int depth, const LaunchShape& ls,
                          hipStream_t s);
@@ -154,6 +156,24 @@ struct ImpAccum {
   double kap[MFWH_MAX_NF], kap0[MFWH_MAX_NF];
   int nf, mask, first;
 };
+
+// The bottom of a V-cycle, levels lc .. nlev-1, in one single-workgroup
+// launch (every level at most kMgCoarseMax points): pre-smoothing, residual,
+// restriction down; `coarse_sweeps` Jacobi sweeps on the coarsest; prolongation
+// and post-smoothing up.  x[lc] and b[lc] hold the level-lc problem.
+constexpr int kMgMaxLev = 16;
+constexpr int kMgCoarseMax = 1024;
+struct MgCoarse {
+  MgLevel lev[kMgMaxLev];
+  double* x[kMgMaxLev];
+  double* b[kMgMaxLev];
+  double* t[kMgMaxLev];
+  double* r[kMgMaxLev];
+  double w[kMgMaxLev];      // Jacobi weight per level
+  int order[kMgMaxLev];     // 2 or 4 per level
+  int lc, nlev, pre, post, coarse_sweeps;
+};
+hipError_t launch_mg_coarse(const MgCoarse& a, hipStream_t s);
 
 hipError_t launch_mg_jacobi(const MgLevel& L, int order, const double* x, const double* b,
                             double* y, double w, hipStream_t s);

@@ -159,7 +159,7 @@ __global__ void __launch_bounds__(BX) k_leap2d(LeapArgs<T> a) {
       const double wd = (double)wn;
 #pragma unroll
       for (int j = 0; j < QM; ++j)
-        if (j < a.nq) a.q[a.qm[j] * fs + idx] = o.q[j] + a.k1[j] * wd;
+        if (j < a.nq) a.q[a.qm[j] * fs + idx] = o.q[j] + a.kk[0][j] * wd;
     }
   };
 
@@ -310,7 +310,7 @@ __global__ void __launch_bounds__(BX) k_leap2d_x2(LeapArgs<T> a) {
       const double d1 = (double)w1[R], d2 = (double)v2;
 #pragma unroll
       for (int j = 0; j < QM; ++j)
-        if (j < a.nq) a.q[a.qm[j] * fs + idx] = (o.q[j] + a.k1[j] * d1) + a.k2[j] * d2;
+        if (j < a.nq) a.q[a.qm[j] * fs + idx] = (o.q[j] + a.kk[0][j] * d1) + a.kk[1][j] * d2;
     }
   };
 
@@ -339,6 +339,181 @@ __global__ void __launch_bounds__(BX) k_leap2d_x2(LeapArgs<T> a) {
         fetch(rs[(u + PD - 1) % PD], min(r + u + PD - 1, y1 - 1));
         process(r + u, rs[u], rn[u & 1], r1[u & 1]);
       }
+    }
+  }
+}
+
+// -------------------------------------------------------------------------
+// KS steps per pass, forcing-free (GMRES matvecs)
+// -------------------------------------------------------------------------
+// Level j = 1..KS is W^{n+j}; in iteration r it is computed on row
+// e_j = r + (KS - j) R, so level j's stencil rows (e_j - R .. e_j + R of
+// level j-1) are complete when it runs.  Level 0 is W^n (loaded; newest row
+// r + KS R).  Level j keeps its newest rows in a register window: 2R + 1
+// rows for the next level's stencil, and back to row r, (KS - j) R rows
+// behind its newest, for the accumulators -- every accumulator is read and
+// written once per KS steps.  A block owns BX - 2 KS R columns; level j is
+// computed on lanes jR .. BX - jR - 1 and on R (KS - j) extra rows at each
+// chunk end, so the pass needs nothing from other blocks.  Only W^{n+KS-1}
+// and W^{n+KS} are written.
+template <int R, int KS>
+struct XkShape {
+  static constexpr int len(int j) {   // window length of level j (0 .. KS-1)
+    return j == 0 ? 2 * R + 1
+                  : ((KS - j) * R + 1 > 2 * R + 1 ? (KS - j) * R + 1 : 2 * R + 1);
+  }
+  static constexpr int off(int j) {   // offset of level j in the flat window array
+    return j == 0 ? 0 : off(j - 1) + len(j - 1);
+  }
+  static constexpr int total = off(KS);
+  static constexpr int clen = (KS - 1) * R + 1;   // c^2 of rows e_KS .. e_1
+};
+
+template <typename T, int QM>
+struct RowK {
+  T w, sw;        // new W^n row value and its extension factor
+  T p;            // W^{n-1} at the first level's row
+  T c;            // c^2 at the first level's row
+  double q[QM];   // accumulators at row r
+};
+
+template <typename T, int R, int BX, int QM, int KS, int PD>
+__global__ void __launch_bounds__(BX) k_leap2d_xk(LeapArgs<T> a) {
+  using S = XkShape<R, KS>;
+  constexpr int OW = BX - 2 * KS * R;
+  __shared__ T lds[2][KS][BX];            // x-neighbour rows of levels 0 .. KS-1
+  const int lb = xcd_tile(blockIdx.x, gridDim.x);
+  if (lb >= a.nblocks) return;
+  const int bx = lb / a.nchunk;
+  const int by = lb - bx * a.nchunk;
+  const int l = threadIdx.x;
+  const int nxi = a.g.nxi, nyi = a.g.nyi;
+  const long long py = a.g.py, fs = a.g.fs;
+  const int x0 = bx * OW;
+  const int e = x0 - KS * R + l;          // column of this lane
+  T xs;
+  const int ix = ext_src(e, nxi, xs);
+  const bool inx = e >= 0 && e < nxi;
+  const bool own = inx && l >= KS * R && l < BX - KS * R;
+  const int qcol = min(max(e, x0), min(x0 + OW, nxi) - 1);   // an owned column
+  const T* __restrict__ c2p = a.c2 ? a.c2 : a.wp;            // read and ignored when c = 1
+  const int y0 = by * a.chunk;
+  const int y1 = min(y0 + a.chunk, nyi);
+  const T* __restrict__ wc = a.wc;
+  auto ldw = [&](int y, T& sg) -> T {
+    T sy;
+    const int iy = ext_src(y, nyi, sy);
+    sg = xs * sy;
+    return wc[(long long)iy * py + ix];
+  };
+
+  T wv[S::total];      // windows of levels 0 .. KS-1 (newest last)
+  T cw[S::clen];       // c^2 of rows e_KS .. e_1 (newest last)
+  const int r0 = y0 - 2 * (KS - 1) * R;
+#pragma unroll
+  for (int k = 0; k < S::total; ++k) wv[k] = T(0);
+#pragma unroll
+  for (int k = 0; k < S::clen; ++k) cw[k] = T(1);
+#pragma unroll
+  for (int k = 0; k < 2 * R; ++k) {       // W^n rows before the first iteration's newest
+    T sg;
+    const T v = ldw(r0 + KS * R - 2 * R + k, sg);
+    wv[k + 1] = sg * v;
+  }
+
+  auto fetch = [&](RowK<T, QM>& o, int r) {
+    o.w = ldw(r + KS * R, o.sw);
+    const int e1 = min(max(r + (KS - 1) * R, 0), nyi - 1);
+    const long long i1 = (long long)e1 * py + ix;
+    o.p = a.wp[i1];
+    o.c = c2p[i1];
+    const long long i2 = (long long)max(r, y0) * py + qcol;
+#pragma unroll
+    for (int j = 0; j < QM; ++j) o.q[j] = a.q[a.qm[j] * fs + i2];
+  };
+
+  auto process = [&](int r, const RowK<T, QM>& o, int buf) {
+    // shift every window by one row; level 0 takes the new W^n row
+#pragma unroll
+    for (int j = 0; j < KS; ++j) {
+#pragma unroll
+      for (int k = 0; k < S::len(j) - 1; ++k) wv[S::off(j) + k] = wv[S::off(j) + k + 1];
+    }
+    wv[S::off(0) + 2 * R] = o.sw * o.w;
+#pragma unroll
+    for (int k = 0; k < S::clen - 1; ++k) cw[k] = cw[k + 1];
+    cw[S::clen - 1] = a.c2 ? o.c : T(1);
+    // x-neighbour rows: level j's row e_{j+1} = e_j - R (level 0: index R)
+#pragma unroll
+    for (int j = 0; j < KS; ++j) {
+      const T v = j == 0 ? wv[R] : wv[S::off(j) + S::len(j) - 1 - R];
+      T* rb = lds[buf][j];
+      if (j == 0 || !(R == 2 && (e == -2 || e == nxi + 1))) rb[l] = v;
+      if (j > 0 && R == 2 && e == 0) rb[l - 2] = -v;
+      if (j > 0 && R == 2 && e == nxi - 1 && l + 2 < BX) rb[l + 2] = -v;
+    }
+    __syncthreads();
+    T vk = T(0);                          // W^{n+KS} on row r
+#pragma unroll
+    for (int j = 1; j <= KS; ++j) {
+      const int ej = r + (KS - j) * R;
+      // level j-1 around row ej: its centre index (level 0: R)
+      const int cj = j == 1 ? R : S::off(j - 1) + S::len(j - 1) - 1 - R;
+      const int b0 = j == 1 ? 0 : S::off(j - 1);
+      const T* rb = lds[buf][j - 1];
+      T v = T(0);
+      const bool comp = inx && l >= j * R && l < BX - j * R && ej >= 0 && ej < nyi;
+      if (comp) {
+        const T cen = wv[b0 + (cj - b0)];
+        T lap = (a.wx[0] + a.wy[0]) * cen;
+#pragma unroll
+        for (int k = 1; k <= R; ++k)
+          lap += a.wx[k] * (rb[l - k] + rb[l + k]) + a.wy[k] * (wv[cj - k] + wv[cj + k]);
+        // W^{n+j-2} on row ej: W^{n-1} (prefetched), W^n (level 0 oldest) or
+        // level j-2, 2R rows behind its newest
+        const T prev = j == 1 ? o.p
+                     : j == 2 ? wv[0]
+                              : wv[S::off(j - 2) + S::len(j - 2) - 1 - 2 * R];
+        const T c2v = cw[S::clen - 1 - (j - 1) * R];
+        v = a.cA * cen + a.cB * prev + a.cC * (c2v * lap);
+      }
+      if (j < KS) {
+        const int base = S::off(j), last = base + S::len(j) - 1;
+        if (R == 2 && ej == nyi + 1) v = -wv[last - 2];   // ghost row: reflects row nyi-1
+        wv[last] = v;
+        if (R == 2 && ej == 0) wv[last - 2] = -v;         // ghost row -2 reflects row 0
+      } else {
+        vk = v;
+      }
+    }
+    if (r >= y0 && own) {
+      const long long idx = (long long)r * py + e;
+      constexpr int ip = S::off(KS - 1) + S::len(KS - 1) - 1 - R;   // level KS-1, row r
+      a.w1[idx] = wv[ip];
+      a.w2[idx] = vk;
+#pragma unroll
+      for (int q = 0; q < QM; ++q) {
+        if (q < a.nq) {
+          double acc = o.q[q];
+#pragma unroll
+          for (int j = 1; j < KS; ++j)
+            acc += a.kk[j - 1][q] * (double)wv[S::off(j) + S::len(j) - 1 - (KS - j) * R];
+          acc += a.kk[KS - 1][q] * (double)vk;
+          a.q[a.qm[q] * fs + idx] = acc;
+        }
+      }
+    }
+  };
+
+  RowK<T, QM> rs[PD];
+#pragma unroll
+  for (int u = 0; u < PD - 1; ++u) fetch(rs[u], min(r0 + u, y1 - 1));
+  for (int r = r0; r < y1; r += PD) {
+#pragma unroll
+    for (int u = 0; u < PD; ++u) {
+      if (r + u >= y1) break;
+      fetch(rs[(u + PD - 1) % PD], min(r + u + PD - 1, y1 - 1));
+      process(r + u, rs[u], u & 1);
     }
   }
 }
@@ -386,11 +561,26 @@ hipError_t launch_pd(LeapArgs<T>& a, int steps, int grid, hipStream_t s) {
 template <typename T, int R, int BX>
 hipError_t launch_bx(LeapArgs<T>& a, int steps, int depth, hipStream_t s) {
   const Geom& g = a.g;
-  const int ow = steps == 2 ? BX - 4 * R : BX;
+  const int ow = steps >= 2 ? BX - 2 * steps * R : BX;
   a.ntx = (g.nxi + ow - 1) / ow;
   a.nchunk = (g.nyi + a.chunk - 1) / a.chunk;
   a.nblocks = a.ntx * a.nchunk;
   const int grid = pad8(a.nblocks);
+  if (steps >= 3) {
+    if constexpr (BX >= 128) {
+      const bool q4 = a.nq <= 4;
+      if (depth != 4 || a.force) return hipErrorInvalidValue;
+      if (steps == 3) {
+        if (q4) k_leap2d_xk<T, R, BX, 4, 3, 4><<<grid, BX, 0, s>>>(a);
+        else k_leap2d_xk<T, R, BX, 8, 3, 4><<<grid, BX, 0, s>>>(a);
+      } else {
+        if (q4) k_leap2d_xk<T, R, BX, 4, 4, 4><<<grid, BX, 0, s>>>(a);
+        else k_leap2d_xk<T, R, BX, 8, 4, 4><<<grid, BX, 0, s>>>(a);
+      }
+      return hipGetLastError();
+    }
+    return hipErrorInvalidValue;
+  }
   switch (depth) {
     case 2: return launch_pd<T, R, BX, 2>(a, steps, grid, s);
     case 4: return launch_pd<T, R, BX, 4>(a, steps, grid, s);
@@ -414,9 +604,9 @@ hipError_t launch_r(LeapArgs<T>& a, int steps, int depth, const LaunchShape& ls,
 template <typename T>
 hipError_t launch_leap2d(LeapArgs<T>& a, int order, int steps, int depth, const LaunchShape& ls,
                          hipStream_t s) {
-  if (a.g.dim != 2 || (steps != 1 && steps != 2) || a.nq < 0 || a.nq > MFWH_MAX_NF)
+  if (a.g.dim != 2 || steps < 1 || steps > 4 || a.nq < 0 || a.nq > MFWH_MAX_NF)
     return hipErrorInvalidValue;
-  if (steps == 2 && (a.w1 == a.wc || a.w1 == a.wp || a.w2 == a.wc || a.w2 == a.wp ||
+  if (steps >= 2 && (a.w1 == a.wc || a.w1 == a.wp || a.w2 == a.wc || a.w2 == a.wp ||
                      a.w1 == a.w2 || !a.w2))
     return hipErrorInvalidValue;
   a.chunk = std::max(1, ls.chunk);
@@ -431,13 +621,16 @@ template hipError_t launch_leap2d<float>(LeapArgs<float>&, int, int, int, const 
 LaunchShape default_leap_shape(const Geom& g, int steps) {
   LaunchShape ls;
   ls.by = 1;
-  ls.bx = g.nxi > 512 ? 128 : 64;
-  const int ow = steps == 2 ? ls.bx - 8 : ls.bx;
+  ls.bx = (g.nxi > 512 || steps >= 3) ? 128 : 64;
+  const int ow = steps >= 2 ? ls.bx - 4 * steps : ls.bx;   // order-4 halo
   const long long strips = (g.nxi + ow - 1) / ow;
   const long long waves_per_row = strips * (ls.bx / 64);
   const long long target_waves = 256LL * 16;
   long long ch = waves_per_row * g.nyi / target_waves;
-  ls.chunk = (int)std::min<long long>(std::max<long long>(ch, 4), 64);
+  // three and four steps per pass recompute 2 (steps - 1) R rows per chunk;
+  // longer chunks leave a 1023^2 grid too few blocks (measured: 8 is best)
+  const long long lo = steps >= 3 ? 8 : 4;
+  ls.chunk = (int)std::min<long long>(std::max<long long>(ch, lo), 64);
   return ls;
 }
 

@@ -253,6 +253,117 @@ __global__ void __launch_bounds__(kNT) k_imp_accum(ImpAccum a) {
   }
 }
 
+// The bottom of a V-cycle in one launch: levels lc .. nlev-1 (each at most
+// kCoarseMax points) by a single workgroup, with a barrier between the
+// passes.  Same operations as the per-level kernels; saves the launch
+// overhead of the small levels, which otherwise dominates the cycle.
+constexpr int kCT = 1024;
+
+template <int R>
+__device__ void co_jacobi(const MgLevel& L, const double* x, const double* b, double* y,
+                          double w) {
+  const int n = L.nx * L.ny;
+  for (int p = threadIdx.x; p < n; p += kCT) {
+    const int j = p / L.nx, i = p - j * L.nx;
+    const long long idx = (long long)j * L.py + i;
+    const double xc = x[idx];
+    const double c2 = L.c2 ? L.c2[idx] : 1.0;
+    const double mx = xc - c2 * klap<R>(x, L, i, j, xc);
+    y[idx] = xc + w * (b[idx] - mx) / mdiag<R>(L, i, j, c2);
+  }
+  __syncthreads();
+}
+
+template <int R>
+__device__ void co_resid(const MgLevel& L, const double* x, const double* b, double* r) {
+  const int n = L.nx * L.ny;
+  for (int p = threadIdx.x; p < n; p += kCT) {
+    const int j = p / L.nx, i = p - j * L.nx;
+    const long long idx = (long long)j * L.py + i;
+    const double xc = x[idx];
+    const double c2 = L.c2 ? L.c2[idx] : 1.0;
+    r[idx] = b[idx] - (xc - c2 * klap<R>(x, L, i, j, xc));
+  }
+  __syncthreads();
+}
+
+__global__ void __launch_bounds__(kCT) k_mg_coarse(MgCoarse a) {
+  // down: smooth, residual, restrict
+  for (int l = a.lc; l < a.nlev - 1; ++l) {
+    const MgLevel& L = a.lev[l];
+    const MgLevel& C = a.lev[l + 1];
+    for (int k = 0; k < a.pre; k += 2) {
+      if (a.order[l] == 4) {
+        co_jacobi<2>(L, a.x[l], a.b[l], a.t[l], a.w[l]);
+        co_jacobi<2>(L, a.t[l], a.b[l], a.x[l], a.w[l]);
+      } else {
+        co_jacobi<1>(L, a.x[l], a.b[l], a.t[l], a.w[l]);
+        co_jacobi<1>(L, a.t[l], a.b[l], a.x[l], a.w[l]);
+      }
+    }
+    if (a.order[l] == 4) co_resid<2>(L, a.x[l], a.b[l], a.r[l]);
+    else co_resid<1>(L, a.x[l], a.b[l], a.r[l]);
+    const int nc = C.nx * C.ny;
+    for (int p = threadIdx.x; p < nc; p += kCT) {
+      const int J = p / C.nx, I = p - J * C.nx;
+      const int i = 2 * I + 1, j = 2 * J + 1;
+      const double* rf = a.r[l];
+      auto v = [&](int q, int c) { return rf[(long long)c * L.py + q]; };
+      const double s = 4.0 * v(i, j) + 2.0 * (v(i - 1, j) + v(i + 1, j) + v(i, j - 1) + v(i, j + 1)) +
+                       (v(i - 1, j - 1) + v(i + 1, j - 1) + v(i - 1, j + 1) + v(i + 1, j + 1));
+      const long long o = (long long)J * C.py + I;
+      a.b[l + 1][o] = s * (1.0 / 16.0);
+      a.x[l + 1][o] = 0.0;
+    }
+    __syncthreads();
+  }
+  // coarsest level
+  {
+    const int l = a.nlev - 1;
+    const MgLevel& L = a.lev[l];
+    for (int k = 0; k < a.coarse_sweeps; k += 2) {
+      if (a.order[l] == 4) {
+        co_jacobi<2>(L, a.x[l], a.b[l], a.t[l], a.w[l]);
+        co_jacobi<2>(L, a.t[l], a.b[l], a.x[l], a.w[l]);
+      } else {
+        co_jacobi<1>(L, a.x[l], a.b[l], a.t[l], a.w[l]);
+        co_jacobi<1>(L, a.t[l], a.b[l], a.x[l], a.w[l]);
+      }
+    }
+  }
+  // up: prolong, smooth
+  for (int l = a.nlev - 2; l >= a.lc; --l) {
+    const MgLevel& F = a.lev[l];
+    const MgLevel& C = a.lev[l + 1];
+    const int nf = F.nx * F.ny;
+    const double* ec = a.x[l + 1];
+    for (int p = threadIdx.x; p < nf; p += kCT) {
+      const int j = p / F.nx, i = p - j * F.nx;
+      auto e = [&](int I, int J) -> double {
+        return (I >= 0 && I < C.nx && J >= 0 && J < C.ny) ? ec[(long long)J * C.py + I] : 0.0;
+      };
+      const int I0 = (i - 1) >> 1, J0 = (j - 1) >> 1;
+      const bool xo = i & 1, yo = j & 1;
+      double v;
+      if (xo && yo) v = e(I0, J0);
+      else if (xo) v = 0.5 * (e(I0, J0) + e(I0, J0 + 1));
+      else if (yo) v = 0.5 * (e(I0, J0) + e(I0 + 1, J0));
+      else v = 0.25 * (e(I0, J0) + e(I0 + 1, J0) + e(I0, J0 + 1) + e(I0 + 1, J0 + 1));
+      a.x[l][(long long)j * F.py + i] += v;
+    }
+    __syncthreads();
+    for (int k = 0; k < a.post; k += 2) {
+      if (a.order[l] == 4) {
+        co_jacobi<2>(F, a.x[l], a.b[l], a.t[l], a.w[l]);
+        co_jacobi<2>(F, a.t[l], a.b[l], a.x[l], a.w[l]);
+      } else {
+        co_jacobi<1>(F, a.x[l], a.b[l], a.t[l], a.w[l]);
+        co_jacobi<1>(F, a.t[l], a.b[l], a.x[l], a.w[l]);
+      }
+    }
+  }
+}
+
 int blocks_for(long long n) {
   return (int)std::max<long long>(1, std::min<long long>((n + kNT - 1) / kNT, 8192));
 }
@@ -291,6 +402,11 @@ hipError_t launch_mg_prolong(const MgLevel& C, const double* ec, const MgLevel& 
 hipError_t launch_mg_inject(const MgLevel& F, const double* cf, const MgLevel& C, double* cc,
                             hipStream_t s) {
   k_mg_inject<<<blocks_for((long long)C.nx * C.ny), kNT, 0, s>>>(F, cf, C, cc);
+  return hipGetLastError();
+}
+
+hipError_t launch_mg_coarse(const MgCoarse& a, hipStream_t s) {
+  k_mg_coarse<<<1, kCT, 0, s>>>(a);
   return hipGetLastError();
 }
 

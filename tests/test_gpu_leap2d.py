@@ -93,9 +93,9 @@ def test_steps_per_pass_agree_fp64(case, forcing):
     prob, pl = workload.setup(w)
     V = rand_v(w["shape"], case["nf"], 31)
     ref = omf.apply(prob, pl, w["f"], V, forcing)
-    out = {spp: _apply(w, V, forcing, spp)[0] for spp in (0, 1, 2)}
+    out = {spp: _apply(w, V, forcing, spp)[0] for spp in (0, 1, 2, 3, 4)}
     bar = 1e-12 * max(1.0, np.linalg.cond(pl.B) / 10)
-    for spp in (1, 2):
+    for spp in (1, 2, 3, 4):
         print(f"steps per pass {spp}: vs general {rel(out[spp], out[0]):.2e}, "
               f"vs oracle {rel(out[spp], ref):.2e}, bar {bar:.1e}")
         assert rel(out[spp], out[0]) < bar, spp
@@ -109,10 +109,10 @@ def test_steps_per_pass_agree_fp32(case):
     w = inputs.small(**case)
     prob, pl = workload.setup(w)
     V = rand_v(w["shape"], case["nf"], 32)
-    ref = omf.apply(prob, pl, w["f"], V, True)
-    out = {spp: _apply(w, V, True, spp, precision=1)[0] for spp in (0, 1, 2)}
+    out = {spp: _apply(w, V, False, spp, precision=1)[0] for spp in (0, 1, 2, 3, 4)}
+    ref = omf.apply(prob, pl, w["f"], V, False)
     bar = max(1e-5, 4 * 2.0 ** -24 * pl.nt * max(1.0, np.linalg.cond(pl.B)))
-    for spp in (1, 2):
+    for spp in (1, 2, 3, 4):
         print(f"steps per pass {spp}: vs general {rel(out[spp], out[0]):.2e}, "
               f"vs oracle {rel(out[spp], ref):.2e}, bar {bar:.1e}")
         assert rel(out[spp], out[0]) < bar, spp
@@ -177,3 +177,34 @@ def test_two_step_gmres_matches_general_kernel():
     assert res[0][1]["converged"] and res[2][1]["converged"]
     assert abs(res[0][1]["iterations"] - res[2][1]["iterations"]) <= 1
     assert rel(res[2][0], res[0][0]) < 1e-9
+
+
+# three and four steps per pass (forcing-free passes): bx 128 or 256; chunks
+# below, at and above the 2 (KS - 1) R recomputed rows, one chunk for all rows
+SHAPES_K = [(128, 1, 1), (128, 1, 5), (128, 1, 16), (256, 1, 7), (256, 1, 64), (128, 1, 1000)]
+
+
+@pytest.mark.parametrize("spp", [3, 4])
+@pytest.mark.parametrize("shape", SHAPES_K, ids=lambda s: f"bx{s[0]}-c{s[2]}")
+def test_multi_step_launch_shapes(shape, spp):
+    for case in (dict(seed=5, shape=(37, 269), nf=3, order=4, varc=True),
+                 dict(seed=6, shape=(45, 131), nf=6, order=2)):
+        w = inputs.small(**case)
+        prob, pl = workload.setup(w)
+        V = rand_v(w["shape"], case["nf"], 7)
+        ref = omf.apply(prob, pl, w["f"], V, False)
+        out, _ = _apply(w, V, False, spp, shape=shape)
+        assert rel(out, ref) < 1e-12 * max(1.0, np.linalg.cond(pl.B) / 10), case
+
+
+def test_multi_step_remainders():
+    """N_t - 1 not a multiple of the steps per pass: the tail runs two-step
+    and one-step passes."""
+    for seed in range(6):
+        w = inputs.small(seed=seed, shape=(19, 70), nf=2, order=4)
+        prob, pl = workload.setup(w)
+        V = rand_v(w["shape"], 2, seed)
+        ref = omf.apply(prob, pl, w["f"], V, False)
+        for spp in (3, 4):
+            out, nt = _apply(w, V, False, spp)
+            assert rel(out, ref) < 1e-12 * max(1.0, np.linalg.cond(pl.B) / 10), (seed, spp, nt)
