@@ -46,11 +46,11 @@ HBM_PEAK_GBS = 8000.0
 # HBM traffic per launch of the dominant step kernel, from two rocprofv3
 # --pmc runs (FETCH_SIZE, WRITE_SIZE) on `python bench.py --mode apply`, each
 # scaled by the same counter on a plain 1 GiB copy (factors 2.0 and 1.0;
-# profiles/k_leap2d_x2_fp64_2d-n1025-nf4.md).  Keyed by (steps per pass, bx,
+# profiles/k_leap2d_xk3_fp64_2d-n1025-nf4.md).  Keyed by (steps per pass, bx,
 # chunk) and valid only for the kernel source it was measured on: reported
 # as null for another configuration or once leap2d.hip changes.
-TRAFFIC = {"leap2d_sha256_16": None,
-           "bytes": {(2, 128, 4): 30911.5 * 1024 * 2.0 + 48668.0 * 1024 * 1.0}}
+TRAFFIC = {"leap2d_sha256_16": "2c7a8e7918e199b5",
+           "bytes": {(3, 128, 8): 33643.4 * 1024 * 2.0 + 48754.8 * 1024 * 1.0}}
 
 
 def measured_traffic(cfg):
@@ -268,8 +268,11 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-fp32", action="store_true", help="skip the float32-stencil solve")
     ap.add_argument("--n", type=int, default=1025, help="grid points per axis")
-    ap.add_argument("--spp", type=int, default=2, choices=[0, 1, 2],
-                    help="2D step kernel: 0 general, 1 streamlined, 2 streamlined two-step")
+    ap.add_argument("--config", type=int, default=2, choices=[2, 3],
+                    help="apply mode: the 2D 1025^2 workload (float64) or the 3D 256^3 "
+                         "workload (float32 stencil, variable c, 8 frequencies)")
+    ap.add_argument("--spp", type=int, default=2, choices=[0, 1, 2, 3, 4],
+                    help="2D step kernel: 0 general, 1..4 streamlined steps per launch")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); multi-GPU slab "
@@ -295,11 +298,16 @@ def main():
         implicit_bench(args)
         return
 
-    w = inputs.config2(0, n=args.n)
+    if args.mode == "apply" and args.config == 3:
+        w = inputs.config3(0)
+        prec = L.MFWH_FP32_STENCIL
+    else:
+        w = inputs.config2(0, n=args.n)
+        prec = L.MFWH_FP64
     nf = len(w["omega"])
     log(f"workload {w['name']}: omega={np.round(w['omega'], 3).tolist()} N_p={w['np']}")
     RESTART = 128
-    gp = GpuProblem(w, precision=L.MFWH_FP64, restart=RESTART)
+    gp = GpuProblem(w, precision=prec, restart=0 if args.mode == "apply" else RESTART)
     log(f"N_t={gp.nt} dt={gp.dt:.3e} interior={gp.interior_points}")
     spp, shape = args.spp, None
     if not args.no_tune and args.mode == "solve":
