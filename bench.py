@@ -372,6 +372,13 @@ def main():
                       "solver's stream, divided by its launches (first step and tail included)",
             "avg_launch_us": round(avg_us, 3), "bytes_per_launch": round(bytes_per_launch),
             "timed_launches": launches}
+    # the same point-step rate priced at the 88 B per point-step of a kernel
+    # that streams every step (no temporal blocking): above 1 means the fused
+    # passes beat the one-step-per-launch HBM roofline
+    ps_per_s_kernel = total_ps / (kms / 1e3) if kms > 0 else 0.0   # point-steps per kernel-second
+    roof["one_step_equivalent"] = {
+        "bytes_per_point_step": 88, "achieved": round(88 * ps_per_s_kernel / 1e9, 1),
+        "frac": round(88 * ps_per_s_kernel / 1e9 / HBM_PEAK_GBS, 4)}
 
     t2e = {"fp64_s": round(elapsed / args.steps, 3)}
     if not args.no_fp32:

@@ -344,14 +344,16 @@ int mfwh_set_launch_shape(int bx, int by, int chunk);
  * replay it for every application; 0 launches every step from the host.
  * While step timing (mfwh_stats_enable) is on, a graph replay is timed as a
  * whole and counted as the number of step launches it holds.
- * MFWH_OPT_STEPS_PER_PASS (2D grids; default 2): after the first step,
+ * MFWH_OPT_STEPS_PER_PASS (default 2): 2D grids: after the first step,
  * 0 runs every step with the general step kernel, 1 with the streamlined 2D
  * kernel one step per launch, 2 with the streamlined kernel two steps per
  * launch (temporal blocking: W^{n+1} is recomputed on a halo and every filter
  * accumulator is read and written once per two steps), 3 or 4 that many
  * steps per launch for applications without forcing (with forcing: two).
- * All compute the same values up to floating-point contraction; 1D and 3D
- * grids always use the general kernel.
+ * 3D grids: 0 runs the general kernel, 1 or more the streamlined 3D kernel
+ * (one step per launch, launch shapes 64 x 4 or 64 x 8).  All compute the
+ * same values up to floating-point contraction; 1D grids always use the
+ * general kernel.
  * MFWH_OPT_PREFETCH_DEPTH (2 or 4; default 4): register sets of row operands
  * a wave of the streamlined 2D kernels rotates through, i.e. it requests the
  * operands of row y + depth - 1 before computing row y. */

@@ -22,6 +22,9 @@ CAND_2D_PASS = [(2, (bx, 1, ch)) for bx in (64, 128) for ch in (2, 4, 8, 16)] + 
 CAND_3D = [(64, 4, ch) for ch in (2, 4, 8, 16, 32)] + \
           [(64, 8, ch) for ch in (4, 8, 16)] + [(128, 2, ch) for ch in (4, 8, 16)] + \
           [(32, 8, ch) for ch in (4, 8)]
+# 3D (steps-per-pass option, shape): 0 = general kernel, 1 = streamlined kernel
+CAND_3D_PASS = [(1, (64, by, ch)) for by in (4, 8) for ch in (4, 8, 16, 32)] + \
+               [(0, (64, 4, ch)) for ch in (4, 8, 16)]
 
 
 def _time_apply(gp, v, out, reps):
@@ -39,18 +42,18 @@ def _time_apply(gp, v, out, reps):
 def tune(gp, reps=2, candidates=None, log=None):
     """Returns (best, {candidate: ms per application}) and installs the best.
 
-    ``gp``: a GpuProblem (its workspace and time grid are used).  In 2D a
-    candidate is (steps per pass, shape), elsewhere a shape.  mfwh_apply runs
+    ``gp``: a GpuProblem (its workspace and time grid are used).  In 2D and
+    3D a candidate is (steps-per-pass option, shape), in 1D a shape.  mfwh_apply runs
     on the current torch stream, so torch events time it."""
     dim = len(gp.shape)
     if candidates is None:
-        candidates = CAND_2D_PASS if dim == 2 else CAND_3D if dim == 3 else [(64, 1, 1)]
+        candidates = CAND_2D_PASS if dim == 2 else CAND_3D_PASS if dim == 3 else [(64, 1, 1)]
     v = torch.randn((gp.nf,) + gp.shape, dtype=torch.float64, device=gp.device)
     out = torch.empty_like(v)
     times = {}
 
     def install(c):
-        if dim == 2:
+        if dim in (2, 3):
             L.mfwh_set_option(L.MFWH_OPT_STEPS_PER_PASS, c[0])
             L.mfwh_set_launch_shape(*c[1])
         else:

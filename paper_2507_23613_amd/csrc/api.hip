@@ -291,9 +291,10 @@ int setup(Problem& pr, const mfwh_grid* g, const mfwh_time* t, int restart, void
                                      " bytes, got " + std::to_string(ws_bytes));
   pr.shape64 = default_shape(pr.G, g->order, 8);
   pr.shape32 = default_shape(pr.G, g->order, 4);
-  pr.spp = pr.G.dim == 2 ? g_steps_per_pass : 0;
+  // 2D: 0..4 steps per pass; 3D: 0 (general kernel) or 1 (streamlined)
+  pr.spp = pr.G.dim == 2 ? g_steps_per_pass : pr.G.dim == 3 ? std::min(g_steps_per_pass, 1) : 0;
   pr.depth = g_depth;
-  pr.leap = default_leap_shape(pr.G, pr.spp);
+  pr.leap = pr.G.dim == 3 ? default_leap3d_shape(pr.G) : default_leap_shape(pr.G, pr.spp);
   if (g_shape_set) pr.shape64 = pr.shape32 = pr.leap = g_shape_override;
   if (pr.implicit) {
     pr.W.lev[0].c2 = pr.varc ? pr.W.c64 : nullptr;
@@ -544,7 +545,7 @@ int apply_t(Problem& pr, const double* v, ExtLayout vl, bool forcing, const Out&
   } else {
     wc4 = (T*)pr.W.w32c; wd4 = (T*)pr.W.w32d;
   }
-  const int spp = (wc4 && wd4) ? pr.spp : 0;
+  const int spp = pr.G.dim == 2 ? ((wc4 && wd4) ? pr.spp : 0) : pr.spp;
 
   StepArgs<T> a{};
   a.c2 = pr.varc ? c2 : nullptr;
@@ -561,6 +562,7 @@ int apply_t(Problem& pr, const double* v, ExtLayout vl, bool forcing, const Out&
   for (int k = 0; k < 3; ++k) {
     la.wx[k] = a.wx[k];
     la.wy[k] = a.wy[k];
+    la.wz[k] = a.wz[k];
   }
   la.force = a.force;
   const int sort = sizeof(T) == 8 ? 8 : 4;
@@ -675,6 +677,7 @@ int apply_t(Problem& pr, const double* v, ExtLayout vl, bool forcing, const Out&
     // unused slots repeat the last used accumulator (the kernels load every
     // slot unconditionally and store only the first nq)
     for (int j = nq; j < MFWH_MAX_NF; ++j) la.qm[j] = nq > 0 ? la.qm[nq - 1] : 0;
+    if (pr.G.dim == 3) return launch_leap3d<T>(la, pr.grid->order, pr.leap, s);
     return launch_leap2d<T>(la, pr.grid->order, ns, pr.depth, pr.leap, s);
   };
   double bytes_all = 0.0;          // algorithmic bytes of the whole sequence

@@ -99,14 +99,14 @@ struct LeapArgs {
   const T* f;           // forcing fields or nullptr
   double* q;
   Geom g;
-  T wx[3], wy[3];
+  T wx[3], wy[3], wz[3];
   T cA, cB, cC;
   T phi1[MFWH_MAX_NF], phi2[MFWH_MAX_NF];
   double kk[4][MFWH_MAX_NF];
   int qm[MFWH_MAX_NF];  // slots nq.. repeat slot nq-1 (they are loaded, never stored)
   int nq;               // active accumulators
   int force;
-  int chunk, nchunk, ntx, nblocks;
+  int chunk, nchunk, ntx, nty, nblocks;
 };
 
 // Launch one streamlined 2D pass of `steps` fused steps (1, 2; 3 or 4
@@ -118,6 +118,10 @@ hipError_t launch_leap2d(LeapArgs<T>& a, int order, int steps, int depth, const 
                          hipStream_t s);
 // Default launch shapes of the streamlined kernels.
 LaunchShape default_leap_shape(const Geom& g, int steps);
+// leap3d.hip: one streamlined 3D step (z-march), shape (64, 4) or (64, 8)
+template <typename T>
+hipError_t launch_leap3d(LeapArgs<T>& a, int order, const LaunchShape& ls, hipStream_t s);
+LaunchShape default_leap3d_shape(const Geom& g);
 
 // mg2d.hip: implicit trapezoid steps and their multigrid solver (2D, float64)
 // One multigrid level: interior nx x ny points at row pitch py; the operator

@@ -1,0 +1,221 @@
+// Streamlined 3D leapfrog + filter kernel for every step after the first
+// (Section 6, eqs. WaveScheme and pDefQ), organised like the 2D streamlined
+// kernels: no global load sits behind a branch on loaded data (values
+// outside the interior come from a clamped index times a factor: 1 inside,
+// -1 for the order-4 odd-reflection ghost, 0 on the boundary), and the
+// operands of plane z+1 are requested before plane z is computed (two
+// register sets alternate).
+//
+// A BX x BY block owns a column tile and marches a chunk of z-planes (2.5D):
+// z-neighbours in a register window, x/y-neighbours from a double-buffered
+// LDS plane tile.  The tile's x- and y-halo (2R (BX + BY) values, no
+// corners) is spread over the block's threads, each with a fixed source
+// index and factor computed once.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "kernels.h"
+
+namespace mfwh {
+
+namespace {
+
+__device__ __forceinline__ int xcd_tile3(int b, int grid) {
+  const int per = grid >> 3;               // grid is a multiple of 8
+  return (b & 7) * per + (b >> 3);
+}
+
+inline int pad8(int n) { return (n + 7) & ~7; }
+
+template <typename T>
+__device__ __forceinline__ int ext_src3(int e, int n, T& sg) {
+  const bool in = e >= 0 && e < n;
+  const bool ghost = e == -2 || e == n + 1;
+  sg = in ? T(1) : (ghost ? T(-1) : T(0));
+  return in ? e : (e == n + 1 ? n - 1 : 0);
+}
+
+template <typename T, int QM, int HS>
+struct Plane {
+  T w, sw;          // new z-window value and its factor
+  T h[HS];          // raw halo values (factors fixed per slot)
+  T p, c, f;        // W^{n-1}, c^2, forcing
+  double q[QM];
+};
+
+template <typename T, int R, int BX, int BY, int QM, bool FORCE>
+__global__ void __launch_bounds__(BX * BY) k_leap3d(LeapArgs<T> a) {
+  constexpr int NT = BX * BY;
+  constexpr int NH = 2 * R * (BX + BY);            // halo slots per plane
+  constexpr int HS = (NH + NT - 1) / NT;           // halo slots per thread
+  __shared__ T tile[2][BY + 2 * R][BX + 2 * R];
+  const int lb = xcd_tile3(blockIdx.x, gridDim.x);
+  if (lb >= a.nblocks) return;
+  const int cz = lb % a.nchunk;
+  const int t2 = lb / a.nchunk;
+  const int tx = t2 % a.ntx;
+  const int ty = t2 / a.ntx;
+  const int lx = threadIdx.x, ly = threadIdx.y;
+  const int tid = ly * BX + lx;
+  const int nxi = a.g.nxi, nyi = a.g.nyi, nzi = a.g.nzi;
+  const long long py = a.g.py, pz = a.g.pz, fs = a.g.fs;
+  const int i0 = tx * BX, j0 = ty * BY;
+  const int i = i0 + lx, j = j0 + ly;
+  const bool act = i < nxi && j < nyi;
+  T sx, sy;
+  const int ix = ext_src3(i, nxi, sx), iy = ext_src3(j, nyi, sy);
+  const T sxy = sx * sy;
+  const long long col = (long long)iy * py + ix;
+  // halo slots of this thread: tile position and source column
+  int hr[HS], hc[HS];
+  long long hcol[HS];
+  T hsg[HS];
+#pragma unroll
+  for (int k = 0; k < HS; ++k) {
+    const int h = tid + k * NT;
+    int r, c, gi, gj;
+    if (h < 2 * R * BY) {                          // x-halo: left/right columns
+      const int rr = h / (2 * R), s = h % (2 * R);
+      r = R + rr;
+      c = s < R ? s : BX + s;
+      gi = i0 + c - R;
+      gj = j0 + rr;
+    } else {                                       // y-halo: bottom/top rows
+      const int hh = min(h, NH - 1) - 2 * R * BY;
+      const int cc = hh % BX, s = hh / BX;
+      r = s < R ? s : BY + s;
+      c = R + cc;
+      gi = i0 + cc;
+      gj = j0 + r - R;
+    }
+    T fx, fy;
+    const int si = ext_src3(gi, nxi, fx), sj = ext_src3(gj, nyi, fy);
+    hr[k] = r;
+    hc[k] = c;
+    hcol[k] = (long long)sj * py + si;
+    hsg[k] = h < NH ? fx * fy : T(0);
+  }
+  const int z0 = cz * a.chunk;
+  const int z1 = min(z0 + a.chunk, nzi);
+  const T* __restrict__ wc = a.wc;
+  const T* __restrict__ c2p = a.c2 ? a.c2 : a.wp;  // read and ignored when c = 1
+
+  T w[2 * R + 1];                                  // own column along z
+#pragma unroll
+  for (int k = 0; k < 2 * R; ++k) {
+    T sz;
+    const int iz = ext_src3(z0 - R + k, nzi, sz);
+    w[k + 1] = (sxy * sz) * wc[(long long)iz * pz + col];
+  }
+
+  auto fetch = [&](Plane<T, QM, HS>& o, int z) {
+    T sz;
+    const int iz = ext_src3(z + R, nzi, sz);
+    o.sw = sxy * sz;
+    o.w = wc[(long long)iz * pz + col];
+    const long long zo = (long long)z * pz;
+#pragma unroll
+    for (int k = 0; k < HS; ++k) o.h[k] = wc[zo + hcol[k]];
+    const long long idx = zo + col;
+    o.p = a.wp[idx];
+    o.c = c2p[idx];
+    o.f = T(0);
+    if (FORCE) {
+#pragma unroll
+      for (int m = 0; m < MFWH_MAX_NF; ++m)
+        if (a.phi1[m] != T(0)) o.f += a.phi1[m] * a.f[m * fs + idx];
+    }
+#pragma unroll
+    for (int q = 0; q < QM; ++q) o.q[q] = a.q[a.qm[q] * fs + idx];
+  };
+  auto process = [&](int z, const Plane<T, QM, HS>& o, int buf) {
+#pragma unroll
+    for (int k = 0; k < 2 * R; ++k) w[k] = w[k + 1];
+    w[2 * R] = o.sw * o.w;
+    auto& tb = tile[buf];
+    tb[R + ly][R + lx] = w[R];
+#pragma unroll
+    for (int k = 0; k < HS; ++k)
+      if (tid + k * NT < NH) tb[hr[k]][hc[k]] = hsg[k] * o.h[k];
+    __syncthreads();
+    if (act) {
+      T lap = (a.wx[0] + a.wy[0] + a.wz[0]) * w[R];
+#pragma unroll
+      for (int k = 1; k <= R; ++k)
+        lap += a.wx[k] * (tb[R + ly][R + lx - k] + tb[R + ly][R + lx + k]) +
+               a.wy[k] * (tb[R + ly - k][R + lx] + tb[R + ly + k][R + lx]) +
+               a.wz[k] * (w[R - k] + w[R + k]);
+      const T c2v = a.c2 ? o.c : T(1);
+      const T wn = a.cA * w[R] + a.cB * o.p + a.cC * (c2v * lap - o.f);
+      const long long idx = (long long)z * pz + (long long)j * py + i;
+      a.w1[idx] = wn;
+      const double wd = (double)wn;
+#pragma unroll
+      for (int q = 0; q < QM; ++q)
+        if (q < a.nq) a.q[a.qm[q] * fs + idx] = o.q[q] + a.kk[0][q] * wd;
+    }
+  };
+
+  // fetches past the last plane re-read the last plane (valid, unused)
+  Plane<T, QM, HS> ra, rb;
+  fetch(ra, z0);
+  for (int z = z0; z < z1; z += 2) {
+    fetch(rb, min(z + 1, z1 - 1));
+    process(z, ra, 0);
+    if (z + 1 >= z1) break;
+    fetch(ra, min(z + 2, z1 - 1));
+    process(z + 1, rb, 1);
+  }
+}
+
+template <typename T, int R, int BX, int BY>
+hipError_t launch_shape3(LeapArgs<T>& a, hipStream_t s) {
+  const Geom& g = a.g;
+  a.ntx = (g.nxi + BX - 1) / BX;
+  a.nty = (g.nyi + BY - 1) / BY;
+  a.nchunk = (g.nzi + a.chunk - 1) / a.chunk;
+  a.nblocks = a.ntx * a.nty * a.nchunk;
+  const int grid = pad8(a.nblocks);
+  const dim3 blk(BX, BY);
+  const bool q4 = a.nq <= 4;
+  if (a.force) {
+    if (q4) k_leap3d<T, R, BX, BY, 4, true><<<grid, blk, 0, s>>>(a);
+    else k_leap3d<T, R, BX, BY, 8, true><<<grid, blk, 0, s>>>(a);
+  } else {
+    if (q4) k_leap3d<T, R, BX, BY, 4, false><<<grid, blk, 0, s>>>(a);
+    else k_leap3d<T, R, BX, BY, 8, false><<<grid, blk, 0, s>>>(a);
+  }
+  return hipGetLastError();
+}
+
+template <typename T, int R>
+hipError_t launch_r3(LeapArgs<T>& a, const LaunchShape& ls, hipStream_t s) {
+  if (ls.bx == 64 && ls.by == 4) return launch_shape3<T, R, 64, 4>(a, s);
+  if (ls.bx == 64 && ls.by == 8) return launch_shape3<T, R, 64, 8>(a, s);
+  return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+template <typename T>
+hipError_t launch_leap3d(LeapArgs<T>& a, int order, const LaunchShape& ls, hipStream_t s) {
+  if (a.g.dim != 3 || a.nq < 0 || a.nq > MFWH_MAX_NF) return hipErrorInvalidValue;
+  a.chunk = std::max(1, ls.chunk);
+  return order == 2 ? launch_r3<T, 1>(a, ls, s) : launch_r3<T, 2>(a, ls, s);
+}
+template hipError_t launch_leap3d<double>(LeapArgs<double>&, int, const LaunchShape&, hipStream_t);
+template hipError_t launch_leap3d<float>(LeapArgs<float>&, int, const LaunchShape&, hipStream_t);
+
+LaunchShape default_leap3d_shape(const Geom& g) {
+  LaunchShape ls;
+  ls.bx = 64;
+  ls.by = 4;
+  const long long tiles = ((g.nxi + 63) / 64) * (long long)((g.nyi + 3) / 4);
+  const long long target_waves = 256LL * 16;
+  long long ch = tiles * 4 * g.nzi / target_waves;
+  ls.chunk = (int)std::min<long long>(std::max<long long>(ch, 4), 64);
+  return ls;
+}
+
+}  // namespace mfwh

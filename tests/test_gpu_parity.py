@@ -118,6 +118,8 @@ def test_apply_fp32_stencil(case):
 
 SHAPES_2D = [(64, 1, 1), (64, 1, 5), (128, 1, 3), (256, 1, 8), (128, 1, 64)]
 SHAPES_3D = [(64, 4, 1), (64, 4, 7), (64, 8, 3), (128, 2, 4), (32, 8, 2)]
+# the streamlined 3D kernel (MFWH_OPT_STEPS_PER_PASS >= 1) takes 64 x 4 and 64 x 8
+SHAPES_3D_LEAP = [(64, 4, 1), (64, 4, 5), (64, 8, 3), (64, 8, 200)]
 
 
 @pytest.mark.parametrize("shape", SHAPES_2D, ids=lambda s: f"bx{s[0]}-c{s[2]}")
@@ -137,20 +139,25 @@ def test_launch_shapes_2d(shape, order):
     assert rel(out, ref) < tol64(pl)
 
 
-@pytest.mark.parametrize("shape", SHAPES_3D, ids=lambda s: f"bx{s[0]}-by{s[1]}-c{s[2]}")
+@pytest.mark.parametrize("kernel", [(0, s) for s in SHAPES_3D] + [(1, s) for s in SHAPES_3D_LEAP],
+                         ids=lambda k: f"{'leap' if k[0] else 'general'}-bx{k[1][0]}-by{k[1][1]}-c{k[1][2]}")
+@pytest.mark.parametrize("forcing", [True, False], ids=["forced", "free"])
 @pytest.mark.parametrize("order", [2, 4])
-def test_launch_shapes_3d(shape, order):
+def test_launch_shapes_3d(kernel, forcing, order):
     L = _L()
+    spp, shape = kernel
     w = inputs.small(seed=4, shape=(11, 19, 133), nf=2, order=order, varc=True)
     prob, pl = workload.setup(w)
     V = rand_v(w["shape"], 2, 8)
-    ref = omf.apply(prob, pl, w["f"], V, True)
+    ref = omf.apply(prob, pl, w["f"], V, forcing)
     try:
+        L.mfwh_set_option(L.MFWH_OPT_STEPS_PER_PASS, spp)
         L.mfwh_set_launch_shape(*shape)
         gp = _gp(w)
-        out = gp.apply(torch.as_tensor(V, device="cuda"), forcing=True).cpu().numpy()
+        out = gp.apply(torch.as_tensor(V, device="cuda"), forcing=forcing).cpu().numpy()
     finally:
         L.mfwh_set_launch_shape(0)
+        L.mfwh_set_option(L.MFWH_OPT_STEPS_PER_PASS, 2)
     assert rel(out, ref) < tol64(pl)
 
 
