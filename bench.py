@@ -26,6 +26,7 @@ Extra fields:
     python bench.py --mode batch     # 64 independent 2D problems solved as one batch
     python bench.py --mode warmstart # learned warm start: data, training, evaluation
     python bench.py --mode implicit  # implicit scheme + multigrid: O(N) grid study
+    python bench.py --mode bc        # Dirichlet data / Neumann faces at 1025^2
     python bench.py --mode apply --applies 3   # a few forcing-free float64
                                      # applications of the same workload (for
                                      # rocprofv3: the step kernel as the solver runs it)
@@ -249,13 +250,63 @@ def implicit_bench(args):
                       "rows": rows}), flush=True)
 
 
+def bc_bench(args):
+    """Other boundary conditions at the 2D workload's size (1025^2, order 4,
+    4 frequencies, float64, forced applications): homogeneous Dirichlet (the
+    streamlined kernels), Dirichlet with boundary data g (the same kernels;
+    g is folded into the forcing once per solve), Neumann on the x faces with
+    Dirichlet data on the y faces, and Neumann everywhere (both on the
+    general step kernels).  Per case: ms per application, grid-point-steps/s
+    x N_f, and the step kernels' algorithmic bytes / their event-timed
+    duration against the 8 TB/s peak."""
+    import torch
+    from paper_2507_23613_amd import _lib as L
+    from paper_2507_23613_amd import inputs
+    from paper_2507_23613_amd.problem import GpuProblem
+    D, N = ("D",), ("N",)
+    base = inputs.config2(0, n=args.n)
+    rng = np.random.default_rng(123)
+    g = inputs.smooth_boundary_data(rng, base["shape"], base["lengths"], 4)
+    cases = [("dirichlet g=0", None, None), ("dirichlet with data", [(D, D), (D, D)], g),
+             ("neumann x, dirichlet data y", [(D, D), (N, N)], g),
+             ("neumann everywhere", [(N, N), (N, N)], None)]
+    rows = []
+    for name, bc, data in cases:
+        w = dict(base, bc=bc, g=data)
+        gp = GpuProblem(w, restart=0)
+        v = torch.zeros((4,) + tuple(w["shape"]), dtype=torch.float64, device="cuda")
+        out = torch.empty_like(v)
+        L.mfwh_apply(gp.grid, gp.time, gp.f, v, out, 1, gp.ws)      # warm-up
+        torch.cuda.synchronize()
+        L.mfwh_stats_read()
+        L.mfwh_stats_enable(1, 1)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        L.mfwh_apply(gp.grid, gp.time, gp.f, v, out, 1, gp.ws)
+        e1.record()
+        torch.cuda.synchronize()
+        L.mfwh_stats_enable(0, 8)
+        launches, kms, kbytes = L.mfwh_stats_read()
+        ms = e0.elapsed_time(e1)
+        row = {"case": name, "unknowns": gp.interior_points, "nt": gp.nt,
+               "ms_per_apply": round(ms, 2),
+               "point_steps_x_nf_per_s": gp.interior_points * gp.nt * 4 / ms * 1e3,
+               "step_kernels_TBps": round(kbytes / kms / 1e9, 3),
+               "frac": round(kbytes / kms / 1e9 / (HBM_PEAK_GBS / 1e3), 3)}
+        rows.append(row)
+        log(json.dumps(row))
+        del gp, v, out
+        torch.cuda.empty_cache()
+    print(json.dumps({"mode": "bc", "workload": base["name"], "rows": rows}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--mode", default="solve",
-                    choices=["solve", "copy", "apply", "batch", "warmstart", "implicit"])
+                    choices=["solve", "copy", "apply", "batch", "warmstart", "implicit", "bc"])
     ap.add_argument("--train", type=int, default=2000)
     ap.add_argument("--test", type=int, default=200)
     ap.add_argument("--epochs", type=int, default=20)
@@ -296,6 +347,9 @@ def main():
         return
     if args.mode == "implicit":
         implicit_bench(args)
+        return
+    if args.mode == "bc":
+        bc_bench(args)
         return
 
     if args.mode == "apply" and args.config == 3:

@@ -17,9 +17,12 @@
  *        m * (n0*n1*n2) + iz * (n0*n1) + iy * n0 + ix,
  *    n[] counting grid points INCLUDING both boundary points of each axis
  *    (n[k] = 1 for axes beyond dim).  Multi-frequency arrays hold nf fields.
- *  - All device arrays at the ABI are float64.  Boundary entries of inputs are
- *    ignored (homogeneous Dirichlet data, g = 0, the setting of all the
- *    paper's experiments); outputs get 0 on the boundary.
+ *  - All device arrays at the ABI are float64.  By default every face is
+ *    Dirichlet with g = 0 (the setting of all the paper's experiments):
+ *    boundary entries of inputs are ignored and outputs get 0 there.  With
+ *    Neumann or Robin faces (mfwh_grid.bc) the points of those faces are
+ *    unknowns like interior points; with boundary data (mfwh_grid.g) outputs
+ *    of forced applications and solutions carry g_m on Dirichlet faces.
  *  - Host arrays (omega, filter parameters, histories, plan outputs) are plain
  *    host memory owned by the caller.
  *  - Scratch: the library never allocates device memory.  Every GPU entry point
@@ -64,6 +67,20 @@ enum { MFWH_FP64 = 0,          /* wave field, forcing and c^2 in float64        
                                   accumulators, iterates and Krylov data float64   */
 };
 
+/* Boundary condition of one face (Section 2, eq. MultipleHelmholtz: B u = g
+ * with B Dirichlet, Neumann or Robin; eq. WaveSchemeBC imposes B_ph W^n =
+ * sum_m g_m cos(omega~_m t^n)).  n is the outward normal.
+ *   MFWH_BC_DIRICHLET  u = g.  The face's points are not unknowns; the order-4
+ *                      stencil's ghost is the odd reflection about the
+ *                      boundary value, W_{-1} = 2 g - W_1.
+ *   MFWH_BC_NEUMANN    du/dn = g.  The face's points are unknowns; the ghost
+ *                      at distance k is W_{-k} = W_k + 2 k h g.
+ *   MFWH_BC_ROBIN      du/dn + r u = g, r >= 0 (order 2 only).  Ghost
+ *                      W_{-k} = W_k + 2 k h (g - r W_0).
+ * A point on a Dirichlet face is a Dirichlet point; a point on two Neumann /
+ * Robin faces uses its one value of g for both. */
+enum { MFWH_BC_DIRICHLET = 0, MFWH_BC_NEUMANN = 1, MFWH_BC_ROBIN = 2 };
+
 /* Problem geometry and discretisation (Section 6). */
 typedef struct mfwh_grid {
   int dim;            /* 1, 2 or 3                                                 */
@@ -75,6 +92,17 @@ typedef struct mfwh_grid {
                          boundary for its one ghost value.                          */
   int precision;      /* MFWH_FP64 or MFWH_FP32_STENCIL                            */
   const double* c;    /* device, wave speed at every grid point, or NULL (c = 1)   */
+  int bc[6];          /* face conditions: bc[2k] lower, bc[2k+1] upper face of axis
+                         k (MFWH_BC_*; all zero = homogeneous Dirichlet).  Faces
+                         other than Dirichlet run on the general step kernels
+                         of the explicit scheme only (no implicit scheme, no
+                         batching); an axis with such a face needs at least 4
+                         points with order 4                                     */
+  double robin[6];    /* r of each MFWH_BC_ROBIN face (ignored otherwise)          */
+  const double* g;    /* device [nf][grid] boundary data, read on boundary points
+                         (interior entries ignored), or NULL (g = 0).  Applied in
+                         forced applications (with_forcing = 1) and solves; the
+                         implicit scheme and batching take g = NULL             */
 } mfwh_grid;
 
 /* Time-stepping schemes of Section 6 (eq. WaveSchemeA). */
@@ -335,7 +363,10 @@ int mfwh_stats_read(long long* launches, double* total_ms, double* total_bytes);
  * process (autotuning): bx threads along x (32, 64, 128 or 256; the
  * streamlined 2D kernels take 64, 128 or 256), by threads along y (3D: 4, 8
  * or 2 with bx 64/64/128; 8 with bx 32), chunk rows (2D) or planes (3D)
- * marched per block.  bx = 0 restores the built-in heuristics. */
+ * marched per block.  In 3D a shape with by = 16 (bx 64 or 32) sets only the
+ * two-step kernel; any other shape sets the one-step kernels (and the
+ * two-step kernel keeps its default).  bx = 0 restores the built-in
+ * heuristics. */
 int mfwh_set_launch_shape(int bx, int by, int chunk);
 
 /* Process-wide options, read when a call sets up its problem.
@@ -350,8 +381,9 @@ int mfwh_set_launch_shape(int bx, int by, int chunk);
  * launch (temporal blocking: W^{n+1} is recomputed on a halo and every filter
  * accumulator is read and written once per two steps), 3 or 4 that many
  * steps per launch for applications without forcing (with forcing: two).
- * 3D grids: 0 runs the general kernel, 1 or more the streamlined 3D kernel
- * (one step per launch, launch shapes 64 x 4 or 64 x 8).  All compute the
+ * 3D grids: 0 runs the general kernel, 1 the streamlined 3D kernel (one
+ * step per launch, launch shapes 64 x 4 or 64 x 8), 2 or more two steps
+ * per launch (launch shapes 64 x 16 or 32 x 16).  All compute the
  * same values up to floating-point contraction; 1D grids always use the
  * general kernel.
  * MFWH_OPT_PREFETCH_DEPTH (2 or 4; default 4): register sets of row operands

@@ -13,7 +13,7 @@ def setup(w, filt=None):
     """Returns (Problem, Plan) for workload ``w``: explicit recipe with the
     workload's N_p and CFL; filter "traditional" (p_0), "adjusted"
     (eq. origParamAdjust) or "optimised" (Algorithm 2 on omega~)."""
-    prob = mfwh.Problem(w["shape"], w["order"], w["lengths"], w["c"])
+    prob = mfwh.Problem(w["shape"], w["order"], w["lengths"], w["c"], w.get("bc"))
     cmax = 1.0 if w["c"] is None else float(np.max(w["c"]))
     Tf, dt, nt = P.time_step_explicit(w["omega"][0], w["np"], prob.h, len(w["shape"]),
                                       w["order"], cmax, w["cfl"])

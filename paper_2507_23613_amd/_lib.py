@@ -38,7 +38,8 @@ class MfwhError(RuntimeError):
 
 class mfwh_grid(ctypes.Structure):
     _fields_ = [("dim", c_int), ("n", c_int * 3), ("len", c_double * 3), ("order", c_int),
-                ("precision", c_int), ("c", c_void_p)]
+                ("precision", c_int), ("c", c_void_p), ("bc", c_int * 6),
+                ("robin", c_double * 6), ("g", c_void_p)]
 
 
 class mfwh_time(ctypes.Structure):
@@ -166,22 +167,40 @@ def _stream(stream):
 # ----------------------------------------------------------------------------
 # struct builders (keep referenced arrays alive on the struct)
 # ----------------------------------------------------------------------------
-def make_grid(shape, lengths=None, order=4, precision=MFWH_FP64, c=None):
-    """shape: points per axis incl. boundary, x LAST (NumPy order)."""
+MFWH_BC_DIRICHLET = 0
+MFWH_BC_NEUMANN = 1
+MFWH_BC_ROBIN = 2
+_BC_CODES = {"D": MFWH_BC_DIRICHLET, "N": MFWH_BC_NEUMANN, "R": MFWH_BC_ROBIN}
+
+
+def make_grid(shape, lengths=None, order=4, precision=MFWH_FP64, c=None, bc=None, g=None):
+    """shape: points per axis incl. boundary, x LAST (NumPy order).
+    bc: None (homogeneous Dirichlet) or one (lo, hi) pair of face specs per
+    NumPy axis, each ("D",), ("N",) or ("R", r); g: device tensor of boundary
+    data (nf,) + shape or None."""
     d = len(shape)
     lengths = [1.0] * d if lengths is None else list(lengths)
-    g = mfwh_grid()
-    g.dim = d
+    gr = mfwh_grid()
+    gr.dim = d
     n = list(reversed([int(s) for s in shape])) + [1] * (3 - d)
     ln = list(reversed([float(x) for x in lengths])) + [1.0] * (3 - d)
     for k in range(3):
-        g.n[k] = n[k]
-        g.len[k] = ln[k]
-    g.order = int(order)
-    g.precision = int(precision)
-    g.c = _tptr(c, "c")
-    g._keep = c
-    return g
+        gr.n[k] = n[k]
+        gr.len[k] = ln[k]
+    gr.order = int(order)
+    gr.precision = int(precision)
+    gr.c = _tptr(c, "c")
+    if bc is not None:
+        if len(bc) != d:
+            raise ValueError("one (lo, hi) pair of face specs per axis")
+        for a, pair in enumerate(bc):
+            k = d - 1 - a                    # ABI axis: x first
+            for side, spec in enumerate(pair):
+                gr.bc[2 * k + side] = _BC_CODES[spec[0]]
+                gr.robin[2 * k + side] = float(spec[1]) if spec[0] == "R" else 0.0
+    gr.g = _tptr(g, "g")
+    gr._keep = (c, g)
+    return gr
 
 
 MFWH_EXPLICIT = 0

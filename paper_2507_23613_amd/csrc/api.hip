@@ -8,6 +8,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <map>
 #include <memory>
 #include <cmath>
 #include <cstdio>
@@ -83,10 +84,32 @@ int make_geom(const mfwh_grid* g, Geom* G) {
   }
   const long long tot = (long long)g->n[0] * g->n[1] * g->n[2];
   if (tot > (1LL << 33)) return fail(MFWH_EINVAL, "grid too large");
+  for (int k = 0; k < 2 * g->dim; ++k) {
+    const int b = g->bc[k];
+    if (b != MFWH_BC_DIRICHLET && b != MFWH_BC_NEUMANN && b != MFWH_BC_ROBIN)
+      return fail(MFWH_EINVAL, "unknown boundary condition");
+    if (b == MFWH_BC_ROBIN && g->order != 2)
+      return fail(MFWH_EINVAL, "Robin faces need order 2");
+    if (b == MFWH_BC_ROBIN && !(g->robin[k] >= 0.0))
+      return fail(MFWH_EINVAL, "Robin coefficient must be >= 0");
+  }
+  for (int k = 2 * g->dim; k < 6; ++k)
+    if (g->bc[k] != MFWH_BC_DIRICHLET) return fail(MFWH_EINVAL, "bc[] beyond dim must be 0");
+  // stored points per axis: the grid points off Dirichlet faces
+  int ns[3];
+  for (int k = 0; k < 3; ++k) {
+    ns[k] = k < g->dim ? g->n[k] - (g->bc[2 * k] == MFWH_BC_DIRICHLET) -
+                             (g->bc[2 * k + 1] == MFWH_BC_DIRICHLET)
+                       : 1;
+    const bool refl = k < g->dim && (g->bc[2 * k] != MFWH_BC_DIRICHLET ||
+                                     g->bc[2 * k + 1] != MFWH_BC_DIRICHLET);
+    if (refl && g->order == 4 && ns[k] < 3)
+      return fail(MFWH_EINVAL, "an axis with a Neumann face needs 4 points with order 4");
+  }
   G->dim = g->dim;
-  G->nxi = g->n[0] - 2;
-  G->nyi = g->dim >= 2 ? g->n[1] - 2 : 1;
-  G->nzi = g->dim >= 3 ? g->n[2] - 2 : 1;
+  G->nxi = ns[0];
+  G->nyi = ns[1];
+  G->nzi = ns[2];
   G->py = g->dim >= 2 ? round_up(G->nxi, 64) : G->nxi;
   G->pz = G->py * G->nyi;
   G->fs = round_up(G->pz * G->nzi, 64);
@@ -99,8 +122,24 @@ ExtLayout abi_layout(const mfwh_grid* g) {
   l.sy = n0;
   l.sz = n0 * n1;
   l.sf = n0 * n1 * n2;
-  l.base = 1 + (g->dim >= 2 ? n0 : 0) + (g->dim >= 3 ? n0 * n1 : 0);
+  // first stored point: grid index 1 along axes whose lower face is Dirichlet
+  l.base = (g->bc[0] == MFWH_BC_DIRICHLET ? 1 : 0) +
+           (g->dim >= 2 && g->bc[2] == MFWH_BC_DIRICHLET ? n0 : 0) +
+           (g->dim >= 3 && g->bc[4] == MFWH_BC_DIRICHLET ? n0 * n1 : 0);
   return l;
+}
+
+// bit 2k / 2k+1: lower / upper face of axis k is Neumann or Robin
+int reflective_faces(const mfwh_grid* g) {
+  int r = 0;
+  for (int k = 0; k < 2 * g->dim; ++k)
+    if (g->bc[k] != MFWH_BC_DIRICHLET) r |= 1 << k;
+  return r;
+}
+
+// bit 2k / 2k+1: lower / upper face of axis k is Dirichlet
+int dirichlet_faces(const mfwh_grid* g) {
+  return ((1 << (2 * g->dim)) - 1) & ~reflective_faces(g);
 }
 
 ExtLayout int_layout(const Geom& G) {
@@ -174,7 +213,7 @@ Workspace carve(const Geom& G, int nf, bool fp32, bool varc, int restart, char* 
     return p;
   };
   const size_t fs = (size_t)G.fs;
-  const bool two = G.dim == 2;
+  const bool two = G.dim >= 2;      // four W buffers: multi-step passes
   w.w64a = (double*)take(fs * 8);
   w.w64b = (double*)take(fs * 8);
   if (two) {
@@ -242,19 +281,30 @@ struct Problem {
   int spp = 0;                       // 2D: 0 general kernel, 1 or 2 streamlined steps per pass
   int depth = 4;                     // rows of operands in flight (streamlined kernels)
   LaunchShape shape64, shape32;
-  LaunchShape leap;                  // shape of the streamlined 2D kernels
+  LaunchShape leap;                  // shape of the streamlined kernels (3D: two-step)
+  LaunchShape leap1;                 // 3D: shape of the one-step streamlined kernel
   long long point_steps = 0;
   int applies = 0;
+  int refl = 0;                      // Neumann / Robin faces (bit per face)
+  double rg[6] = {0, 0, 0, 0, 0, 0};  // -2 h r per Robin face
+  const double* bdata = nullptr;     // boundary data g (caller layout) or null
   bool implicit = false;             // trapezoid scheme with multigrid step solves
   long long imp_solves = 0, mg_cycles = 0;
   int mg_prev = 0;                   // V-cycles the previous step solve needed
   StepGraph sg[2][2];                // [float32][forcing]
+  // implicit scheme: recorded blocks of k V-cycles + residual norm, per
+  // (k, solution buffer)
+  std::map<std::pair<int, double*>, StepGraph> mgg;
   ~Problem() {
     for (auto& a : sg)
       for (auto& b : a) {
         if (b.x) (void)hipGraphExecDestroy(b.x);
         if (b.g) (void)hipGraphDestroy(b.g);
       }
+    for (auto& kv : mgg) {
+      if (kv.second.x) (void)hipGraphExecDestroy(kv.second.x);
+      if (kv.second.g) (void)hipGraphDestroy(kv.second.g);
+    }
   }
 };
 
@@ -275,9 +325,16 @@ int setup(Problem& pr, const mfwh_grid* g, const mfwh_time* t, int restart, void
   pr.varc = g->c != nullptr;
   pr.s = (hipStream_t)stream;
   pr.implicit = pr.P.scheme == MFWH_IMPLICIT;
+  pr.refl = reflective_faces(g);
+  pr.bdata = g->g;
+  for (int k = 0; k < 2 * g->dim; ++k)
+    pr.rg[k] = g->bc[k] == MFWH_BC_ROBIN ? -2.0 * (g->len[k / 2] / (g->n[k / 2] - 1)) * g->robin[k]
+                                         : 0.0;
   MgLevel mg[kMaxLev];
   int nlev = 0;
   if (pr.implicit) {
+    if (pr.refl || pr.bdata)
+      return fail(MFWH_EINVAL, "the implicit scheme takes homogeneous Dirichlet faces");
     if (g->dim != 2) return fail(MFWH_EINVAL, "the implicit scheme is implemented for 2D grids");
     if (pr.fp32) return fail(MFWH_EINVAL, "the implicit scheme runs in float64 only");
     nlev = mg_hierarchy(pr.G, g, pr.P.alpha, pr.P.dt, mg);
@@ -291,11 +348,21 @@ int setup(Problem& pr, const mfwh_grid* g, const mfwh_time* t, int restart, void
                                      " bytes, got " + std::to_string(ws_bytes));
   pr.shape64 = default_shape(pr.G, g->order, 8);
   pr.shape32 = default_shape(pr.G, g->order, 4);
-  // 2D: 0..4 steps per pass; 3D: 0 (general kernel) or 1 (streamlined)
-  pr.spp = pr.G.dim == 2 ? g_steps_per_pass : pr.G.dim == 3 ? std::min(g_steps_per_pass, 1) : 0;
+  // 2D: 0..4 steps per pass; 3D: 0 (general kernel), 1 or 2
+  pr.spp = pr.G.dim == 2 ? g_steps_per_pass : pr.G.dim == 3 ? std::min(g_steps_per_pass, 2) : 0;
+  if (pr.refl) pr.spp = 0;   // Neumann / Robin faces: general step kernels
   pr.depth = g_depth;
-  pr.leap = pr.G.dim == 3 ? default_leap3d_shape(pr.G) : default_leap_shape(pr.G, pr.spp);
-  if (g_shape_set) pr.shape64 = pr.shape32 = pr.leap = g_shape_override;
+  pr.leap = pr.G.dim == 3 ? default_leap3d_shape(pr.G, pr.spp) : default_leap_shape(pr.G, pr.spp);
+  pr.leap1 = default_leap3d_shape(pr.G, 1);
+  if (g_shape_set) {
+    const LaunchShape& o = g_shape_override;
+    if (pr.G.dim == 3 && o.by == 16) {
+      pr.leap = o;             // two-step 3D shape: the other kernels keep theirs
+    } else {
+      pr.shape64 = pr.shape32 = pr.leap1 = o;
+      if (!(pr.G.dim == 3 && pr.spp == 2)) pr.leap = o;
+    }
+  }
   if (pr.implicit) {
     pr.W.lev[0].c2 = pr.varc ? pr.W.c64 : nullptr;
     pr.W.mx[0] = nullptr;   // level 0 solves in place in the W buffers
@@ -307,28 +374,22 @@ int setup(Problem& pr, const mfwh_grid* g, const mfwh_time* t, int restart, void
   for (int k = 0; k < g->dim; ++k) h[k] = g->len[k] / (g->n[k] - 1);
   if (!pr.varc && t->dt > dt_max_explicit(g->dim, h, g->order, 1.0) * (1 + 1e-12))
     return fail(MFWH_ECFL, "dt exceeds the explicit stability limit");
-  return MFWH_OK;
-}
-
-// Convert forcing and wave speed into the internal layout(s).
-int prepare(Problem& pr, const double* f) {
-  const int nf = pr.P.nf;
-  const ExtLayout al = abi_layout(pr.grid), il = int_layout(pr.G);
-  ExtLayout cl = al, ci = il;
-  cl.sf = 0;
-  ci.sf = 0;
-  if (f) {
-    HIPCHK(launch_copy_fields<double, double>(pr.G, nf, f, al, pr.W.f64, il, 0, pr.s));
-    if (pr.fp32) HIPCHK(launch_copy_fields<double, float>(pr.G, nf, f, al, pr.W.f32, il, 0, pr.s));
-  }
-  if (pr.varc) {
-    HIPCHK(launch_copy_fields<double, double>(pr.G, 1, pr.grid->c, cl, pr.W.c64, ci, 1, pr.s));
-    if (pr.fp32)
-      HIPCHK(launch_copy_fields<double, float>(pr.G, 1, pr.grid->c, cl, pr.W.c32, ci, 1, pr.s));
-    if (pr.implicit)
-      for (int l = 1; l < pr.W.nlev; ++l)
-        HIPCHK(launch_mg_inject(pr.W.lev[l - 1], pr.W.lev[l - 1].c2, pr.W.lev[l], pr.W.mc2[l],
-                                pr.s));
+  // Robin faces raise the spectral radius of Delta_h (order 2, per axis at most
+  // (4 + 2 h r) / h^2 by Gershgorin); leapfrog needs dt^2 c^2 rho <= 4
+  if (!pr.varc) {
+    double rho = 0.0;
+    bool robin = false;
+    for (int k = 0; k < g->dim; ++k) {
+      double r = 0.0;
+      for (int s2 = 0; s2 < 2; ++s2)
+        if (g->bc[2 * k + s2] == MFWH_BC_ROBIN) {
+          r = std::max(r, g->robin[2 * k + s2]);
+          robin = true;
+        }
+      rho += (4.0 + 2.0 * h[k] * r) / (h[k] * h[k]);
+    }
+    if (robin && t->dt * t->dt * rho > 4.0 * (1 + 1e-12))
+      return fail(MFWH_ECFL, "dt exceeds the explicit stability limit with the Robin faces");
   }
   return MFWH_OK;
 }
@@ -351,6 +412,52 @@ void stencil_weights(const mfwh_grid* g, T wx[3], T wy[3], T wz[3]) {
     }
   }
 }
+
+// Convert forcing and wave speed into the internal layout(s); boundary data
+// (when given) is folded into the float64 forcing before its float32 copy.
+int prepare(Problem& pr, const double* f) {
+  const int nf = pr.P.nf;
+  const ExtLayout al = abi_layout(pr.grid), il = int_layout(pr.G);
+  ExtLayout cl = al, ci = il;
+  cl.sf = 0;
+  ci.sf = 0;
+  if (pr.varc)
+    HIPCHK(launch_copy_fields<double, double>(pr.G, 1, pr.grid->c, cl, pr.W.c64, ci, 1, pr.s));
+  if (f) {
+    HIPCHK(launch_copy_fields<double, double>(pr.G, nf, f, al, pr.W.f64, il, 0, pr.s));
+    if (pr.bdata) {
+      const mfwh_grid* g = pr.grid;
+      FoldArgs fa{};
+      fa.G = pr.G;
+      fa.refl = pr.refl;
+      fa.R = g->order == 2 ? 1 : 2;
+      fa.nf = nf;
+      double wx[3], wy[3], wz[3];
+      stencil_weights<double>(g, wx, wy, wz);
+      const double* ws[3] = {wx, wy, wz};
+      for (int k = 0; k < 3; ++k) {
+        fa.n[k] = g->n[k];
+        fa.lo[k] = k < g->dim && g->bc[2 * k] == MFWH_BC_DIRICHLET ? 1 : 0;
+        fa.h[k] = k < g->dim ? g->len[k] / (g->n[k] - 1) : 0.0;
+        for (int j = 0; j < 3; ++j) fa.w[k][j] = ws[k][j];
+      }
+      HIPCHK(launch_fold_boundary_data(fa, pr.bdata, pr.varc ? pr.W.c64 : nullptr, pr.W.f64,
+                                       pr.s));
+    }
+    if (pr.fp32)
+      HIPCHK(launch_copy_fields<double, float>(pr.G, nf, pr.W.f64, il, pr.W.f32, il, 0, pr.s));
+  }
+  if (pr.varc) {
+    if (pr.fp32)
+      HIPCHK(launch_copy_fields<double, float>(pr.G, 1, pr.grid->c, cl, pr.W.c32, ci, 1, pr.s));
+    if (pr.implicit)
+      for (int l = 1; l < pr.W.nlev; ++l)
+        HIPCHK(launch_mg_inject(pr.W.lev[l - 1], pr.W.lev[l - 1].c2, pr.W.lev[l], pr.W.mc2[l],
+                                pr.s));
+  }
+  return MFWH_OK;
+}
+
 
 // Target of the finalize stage.
 struct Out {
@@ -434,11 +541,42 @@ int mg_solve(Problem& pr, double* x, const double* b) {
   // the cycles the previous step needed, less one, run without a check (one
   // host synchronisation per step in the steady state)
   const int blind = std::max(0, std::min(pr.mg_prev - 1, pr.P.imp_max_cycles - 1));
-  for (int k = 0; k < blind; ++k) CHK(vcycle(pr, 0, x, b));
+  // solvers replay the first blind + 1 cycles and the residual norm as one
+  // recorded graph (b is always the same buffer, x one of three)
+  bool first_done = false;
+  if (pr.graphs) {
+    StepGraph& g = pr.mgg[std::make_pair(blind + 1, x)];
+    if (!g.x) {
+      hipStream_t cs;
+      HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+      hipStream_t keep = pr.s;
+      pr.s = cs;
+      hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed);
+      int rc = MFWH_OK;
+      for (int k = 0; k <= blind && e == hipSuccess && rc == MFWH_OK; ++k) rc = vcycle(pr, 0, x, b);
+      if (e == hipSuccess && rc == MFWH_OK)
+        e = launch_mg_resid(L, pr.grid->order, x, b, nullptr, W.partial, kRedBlocks, out2, cs);
+      hipError_t e2 = hipStreamEndCapture(cs, &g.g);
+      pr.s = keep;
+      (void)hipStreamDestroy(cs);
+      if (rc != MFWH_OK) return rc;
+      HIPCHK(e);
+      HIPCHK(e2);
+      HIPCHK(hipGraphInstantiate(&g.x, g.g, nullptr, nullptr, 0));
+    }
+    HIPCHK(hipGraphLaunch(g.x, pr.s));
+    first_done = true;
+  } else {
+    for (int k = 0; k < blind; ++k) CHK(vcycle(pr, 0, x, b));
+  }
   pr.mg_cycles += blind;
   for (int cyc = blind + 1;; ++cyc) {
-    CHK(vcycle(pr, 0, x, b));
-    HIPCHK(launch_mg_resid(L, pr.grid->order, x, b, nullptr, W.partial, kRedBlocks, out2, pr.s));
+    if (!first_done) {
+      CHK(vcycle(pr, 0, x, b));
+      HIPCHK(launch_mg_resid(L, pr.grid->order, x, b, nullptr, W.partial, kRedBlocks, out2,
+                             pr.s));
+    }
+    first_done = false;
     double h2[2];
     HIPCHK(hipMemcpyAsync(h2, out2, 2 * sizeof(double), hipMemcpyDeviceToHost, pr.s));
     HIPCHK(hipStreamSynchronize(pr.s));
@@ -545,7 +683,7 @@ int apply_t(Problem& pr, const double* v, ExtLayout vl, bool forcing, const Out&
   } else {
     wc4 = (T*)pr.W.w32c; wd4 = (T*)pr.W.w32d;
   }
-  const int spp = pr.G.dim == 2 ? ((wc4 && wd4) ? pr.spp : 0) : pr.spp;
+  const int spp = (wc4 && wd4) ? pr.spp : std::min(pr.spp, 1);
 
   StepArgs<T> a{};
   a.c2 = pr.varc ? c2 : nullptr;
@@ -554,6 +692,8 @@ int apply_t(Problem& pr, const double* v, ExtLayout vl, bool forcing, const Out&
   a.g = pr.G;
   stencil_weights<T>(pr.grid, a.wx, a.wy, a.wz);
   a.force = forcing ? 1 : 0;
+  a.refl = pr.refl;
+  for (int k = 0; k < 6; ++k) a.rg[k] = (T)pr.rg[k];
   LeapArgs<T> la{};
   la.c2 = a.c2;
   la.f = a.f;
@@ -677,7 +817,8 @@ int apply_t(Problem& pr, const double* v, ExtLayout vl, bool forcing, const Out&
     // unused slots repeat the last used accumulator (the kernels load every
     // slot unconditionally and store only the first nq)
     for (int j = nq; j < MFWH_MAX_NF; ++j) la.qm[j] = nq > 0 ? la.qm[nq - 1] : 0;
-    if (pr.G.dim == 3) return launch_leap3d<T>(la, pr.grid->order, pr.leap, s);
+    if (pr.G.dim == 3)
+      return launch_leap3d<T>(la, pr.grid->order, ns, ns == 2 ? pr.leap : pr.leap1, s);
     return launch_leap2d<T>(la, pr.grid->order, ns, pr.depth, pr.leap, s);
   };
   double bytes_all = 0.0;          // algorithmic bytes of the whole sequence
@@ -937,6 +1078,8 @@ int batch_sizes(int np, const mfwh_problem* P, int restart, std::vector<size_t>*
     if (P[i].grid.precision != MFWH_FP64)
       return fail(MFWH_EINVAL, "batched solves run in float64");
     if (P[i].grid.dim == 1) return fail(MFWH_EINVAL, "batched solves need dim 2 or 3");
+    if (reflective_faces(&P[i].grid) || P[i].grid.g)
+      return fail(MFWH_EINVAL, "batched solves take homogeneous Dirichlet faces");
     if (P[i].time.scheme != MFWH_EXPLICIT)
       return fail(MFWH_EINVAL, "batched solves use the explicit scheme");
     if (!P[i].time.omega || P[i].time.nf < 1 || P[i].time.nf > MFWH_MAX_NF)
@@ -1206,7 +1349,8 @@ int mfwh_apply(const mfwh_grid* g, const mfwh_time* t, const double* f, const do
   const ExtLayout al = abi_layout(g);
   Out o{v_out, al};
   CHK(apply_any(pr, pr.fp32, v_in, al, with_forcing != 0, o));
-  HIPCHK(launch_zero_boundary(g->dim, g->n, t->nf, v_out, pr.s));
+  HIPCHK(launch_boundary_fill(g->dim, g->n, t->nf, dirichlet_faces(g),
+                              with_forcing ? g->g : nullptr, v_out, pr.s));
   return MFWH_OK;
 }
 
@@ -1221,7 +1365,7 @@ int mfwh_solve_fixed_point(const mfwh_grid* g, const mfwh_time* t, const double*
   pr.graphs = g_graphs;
   CHK(prepare(pr, f));
   const ExtLayout al = abi_layout(g);
-  HIPCHK(launch_zero_boundary(g->dim, g->n, t->nf, v, pr.s));
+  HIPCHK(launch_boundary_fill(g->dim, g->n, t->nf, dirichlet_faces(g), g->g, v, pr.s));
   const double denom = (double)t->nf * (double)pr.G.npts();
   double r1 = 0.0, r = 0.0;
   int k = 0;
@@ -1356,7 +1500,7 @@ int mfwh_solve_gmres(const mfwh_grid* g, const mfwh_time* t, const double* f, do
     }
   }
   HIPCHK(launch_copy_fields<double, double>(pr.G, nf, X, il, v, al, 0, pr.s));
-  HIPCHK(launch_zero_boundary(g->dim, g->n, nf, v, pr.s));
+  HIPCHK(launch_boundary_fill(g->dim, g->n, nf, dirichlet_faces(g), g->g, v, pr.s));
   HIPCHK(hipStreamSynchronize(pr.s));
   if (info) {
     info->iterations = kr.its;

@@ -43,6 +43,8 @@ struct StepArgs {
   double kap0[MFWH_MAX_NF];
   int first;
   int force;
+  int refl;             // bit 2a / 2a+1: lower / upper face of axis a is Neumann or Robin
+  T rg[6];              // per face: -2 h r of a Robin face (0: Neumann, Dirichlet)
   int mask;             // bit m: filter m is updated at this step
   int nchunk;           // chunks along the march axis
   int chunk;            // rows / planes per chunk
@@ -118,10 +120,12 @@ hipError_t launch_leap2d(LeapArgs<T>& a, int order, int steps, int depth, const 
                          hipStream_t s);
 // Default launch shapes of the streamlined kernels.
 LaunchShape default_leap_shape(const Geom& g, int steps);
-// leap3d.hip: one streamlined 3D step (z-march), shape (64, 4) or (64, 8)
+// leap3d.hip: one streamlined 3D step (z-march; shape 64 x 4 or 64 x 8) or
+// two fused steps (shape 64 x 16 or 32 x 16)
 template <typename T>
-hipError_t launch_leap3d(LeapArgs<T>& a, int order, const LaunchShape& ls, hipStream_t s);
-LaunchShape default_leap3d_shape(const Geom& g);
+hipError_t launch_leap3d(LeapArgs<T>& a, int order, int steps, const LaunchShape& ls,
+                         hipStream_t s);
+LaunchShape default_leap3d_shape(const Geom& g, int steps);
 
 // mg2d.hip: implicit trapezoid steps and their multigrid solver (2D, float64)
 // One multigrid level: interior nx x ny points at row pitch py; the operator
@@ -218,6 +222,26 @@ hipError_t launch_finalize(const Geom& g, int nf, const double* q, const double*
                            double* out, ExtLayout ol, double* partial, int nblk_red,
                            hipStream_t s);
 hipError_t launch_zero_boundary(int dim, const int* n, int nf, double* v, hipStream_t s);
+// points of nf full-grid arrays on the faces in `faces` (bit 2a lower, 2a+1
+// upper face of axis a) := data (same layout) or 0 when data is null
+hipError_t launch_boundary_fill(int dim, const int* n, int nf, int faces, const double* data,
+                                double* v, hipStream_t s);
+
+// bc.hip: boundary data g folded into the forcing.  For every stored point
+// f[m] -= c^2 * (the part of Delta_h that the data g_m of the Dirichlet and
+// Neumann/Robin faces contributes through boundary points and ghosts).
+struct FoldArgs {
+  Geom G;
+  int n[3];             // grid points per axis (caller layout)
+  int lo[3];            // 1 if the lower face of the axis is Dirichlet (first stored point = 1)
+  int refl;             // bit 2a / 2a+1: lower / upper face of axis a is Neumann or Robin
+  double w[3][3];       // stencil weights per axis (w[a][k]: offset +-k)
+  double h[3];
+  int R;                // stencil radius (1: order 2, 2: order 4)
+  int nf;
+};
+hipError_t launch_fold_boundary_data(const FoldArgs& a, const double* g, const double* c2,
+                                     double* f, hipStream_t s);
 hipError_t launch_fill(double* x, long long n, double v, hipStream_t s);
 template <typename T>
 hipError_t launch_fill_t(T* x, long long n, T v, hipStream_t s);

@@ -40,14 +40,29 @@ __device__ __forceinline__ int xcd_remap(int b, int grid) {
 inline int pad8(int n) { return (n + 7) & ~7; }
 
 // value of the extended field on one axis line: index e in [-2, n+1] along an
-// axis with n interior points; `at(k)` reads interior index k.
+// axis with n stored points; `at(k)` reads stored index k.  fl / fh select
+// the rule of the lower / upper face:
+//   0 Dirichlet: the boundary point is not stored and reads 0 (nonzero
+//     boundary data is carried by the forcing), the order-4 ghost beyond it
+//     is the odd reflection of the first stored point;
+//   1 Neumann / Robin: the boundary point is stored index 0 (n-1) and the
+//     ghost at distance k is W_k + k c W_0 with c = -2 h r (r = 0: Neumann),
+//     the data term again being carried by the forcing.
 template <typename T, typename F>
-__device__ __forceinline__ T ext_line(int e, int n, F at) {
+__device__ __forceinline__ T ext_line(int e, int n, F at, int fl = 0, int fh = 0, T cl = T(0),
+                                      T ch = T(0)) {
   if (e >= 0 && e < n) return at(e);
-  if (e == -1 || e == n) return T(0);
-  if (e == -2) return -at(0);
-  if (e == n + 1) return -at(n - 1);
-  return T(0);
+  // indices clamped to [0, n): lanes past the ghost range read valid memory
+  // (their values are never used)
+  if (e < 0) {
+    if (fl) return at(min(-e, n - 1)) + T(-e) * cl * at(0);
+    return e == -1 ? T(0) : -at(0);
+  }
+  if (fh) {
+    const int k = e - (n - 1);
+    return at(max(n - 1 - k, 0)) + T(k) * ch * at(n - 1);
+  }
+  return e == n ? T(0) : -at(n - 1);
 }
 
 // -------------------------------------------------------------------------
@@ -93,7 +108,9 @@ __global__ void __launch_bounds__(256) k_step1d(StepArgs<T> a) {
   T lap = a.wx[0] * c;
 #pragma unroll
   for (int k = 1; k <= R; ++k)
-    lap += a.wx[k] * (ext_line<T>(i - k, n, at) + ext_line<T>(i + k, n, at));
+    lap += a.wx[k] * (ext_line<T>(i - k, n, at, a.refl & 1, (a.refl >> 1) & 1, a.rg[0],
+                                  a.rg[1]) +
+                      ext_line<T>(i + k, n, at, a.refl & 1, (a.refl >> 1) & 1, a.rg[0], a.rg[1]));
   point_update(a, i, c, lap);
 }
 
@@ -115,22 +132,26 @@ __device__ __forceinline__ void body2d(const StepArgs<T>& a, int lb, T (*row)[BX
   const T* __restrict__ wc = a.wc;
   auto col = [&](int k) { return wc[(long long)k * py + ic]; };
 
+  const int xl = a.refl & 1, xh = (a.refl >> 1) & 1, yl = (a.refl >> 2) & 1,
+            yh = (a.refl >> 3) & 1;
   T w[2 * R + 1];
 #pragma unroll
-  for (int k = 0; k < 2 * R; ++k) w[k + 1] = ext_line<T>(y0 - R + k, nyi, col);
+  for (int k = 0; k < 2 * R; ++k)
+    w[k + 1] = ext_line<T>(y0 - R + k, nyi, col, yl, yh, a.rg[2], a.rg[3]);
 
   int buf = 0;
   for (int y = y0; y < y1; ++y) {
 #pragma unroll
     for (int k = 0; k < 2 * R; ++k) w[k] = w[k + 1];
-    w[2 * R] = ext_line<T>(y + R, nyi, col);
+    w[2 * R] = ext_line<T>(y + R, nyi, col, yl, yh, a.rg[2], a.rg[3]);
     const long long rowoff = (long long)y * py;
     auto rowat = [&](int k) { return wc[rowoff + k]; };
     T* rb = row[buf];
-    // centre row, extended in x for lanes past the last interior column
-    rb[R + tid] = act ? w[R] : ext_line<T>(i, nxi, rowat);
-    if (tid < R) rb[tid] = ext_line<T>(bx * BX - R + tid, nxi, rowat);
-    if (tid >= BX - R) rb[tid + 2 * R] = ext_line<T>(bx * BX + R + tid, nxi, rowat);
+    // centre row, extended in x for lanes past the last stored column
+    rb[R + tid] = act ? w[R] : ext_line<T>(i, nxi, rowat, xl, xh, a.rg[0], a.rg[1]);
+    if (tid < R) rb[tid] = ext_line<T>(bx * BX - R + tid, nxi, rowat, xl, xh, a.rg[0], a.rg[1]);
+    if (tid >= BX - R)
+      rb[tid + 2 * R] = ext_line<T>(bx * BX + R + tid, nxi, rowat, xl, xh, a.rg[0], a.rg[1]);
     __syncthreads();
     if (act) {
       T lap = (a.wx[0] + a.wy[0]) * w[R];
@@ -174,25 +195,27 @@ __device__ __forceinline__ void body3d(const StepArgs<T>& a, int lb,
   const long long colbase = (long long)jc * py + ic;
   auto zcol = [&](int k) { return wc[(long long)k * pz + colbase]; };
 
+  const int rf = a.refl;
   T w[2 * R + 1];
 #pragma unroll
-  for (int k = 0; k < 2 * R; ++k) w[k + 1] = ext_line<T>(z0 - R + k, nzi, zcol);
+  for (int k = 0; k < 2 * R; ++k)
+    w[k + 1] = ext_line<T>(z0 - R + k, nzi, zcol, (rf >> 4) & 1, (rf >> 5) & 1, a.rg[4], a.rg[5]);
 
   int buf = 0;
   for (int z = z0; z < z1; ++z) {
 #pragma unroll
     for (int k = 0; k < 2 * R; ++k) w[k] = w[k + 1];
-    w[2 * R] = ext_line<T>(z + R, nzi, zcol);
+    w[2 * R] = ext_line<T>(z + R, nzi, zcol, (rf >> 4) & 1, (rf >> 5) & 1, a.rg[4], a.rg[5]);
     const long long zoff = (long long)z * pz;
     // extended plane value at (ii, jj) of plane z; no corner is ever needed
     auto plane = [&](int ii, int jj) -> T {
       if (jj >= 0 && jj < nyi) {
         auto rowat = [&](int k) { return wc[zoff + (long long)jj * py + k]; };
-        return ext_line<T>(ii, nxi, rowat);
+        return ext_line<T>(ii, nxi, rowat, rf & 1, (rf >> 1) & 1, a.rg[0], a.rg[1]);
       }
       if (ii < 0 || ii >= nxi) return T(0);
       auto colat = [&](int k) { return wc[zoff + (long long)k * py + ii]; };
-      return ext_line<T>(jj, nyi, colat);
+      return ext_line<T>(jj, nyi, colat, (rf >> 2) & 1, (rf >> 3) & 1, a.rg[2], a.rg[3]);
     };
     auto& tb = tile[buf];
     tb[R + ly][R + lx] = act ? w[R] : plane(i, j);
@@ -559,8 +582,10 @@ hipError_t launch_finalize(const Geom& g, int nf, const double* q, const double*
   return hipGetLastError();
 }
 
-// zero the boundary points of nf caller arrays (full-grid layout)
-__global__ void __launch_bounds__(256) k_zero_boundary(int dim, int n0, int n1, int n2, int nf,
+// points of nf caller arrays (full-grid layout) on the faces in `faces`
+// (bit 2a: lower, 2a+1: upper face of axis a) := data (same layout) or 0
+__global__ void __launch_bounds__(256) k_boundary_fill(int dim, int n0, int n1, int n2, int nf,
+                                                       int faces, const double* __restrict__ data,
                                                        double* v) {
   const long long tot = (long long)n0 * n1 * n2;
   for (long long p = (long long)blockIdx.x * 256 + threadIdx.x; p < tot * nf;
@@ -569,17 +594,23 @@ __global__ void __launch_bounds__(256) k_zero_boundary(int dim, int n0, int n1, 
     const int i = (int)(r % n0);
     const int j = (int)((r / n0) % n1);
     const int k = (int)(r / ((long long)n0 * n1));
-    const bool bnd = i == 0 || i == n0 - 1 || (dim >= 2 && (j == 0 || j == n1 - 1)) ||
-                     (dim >= 3 && (k == 0 || k == n2 - 1));
-    if (bnd) v[p] = 0.0;
+    const bool bnd = (i == 0 && (faces & 1)) || (i == n0 - 1 && (faces & 2)) ||
+                     (dim >= 2 && ((j == 0 && (faces & 4)) || (j == n1 - 1 && (faces & 8)))) ||
+                     (dim >= 3 && ((k == 0 && (faces & 16)) || (k == n2 - 1 && (faces & 32))));
+    if (bnd) v[p] = data ? data[p] : 0.0;
   }
 }
 
-hipError_t launch_zero_boundary(int dim, const int* n, int nf, double* v, hipStream_t s) {
+hipError_t launch_boundary_fill(int dim, const int* n, int nf, int faces, const double* data,
+                                double* v, hipStream_t s) {
   const long long tot = (long long)n[0] * n[1] * n[2] * nf;
   const int nb = (int)std::min<long long>((tot + 255) / 256, 4096);
-  k_zero_boundary<<<nb, 256, 0, s>>>(dim, n[0], n[1], n[2], nf, v);
+  k_boundary_fill<<<nb, 256, 0, s>>>(dim, n[0], n[1], n[2], nf, faces, data, v);
   return hipGetLastError();
+}
+
+hipError_t launch_zero_boundary(int dim, const int* n, int nf, double* v, hipStream_t s) {
+  return launch_boundary_fill(dim, n, nf, 0x3f, nullptr, v, s);
 }
 
 template <typename T>

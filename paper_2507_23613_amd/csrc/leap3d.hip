@@ -6,7 +6,8 @@
 // operands of plane z+1 are requested before plane z is computed (two
 // register sets alternate).
 //
-// A BX x BY block owns a column tile and marches a chunk of z-planes (2.5D):
+// One step per pass: a BX x BY block owns a column tile and marches a chunk
+// of z-planes (2.5D):
 // z-neighbours in a register window, x/y-neighbours from a double-buffered
 // LDS plane tile.  The tile's x- and y-halo (2R (BX + BY) values, no
 // corners) is spread over the block's threads, each with a fixed source
@@ -169,6 +170,194 @@ __global__ void __launch_bounds__(BX * BY) k_leap3d(LeapArgs<T> a) {
   }
 }
 
+// -------------------------------------------------------------------------
+// two steps per pass (temporal blocking, 3D)
+// -------------------------------------------------------------------------
+// A BX x BY block owns a (BX - 4R) x (BY - 4R) column tile; thread (lx, ly)
+// sits on column (x0 - 2R + lx, y0 - 2R + ly).  W^{n+1} is computed on the
+// owned tile plus an R-wide ring (threads R .. BX-R-1, R .. BY-R-1) and on R
+// planes beyond each end of the z-chunk, so the second step needs nothing
+// from other blocks; every accumulator is read and written once per two
+// steps.  Both x/y-neighbour planes (W^n on plane z+R for the first step,
+// W^{n+1} on plane z for the second) go to LDS before the iteration's one
+// barrier.
+template <typename T, int QM>
+struct Plane2 {
+  T w, sw;          // new W^n value (plane z + 2R) and its factor
+  T p, c;           // W^{n-1}, c^2 on plane z + R
+  T f1, f2;         // forcing of both steps on plane z + R
+  double q[QM];     // accumulators on plane z
+};
+
+template <typename T, int R, int BX, int BY, int QM, bool FORCE>
+__global__ void __launch_bounds__(BX * BY) k_leap3d_x2(LeapArgs<T> a) {
+  constexpr int OX = BX - 4 * R, OY = BY - 4 * R;
+  __shared__ T pn[2][BY][BX];             // W^n on plane z + R
+  __shared__ T p1[2][BY][BX];             // W^{n+1} on plane z
+  const int lb = xcd_tile3(blockIdx.x, gridDim.x);
+  if (lb >= a.nblocks) return;
+  const int cz = lb % a.nchunk;
+  const int t2 = lb / a.nchunk;
+  const int tx = t2 % a.ntx;
+  const int ty = t2 / a.ntx;
+  const int lx = threadIdx.x, ly = threadIdx.y;
+  const int nxi = a.g.nxi, nyi = a.g.nyi, nzi = a.g.nzi;
+  const long long py = a.g.py, pz = a.g.pz, fs = a.g.fs;
+  const int x0 = tx * OX, y0 = ty * OY;
+  const int ex = x0 - 2 * R + lx, ey = y0 - 2 * R + ly;
+  T sx, sy;
+  const int ix = ext_src3(ex, nxi, sx), iy = ext_src3(ey, nyi, sy);
+  const T sxy = sx * sy;
+  const bool inxy = ex >= 0 && ex < nxi && ey >= 0 && ey < nyi;
+  const bool mid = inxy && lx >= R && lx < BX - R && ly >= R && ly < BY - R;
+  const bool own = inxy && lx >= 2 * R && lx < BX - 2 * R && ly >= 2 * R && ly < BY - 2 * R;
+  const long long col = (long long)iy * py + ix;
+  const int qx = min(max(ex, x0), min(x0 + OX, nxi) - 1);
+  const int qy = min(max(ey, y0), min(y0 + OY, nyi) - 1);
+  const long long qcol = (long long)qy * py + qx;       // an owned column
+  const T* __restrict__ c2p = a.c2 ? a.c2 : a.wp;       // read and ignored when c = 1
+  const int z0 = cz * a.chunk;
+  const int z1 = min(z0 + a.chunk, nzi);
+  const T* __restrict__ wc = a.wc;
+  auto ldw = [&](int z, T& sg) -> T {
+    T sz;
+    const int iz = ext_src3(z, nzi, sz);
+    sg = sxy * sz;
+    return wc[(long long)iz * pz + col];
+  };
+
+  T wn[2 * R + 1];     // W^n along z: planes z .. z+2R at iteration z
+  T w1[2 * R + 1];     // W^{n+1} along z: planes z-R .. z+R
+  T cw[R + 1];         // c^2 of planes z .. z+R
+  T fw[R + 1];         // second-step forcing of planes z .. z+R
+#pragma unroll
+  for (int k = 0; k < 2 * R; ++k) {
+    T sg;
+    const T v = ldw(z0 - 2 * R + k, sg);
+    wn[k + 1] = sg * v;
+  }
+#pragma unroll
+  for (int k = 0; k <= 2 * R; ++k) w1[k] = T(0);
+#pragma unroll
+  for (int k = 0; k <= R; ++k) {
+    cw[k] = T(1);
+    fw[k] = T(0);
+  }
+
+  auto fetch = [&](Plane2<T, QM>& o, int z) {
+    o.w = ldw(z + 2 * R, o.sw);
+    const int e1 = min(max(z + R, 0), nzi - 1);
+    const long long i1 = (long long)e1 * pz + col;
+    o.p = a.wp[i1];
+    o.c = c2p[i1];
+    o.f1 = o.f2 = T(0);
+    if (FORCE) {
+#pragma unroll
+      for (int m = 0; m < MFWH_MAX_NF; ++m) {
+        if (a.phi1[m] != T(0) || a.phi2[m] != T(0)) {
+          const T fv = a.f[m * fs + i1];
+          if (a.phi1[m] != T(0)) o.f1 += a.phi1[m] * fv;
+          if (a.phi2[m] != T(0)) o.f2 += a.phi2[m] * fv;
+        }
+      }
+    }
+    const long long i2 = (long long)max(z, z0) * pz + qcol;
+#pragma unroll
+    for (int q = 0; q < QM; ++q) o.q[q] = a.q[a.qm[q] * fs + i2];
+  };
+  auto process = [&](int z, const Plane2<T, QM>& o, int buf) {
+#pragma unroll
+    for (int k = 0; k < 2 * R; ++k) wn[k] = wn[k + 1];
+    wn[2 * R] = o.sw * o.w;
+#pragma unroll
+    for (int k = 0; k < 2 * R; ++k) w1[k] = w1[k + 1];
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      cw[k] = cw[k + 1];
+      fw[k] = fw[k + 1];
+    }
+    pn[buf][ly][lx] = wn[R];
+    // W^{n+1} plane z with its x/y-extension: 0 on boundary columns, the
+    // odd-reflection ghosts written by the interior columns they mirror
+    const bool ghost = R == 2 && (ex == -2 || ex == nxi + 1 || ey == -2 || ey == nyi + 1);
+    if (!ghost) p1[buf][ly][lx] = w1[R];
+    if (R == 2 && inxy) {
+      if (ex == 0) p1[buf][ly][lx - 2] = -w1[R];
+      if (ex == nxi - 1 && lx + 2 < BX) p1[buf][ly][lx + 2] = -w1[R];
+      if (ey == 0) p1[buf][ly - 2][lx] = -w1[R];
+      if (ey == nyi - 1 && ly + 2 < BY) p1[buf][ly + 2][lx] = -w1[R];
+    }
+    __syncthreads();
+    // first step: W^{n+1} on plane ez = z + R
+    const int ez = z + R;
+    T v = T(0);
+    if (mid && ez >= 0 && ez < nzi) {
+      T lap = (a.wx[0] + a.wy[0] + a.wz[0]) * wn[R];
+#pragma unroll
+      for (int k = 1; k <= R; ++k)
+        lap += a.wx[k] * (pn[buf][ly][lx - k] + pn[buf][ly][lx + k]) +
+               a.wy[k] * (pn[buf][ly - k][lx] + pn[buf][ly + k][lx]) +
+               a.wz[k] * (wn[R - k] + wn[R + k]);
+      const T c2v = a.c2 ? o.c : T(1);
+      v = a.cA * wn[R] + a.cB * o.p + a.cC * (c2v * lap - o.f1);
+    }
+    if (R == 2 && ez == nzi + 1) v = -w1[2 * R - 2];   // ghost plane: reflects plane nzi-1
+    w1[2 * R] = v;
+    if (R == 2 && ez == 0) w1[2 * R - 2] = -v;         // ghost plane -2 reflects plane 0
+    cw[R] = a.c2 ? o.c : T(1);
+    fw[R] = o.f2;
+    // second step: W^{n+2} on plane z
+    if (z >= z0 && own) {
+      T lap = (a.wx[0] + a.wy[0] + a.wz[0]) * w1[R];
+#pragma unroll
+      for (int k = 1; k <= R; ++k)
+        lap += a.wx[k] * (p1[buf][ly][lx - k] + p1[buf][ly][lx + k]) +
+               a.wy[k] * (p1[buf][ly - k][lx] + p1[buf][ly + k][lx]) +
+               a.wz[k] * (w1[R - k] + w1[R + k]);
+      const T v2 = a.cA * w1[R] + a.cB * wn[0] + a.cC * (cw[0] * lap - fw[0]);
+      const long long idx = (long long)z * pz + (long long)ey * py + ex;
+      a.w1[idx] = w1[R];
+      a.w2[idx] = v2;
+      const double d1 = (double)w1[R], d2 = (double)v2;
+#pragma unroll
+      for (int q = 0; q < QM; ++q)
+        if (q < a.nq) a.q[a.qm[q] * fs + idx] = (o.q[q] + a.kk[0][q] * d1) + a.kk[1][q] * d2;
+    }
+  };
+
+  // fetches past the last plane re-read the last plane (valid, unused)
+  Plane2<T, QM> ra, rb;
+  const int r0 = z0 - 2 * R;
+  fetch(ra, r0);
+  for (int z = r0; z < z1; z += 2) {
+    fetch(rb, min(z + 1, z1 - 1));
+    process(z, ra, 0);
+    if (z + 1 >= z1) break;
+    fetch(ra, min(z + 2, z1 - 1));
+    process(z + 1, rb, 1);
+  }
+}
+
+template <typename T, int R, int BX, int BY>
+hipError_t launch_x2_3(LeapArgs<T>& a, hipStream_t s) {
+  const Geom& g = a.g;
+  a.ntx = (g.nxi + BX - 4 * R - 1) / (BX - 4 * R);
+  a.nty = (g.nyi + BY - 4 * R - 1) / (BY - 4 * R);
+  a.nchunk = (g.nzi + a.chunk - 1) / a.chunk;
+  a.nblocks = a.ntx * a.nty * a.nchunk;
+  const int grid = pad8(a.nblocks);
+  const dim3 blk(BX, BY);
+  const bool q4 = a.nq <= 4;
+  if (a.force) {
+    if (q4) k_leap3d_x2<T, R, BX, BY, 4, true><<<grid, blk, 0, s>>>(a);
+    else k_leap3d_x2<T, R, BX, BY, 8, true><<<grid, blk, 0, s>>>(a);
+  } else {
+    if (q4) k_leap3d_x2<T, R, BX, BY, 4, false><<<grid, blk, 0, s>>>(a);
+    else k_leap3d_x2<T, R, BX, BY, 8, false><<<grid, blk, 0, s>>>(a);
+  }
+  return hipGetLastError();
+}
+
 template <typename T, int R, int BX, int BY>
 hipError_t launch_shape3(LeapArgs<T>& a, hipStream_t s) {
   const Geom& g = a.g;
@@ -190,7 +379,12 @@ hipError_t launch_shape3(LeapArgs<T>& a, hipStream_t s) {
 }
 
 template <typename T, int R>
-hipError_t launch_r3(LeapArgs<T>& a, const LaunchShape& ls, hipStream_t s) {
+hipError_t launch_r3(LeapArgs<T>& a, int steps, const LaunchShape& ls, hipStream_t s) {
+  if (steps == 2) {
+    if (ls.bx == 64 && ls.by == 16) return launch_x2_3<T, R, 64, 16>(a, s);
+    if (ls.bx == 32 && ls.by == 16) return launch_x2_3<T, R, 32, 16>(a, s);
+    return hipErrorInvalidValue;
+  }
   if (ls.bx == 64 && ls.by == 4) return launch_shape3<T, R, 64, 4>(a, s);
   if (ls.bx == 64 && ls.by == 8) return launch_shape3<T, R, 64, 8>(a, s);
   return hipErrorInvalidValue;
@@ -199,22 +393,30 @@ hipError_t launch_r3(LeapArgs<T>& a, const LaunchShape& ls, hipStream_t s) {
 }  // namespace
 
 template <typename T>
-hipError_t launch_leap3d(LeapArgs<T>& a, int order, const LaunchShape& ls, hipStream_t s) {
-  if (a.g.dim != 3 || a.nq < 0 || a.nq > MFWH_MAX_NF) return hipErrorInvalidValue;
+hipError_t launch_leap3d(LeapArgs<T>& a, int order, int steps, const LaunchShape& ls,
+                         hipStream_t s) {
+  if (a.g.dim != 3 || a.nq < 0 || a.nq > MFWH_MAX_NF || (steps != 1 && steps != 2))
+    return hipErrorInvalidValue;
+  if (steps == 2 && (a.w1 == a.wc || a.w1 == a.wp || a.w2 == a.wc || a.w2 == a.wp ||
+                     a.w1 == a.w2 || !a.w2))
+    return hipErrorInvalidValue;
   a.chunk = std::max(1, ls.chunk);
-  return order == 2 ? launch_r3<T, 1>(a, ls, s) : launch_r3<T, 2>(a, ls, s);
+  return order == 2 ? launch_r3<T, 1>(a, steps, ls, s) : launch_r3<T, 2>(a, steps, ls, s);
 }
-template hipError_t launch_leap3d<double>(LeapArgs<double>&, int, const LaunchShape&, hipStream_t);
-template hipError_t launch_leap3d<float>(LeapArgs<float>&, int, const LaunchShape&, hipStream_t);
+template hipError_t launch_leap3d<double>(LeapArgs<double>&, int, int, const LaunchShape&,
+                                          hipStream_t);
+template hipError_t launch_leap3d<float>(LeapArgs<float>&, int, int, const LaunchShape&,
+                                         hipStream_t);
 
-LaunchShape default_leap3d_shape(const Geom& g) {
+LaunchShape default_leap3d_shape(const Geom& g, int steps) {
   LaunchShape ls;
   ls.bx = 64;
-  ls.by = 4;
-  const long long tiles = ((g.nxi + 63) / 64) * (long long)((g.nyi + 3) / 4);
+  ls.by = steps == 2 ? 16 : 4;
+  const int ox = steps == 2 ? 56 : 64, oy = steps == 2 ? 8 : 4;   // order-4 halo
+  const long long tiles = ((g.nxi + ox - 1) / ox) * (long long)((g.nyi + oy - 1) / oy);
   const long long target_waves = 256LL * 16;
-  long long ch = tiles * 4 * g.nzi / target_waves;
-  ls.chunk = (int)std::min<long long>(std::max<long long>(ch, 4), 64);
+  long long ch = tiles * (ls.bx * ls.by / 64) * g.nzi / target_waves;
+  ls.chunk = (int)std::min<long long>(std::max<long long>(ch, steps == 2 ? 8 : 4), 64);
   return ls;
 }
 

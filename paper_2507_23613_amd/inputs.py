@@ -206,3 +206,48 @@ def small(seed, shape, nf, order, lo=4.0, hi=20.0, varc=False, lengths=None,
     return dict(name=f"small-{len(shape)}d-{'x'.join(map(str, shape))}-nf{nf}-o{order}",
                 shape=shape, lengths=lengths, order=order, omega=omega, f=f, c=c,
                 np=np_, cfl=cfl, filter=filter)
+
+
+def smooth_boundary_data(rng, shape, lengths, nf, terms=3):
+    """Boundary data g_m on the full grid (read on boundary points only): a
+    sum of ``terms`` products of cosines cos(k_a x_a + p_a) with integer
+    wavenumbers k_a ~ U{0..3} pi / len_a, phases ~ U(0, 2 pi), amplitudes
+    ~ N(0, 1)."""
+    d = len(shape)
+    X = _grid_coords(shape, lengths)
+    g = np.zeros((nf,) + tuple(shape))
+    for m in range(nf):
+        for _ in range(terms):
+            A = rng.standard_normal()
+            term = np.ones(shape)
+            for a in range(d):
+                k = rng.integers(0, 4) * np.pi / lengths[a]
+                term = term * np.cos(k * X[a] + rng.uniform(0.0, 2.0 * np.pi))
+            g[m] += A * term
+    return g
+
+
+def bc_case(seed, shape, nf, order, bc, with_data=True, lo=4.0, hi=20.0, varc=False,
+            filter="optimised", cfl=0.5):
+    """Small random workload with other boundary conditions: ``bc`` holds one
+    (lo, hi) pair of face specs per NumPy axis, ("D",), ("N",) or ("R", r).
+    Forcings are Gaussian sums that stay nonzero on Neumann/Robin faces (whose
+    points are unknowns); with ``with_data`` the boundary data are
+    ``smooth_boundary_data``.  Draw order: omega, forcings, c, g."""
+    w = small(seed, shape, nf, order, lo=lo, hi=hi, varc=varc, filter=filter, cfl=cfl)
+    rng = np.random.default_rng(seed + 7919)
+    shape = w["shape"]
+    # forcings again without the zeroed boundary
+    f = np.zeros((nf,) + shape)
+    for m in range(nf):
+        for _ in range(3):
+            A = rng.standard_normal()
+            width = rng.uniform(0.08, 0.15)
+            x0 = [rng.uniform(0.2, 0.8) * w["lengths"][a] for a in range(len(shape))]
+            f[m] += gaussian(shape, w["lengths"], x0, A, 1.0 / width)
+    w["f"] = f
+    w["bc"] = [tuple(tuple(s) for s in pair) for pair in bc]
+    w["g"] = smooth_boundary_data(rng, shape, w["lengths"], nf) if with_data else None
+    tag = "".join(s[0] for pair in bc for s in pair)
+    w["name"] = w["name"] + f"-bc{tag}" + ("-g" if with_data else "")
+    return w

@@ -27,7 +27,11 @@ class GpuProblem:
         self.c = None if w["c"] is None else torch.as_tensor(
             np.ascontiguousarray(w["c"]), dtype=torch.float64, device=self.device)
         cmax = 1.0 if w["c"] is None else float(np.max(w["c"]))
-        self.grid = L.make_grid(self.shape, w["lengths"], w["order"], precision, self.c)
+        self.bc = w.get("bc")
+        self.g = None if w.get("g") is None else torch.as_tensor(
+            np.ascontiguousarray(w["g"]), dtype=torch.float64, device=self.device)
+        self.grid = L.make_grid(self.shape, w["lengths"], w["order"], precision, self.c,
+                                self.bc, self.g)
         self.scheme = scheme
         if time is not None:
             T, dt, nt = time
@@ -67,7 +71,11 @@ class GpuProblem:
 
     @property
     def interior_points(self):
-        return int(np.prod([s - 2 for s in self.shape]))
+        """Unknown points per field (points off Dirichlet faces)."""
+        if self.bc is None:
+            return int(np.prod([s - 2 for s in self.shape]))
+        return int(np.prod([s - (lo[0] == "D") - (hi[0] == "D")
+                            for s, (lo, hi) in zip(self.shape, self.bc)]))
 
     def zeros(self):
         return torch.zeros((self.nf,) + self.shape, dtype=torch.float64, device=self.device)

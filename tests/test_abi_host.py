@@ -215,3 +215,39 @@ def test_small_omega_dt_first_window_is_whole():
         _, pl = workload.setup(dict(w, f=None), filt="traditional")
         assert pl.npm[0] == w["np"] and pl.nt == nt
         assert list(pl.npm) == list(info["npm"])
+
+
+def test_boundary_condition_validation():
+    """Face conditions are checked on the host (mfwh_grid.bc / robin)."""
+    N, D = ("N",), ("D",)
+    t = L.make_time([5.0, 9.0], 1.0, 0.01)
+    ok = L.make_grid((17, 17), order=4, bc=[(N, D), (D, N)])
+    assert L.mfwh_workspace_bytes(ok, t, 0) > 0
+    # Robin faces need order 2
+    assert L.mfwh_workspace_bytes(L.make_grid((17, 17), order=4, bc=[(D, ("R", 1.0)), (D, D)]),
+                                  t, 0) == 0
+    assert L.mfwh_workspace_bytes(L.make_grid((17, 17), order=2, bc=[(D, ("R", 1.0)), (D, D)]),
+                                  t, 0) > 0
+    # negative Robin coefficient
+    assert L.mfwh_workspace_bytes(L.make_grid((17, 17), order=2, bc=[(D, ("R", -1.0)), (D, D)]),
+                                  t, 0) == 0
+    # unknown code, and a face beyond dim
+    g = L.make_grid((17, 17), order=2)
+    g.bc[0] = 7
+    assert L.mfwh_workspace_bytes(g, t, 0) == 0
+    g = L.make_grid((17, 17), order=2)
+    g.bc[4] = 1
+    assert L.mfwh_workspace_bytes(g, t, 0) == 0
+    # order 4: an axis with a Neumann face needs 4 points (3 unknowns)
+    assert L.mfwh_workspace_bytes(L.make_grid((3, 17), order=4, bc=[(D, N), (D, D)]), t, 0) == 0
+    assert L.mfwh_workspace_bytes(L.make_grid((4, 17), order=4, bc=[(D, N), (D, D)]), t, 0) > 0
+    # Neumann faces add unknowns: more workspace than all-Dirichlet
+    assert L.mfwh_workspace_bytes(L.make_grid((17, 127), order=2, bc=[(N, N), (N, N)]), t, 0) > \
+        L.mfwh_workspace_bytes(L.make_grid((17, 127), order=2), t, 0)
+
+
+@pytest.mark.skipif(not _no_gpu(), reason="uses placeholder device pointers: host-only check")
+def test_robin_stability_limit():
+    """A large Robin coefficient raises the spectral radius of Delta_h beyond
+    what the planned dt allows: rejected before any device work."""
+    _bad(-3, grid=L.make_grid((17, 17), order=2, bc=[(("R", 1000.0), ("N",)), (("D",), ("D",))]))

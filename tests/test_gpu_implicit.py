@@ -144,3 +144,23 @@ def test_implicit_full_size_helmholtz_fixed_point():
     b = gp.nt * 1e-12 * (1 + 0.5 * gp.dt ** 2 * lam)
     print(f"implicit 1025^2 fixed point: N_t={gp.nt} rel={e:.2e} bar={b:.1e}")
     assert e < b
+
+
+def test_implicit_graph_replay_matches_eager():
+    """Solvers replay the multigrid cycles of each step from recorded graphs;
+    the same GMRES with graphs off launches them one by one: same kernels in
+    the same order, so the same iterates bit for bit."""
+    L = _L()
+    w = inputs.small(seed=14, shape=(33, 33), nf=2, order=4)
+    res = {}
+    for graphs in (1, 0):
+        try:
+            L.mfwh_set_option(L.MFWH_OPT_GRAPHS, graphs)
+            gp = _gp(w, restart=20, imp_tol=1e-11)
+            v, info = gp.gmres(max_iter=60, tol=1e-10)
+        finally:
+            L.mfwh_set_option(L.MFWH_OPT_GRAPHS, 1)
+        res[graphs] = (v.cpu().numpy(), info)
+    assert res[1][1]["iterations"] == res[0][1]["iterations"]
+    assert res[1][1]["mg_cycles"] == res[0][1]["mg_cycles"]
+    assert np.array_equal(res[1][0], res[0][0])

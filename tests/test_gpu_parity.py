@@ -118,8 +118,10 @@ def test_apply_fp32_stencil(case):
 
 SHAPES_2D = [(64, 1, 1), (64, 1, 5), (128, 1, 3), (256, 1, 8), (128, 1, 64)]
 SHAPES_3D = [(64, 4, 1), (64, 4, 7), (64, 8, 3), (128, 2, 4), (32, 8, 2)]
-# the streamlined 3D kernel (MFWH_OPT_STEPS_PER_PASS >= 1) takes 64 x 4 and 64 x 8
+# the streamlined 3D kernel (MFWH_OPT_STEPS_PER_PASS 1) takes 64 x 4 and 64 x 8,
+# the two-step one (2) 64 x 16 and 32 x 16
 SHAPES_3D_LEAP = [(64, 4, 1), (64, 4, 5), (64, 8, 3), (64, 8, 200)]
+SHAPES_3D_X2 = [(64, 16, 1), (64, 16, 7), (32, 16, 3), (64, 16, 200)]
 
 
 @pytest.mark.parametrize("shape", SHAPES_2D, ids=lambda s: f"bx{s[0]}-c{s[2]}")
@@ -139,8 +141,9 @@ def test_launch_shapes_2d(shape, order):
     assert rel(out, ref) < tol64(pl)
 
 
-@pytest.mark.parametrize("kernel", [(0, s) for s in SHAPES_3D] + [(1, s) for s in SHAPES_3D_LEAP],
-                         ids=lambda k: f"{'leap' if k[0] else 'general'}-bx{k[1][0]}-by{k[1][1]}-c{k[1][2]}")
+@pytest.mark.parametrize("kernel", [(0, s) for s in SHAPES_3D] + [(1, s) for s in SHAPES_3D_LEAP] +
+                         [(2, s) for s in SHAPES_3D_X2],
+                         ids=lambda k: f"{['general', 'leap', 'x2'][k[0]]}-bx{k[1][0]}-by{k[1][1]}-c{k[1][2]}")
 @pytest.mark.parametrize("forcing", [True, False], ids=["forced", "free"])
 @pytest.mark.parametrize("order", [2, 4])
 def test_launch_shapes_3d(kernel, forcing, order):
