@@ -211,6 +211,8 @@ __global__ void __launch_bounds__(BX * BY) k_leap3d_x2(LeapArgs<T> a) {
   const bool inxy = ex >= 0 && ex < nxi && ey >= 0 && ey < nyi;
   const bool mid = inxy && lx >= R && lx < BX - R && ly >= R && ly < BY - R;
   const bool own = inxy && lx >= 2 * R && lx < BX - 2 * R && ly >= 2 * R && ly < BY - 2 * R;
+  const bool qrow = ly >= 2 * R && ly < BY - 2 * R;
+  static_assert(BX == 64 || BX == 32, "a wave covers one or two whole rows");
   const long long col = (long long)iy * py + ix;
   const int qx = min(max(ex, x0), min(x0 + OX, nxi) - 1);
   const int qy = min(max(ey, y0), min(y0 + OY, nyi) - 1);
@@ -261,9 +263,14 @@ __global__ void __launch_bounds__(BX * BY) k_leap3d_x2(LeapArgs<T> a) {
         }
       }
     }
-    const long long i2 = (long long)max(z, z0) * pz + qcol;
+    // accumulators: only waves holding owned rows load them (a wave is one
+    // or two whole rows ly, so the condition is uniform per wave and the
+    // halo-row waves issue no duplicate requests)
+    if (qrow) {
+      const long long i2 = (long long)max(z, z0) * pz + qcol;
 #pragma unroll
-    for (int q = 0; q < QM; ++q) o.q[q] = a.q[a.qm[q] * fs + i2];
+      for (int q = 0; q < QM; ++q) o.q[q] = a.q[a.qm[q] * fs + i2];
+    }
   };
   auto process = [&](int z, const Plane2<T, QM>& o, int buf) {
 #pragma unroll
