@@ -476,6 +476,26 @@ constexpr int kPre = 2, kPost = 2;   // Jacobi sweeps before / after the coarse 
 
 double jacobi_weight(int order) { return order == 4 ? 10.0 / 13.0 : 0.8; }
 
+// Degree-2 Chebyshev smoother on [b/4, b] for the spectrum of diag(M)^-1 M
+// (real and positive: M = I + C K with K symmetric positive semidefinite and
+// C = diag(c^2) > 0).  b is the Gershgorin bound 1 + (off-diagonal row sum /
+// diagonal) of the stencil: 2 for order 2; 1 + 34/29 for order 4, whose
+// first and last rows have the ghost folded into a diagonal of 29/12.
+// Recurrence (Chebyshev acceleration): theta = (a+b)/2, delta = (b-a)/2,
+// sigma = theta/delta, rho0 = 1/sigma, rho1 = 1/(2 sigma - rho0); sweep 1:
+// Jacobi with weight 1/theta; sweep 2: x2 = x1 + rho1 rho0 (x1 - x0) +
+// (2 rho1 / delta) diag^-1 (b - M x1).
+struct Cheb {
+  double w1, c1, c2;
+};
+Cheb cheb_coefs(int order) {
+  const double bmax = order == 4 ? 1.0 + 34.0 / 29.0 : 2.0;
+  const double amin = bmax / 4.0;
+  const double theta = 0.5 * (amin + bmax), delta = 0.5 * (bmax - amin);
+  const double sigma = theta / delta, rho0 = 1.0 / sigma, rho1 = 1.0 / (2.0 * sigma - rho0);
+  return Cheb{1.0 / theta, rho1 * rho0, 2.0 * rho1 / delta};
+}
+
 // One V-cycle on level l for M_l x = b (x updated in place; level 0 uses the
 // caller's x and b, coarser levels the workspace).
 int coarse_sweeps(const MgLevel& L) {
@@ -499,7 +519,10 @@ int vcycle(Problem& pr, int l, double* x, const double* b) {
       mc.t[k] = W.mt[k];
       mc.r[k] = W.mr[k];
       mc.order[k] = k == 0 ? pr.grid->order : 2;
-      mc.w[k] = jacobi_weight(mc.order[k]);
+      const Cheb ch = cheb_coefs(mc.order[k]);
+      mc.w[k] = k == W.nlev - 1 ? jacobi_weight(mc.order[k]) : ch.w1;
+      mc.c1[k] = ch.c1;
+      mc.c2[k] = ch.c2;
     }
     mc.lc = l;
     mc.nlev = W.nlev;
@@ -517,17 +540,18 @@ int vcycle(Problem& pr, int l, double* x, const double* b) {
     }
     return MFWH_OK;
   }
+  const Cheb ch = cheb_coefs(order);
   for (int k = 0; k < kPre; k += 2) {
-    HIPCHK(launch_mg_jacobi(L, order, x, b, t, w, pr.s));
-    HIPCHK(launch_mg_jacobi(L, order, t, b, x, w, pr.s));
+    HIPCHK(launch_mg_jacobi(L, order, x, b, t, ch.w1, pr.s));
+    HIPCHK(launch_mg_cheb2(L, order, t, b, x, ch.c1, ch.c2, pr.s));
   }
   HIPCHK(launch_mg_resid(L, order, x, b, W.mr[l], nullptr, 0, nullptr, pr.s));
   HIPCHK(launch_mg_restrict(L, W.mr[l], W.lev[l + 1], W.mb[l + 1], W.mx[l + 1], pr.s));
   CHK(vcycle(pr, l + 1, W.mx[l + 1], W.mb[l + 1]));
   HIPCHK(launch_mg_prolong(W.lev[l + 1], W.mx[l + 1], L, x, pr.s));
   for (int k = 0; k < kPost; k += 2) {
-    HIPCHK(launch_mg_jacobi(L, order, x, b, t, w, pr.s));
-    HIPCHK(launch_mg_jacobi(L, order, t, b, x, w, pr.s));
+    HIPCHK(launch_mg_jacobi(L, order, x, b, t, ch.w1, pr.s));
+    HIPCHK(launch_mg_cheb2(L, order, t, b, x, ch.c1, ch.c2, pr.s));
   }
   return MFWH_OK;
 }

@@ -177,7 +177,9 @@ struct MgCoarse {
   double* b[kMgMaxLev];
   double* t[kMgMaxLev];
   double* r[kMgMaxLev];
-  double w[kMgMaxLev];      // Jacobi weight per level
+  double w[kMgMaxLev];      // Jacobi weight per level (first Chebyshev sweep: 1/theta)
+  double c1[kMgMaxLev];     // second Chebyshev sweep coefficients per level
+  double c2[kMgMaxLev];
   int order[kMgMaxLev];     // 2 or 4 per level
   int lc, nlev, pre, post, coarse_sweeps;
 };
@@ -189,6 +191,10 @@ hipError_t launch_mg_jacobi(const MgLevel& L, int order, const double* x, const 
 // out2[0] = |r|^2, out2[1] = |b|^2 (device)
 hipError_t launch_mg_resid(const MgLevel& L, int order, const double* x, const double* b,
                            double* r, double* partial, int nred, double* out2, hipStream_t s);
+// second sweep of the degree-2 Chebyshev smoother:
+//   x <- t + c1 (t - x) + c2 (b - M t) / diag(M)
+hipError_t launch_mg_cheb2(const MgLevel& L, int order, const double* t, const double* b,
+                           double* x, double c1, double c2, hipStream_t s);
 hipError_t launch_mg_restrict(const MgLevel& F, const double* rf, const MgLevel& C, double* bc,
                               double* xc, hipStream_t s);
 hipError_t launch_mg_prolong(const MgLevel& C, const double* ec, const MgLevel& F, double* xf,

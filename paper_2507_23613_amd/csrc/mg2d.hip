@@ -9,10 +9,12 @@
 // Multigrid: vertex-centred coarsening of the interior grid, (2n+1) -> n
 // points per axis, while both counts are odd and >= 3; coarse operators are
 // rediscretised with the order-2 stencil at spacing 2^l h and c^2 injected;
-// damped Jacobi smoothing (weight 4/5 for order 2, 10/13 for order 4: the
-// minimisers of the high-frequency amplification of each stencil), full
-// weighting restriction, bilinear prolongation, V(2,2) cycles, a fixed
-// number of Jacobi sweeps on the coarsest level.  Each kernel is one thread
+// degree-2 Chebyshev smoothing (two sweeps per application, on
+// [lambda_max/4, lambda_max] of diag(M)^-1 M, lambda_max the Gershgorin
+// bound: the upper three quarters of the spectrum, the modes the coarse grid
+// cannot represent), full weighting restriction, bilinear prolongation,
+// V(2,2) cycles, a fixed number of damped Jacobi sweeps on the coarsest
+// level.  Each kernel is one thread
 // per point over the padded internal layout; all of them are HBM-bound
 // streams (the stencil neighbours come from L1/L2).
 #include <hip/hip_runtime.h>
@@ -99,6 +101,25 @@ __global__ void __launch_bounds__(kNT) k_mg_jacobi(MgLevel L, const double* __re
     const double c2 = L.c2 ? L.c2[idx] : 1.0;
     const double mx = xc - c2 * klap<R>(x, L, i, j, xc);
     y[idx] = xc + w * (b[idx] - mx) / mdiag<R>(L, i, j, c2);
+  }
+}
+
+// second sweep of the degree-2 Chebyshev smoother (the first is a Jacobi
+// sweep x -> t with weight 1/theta):  x <- t + c1 (t - x) + c2 (b - M t)/diag(M)
+// (x is read and written by the same thread only; t carries the stencil)
+template <int R>
+__global__ void __launch_bounds__(kNT) k_mg_cheb2(MgLevel L, const double* __restrict__ t,
+                                                  const double* __restrict__ b, double* x,
+                                                  double c1, double c2) {
+  const long long n = (long long)L.nx * L.ny;
+  for (long long p = (long long)blockIdx.x * kNT + threadIdx.x; p < n;
+       p += (long long)gridDim.x * kNT) {
+    const int j = (int)(p / L.nx), i = (int)(p - (long long)j * L.nx);
+    const long long idx = (long long)j * L.py + i;
+    const double tc = t[idx];
+    const double cc = L.c2 ? L.c2[idx] : 1.0;
+    const double mt = tc - cc * klap<R>(t, L, i, j, tc);
+    x[idx] = tc + c1 * (tc - x[idx]) + c2 * (b[idx] - mt) / mdiag<R>(L, i, j, cc);
   }
 }
 
@@ -275,6 +296,33 @@ __device__ void co_jacobi(const MgLevel& L, const double* x, const double* b, do
 }
 
 template <int R>
+__device__ void co_cheb2(const MgLevel& L, const double* t, const double* b, double* x,
+                         double c1, double c2) {
+  const int n = L.nx * L.ny;
+  for (int p = threadIdx.x; p < n; p += kCT) {
+    const int j = p / L.nx, i = p - j * L.nx;
+    const long long idx = (long long)j * L.py + i;
+    const double tc = t[idx];
+    const double cc = L.c2 ? L.c2[idx] : 1.0;
+    const double mt = tc - cc * klap<R>(t, L, i, j, tc);
+    x[idx] = tc + c1 * (tc - x[idx]) + c2 * (b[idx] - mt) / mdiag<R>(L, i, j, cc);
+  }
+  __syncthreads();
+}
+
+// one application of the degree-2 Chebyshev smoother on level l (x -> t -> x)
+__device__ void co_smooth(const MgCoarse& a, int l) {
+  const MgLevel& L = a.lev[l];
+  if (a.order[l] == 4) {
+    co_jacobi<2>(L, a.x[l], a.b[l], a.t[l], a.w[l]);
+    co_cheb2<2>(L, a.t[l], a.b[l], a.x[l], a.c1[l], a.c2[l]);
+  } else {
+    co_jacobi<1>(L, a.x[l], a.b[l], a.t[l], a.w[l]);
+    co_cheb2<1>(L, a.t[l], a.b[l], a.x[l], a.c1[l], a.c2[l]);
+  }
+}
+
+template <int R>
 __device__ void co_resid(const MgLevel& L, const double* x, const double* b, double* r) {
   const int n = L.nx * L.ny;
   for (int p = threadIdx.x; p < n; p += kCT) {
@@ -292,15 +340,7 @@ __global__ void __launch_bounds__(kCT) k_mg_coarse(MgCoarse a) {
   for (int l = a.lc; l < a.nlev - 1; ++l) {
     const MgLevel& L = a.lev[l];
     const MgLevel& C = a.lev[l + 1];
-    for (int k = 0; k < a.pre; k += 2) {
-      if (a.order[l] == 4) {
-        co_jacobi<2>(L, a.x[l], a.b[l], a.t[l], a.w[l]);
-        co_jacobi<2>(L, a.t[l], a.b[l], a.x[l], a.w[l]);
-      } else {
-        co_jacobi<1>(L, a.x[l], a.b[l], a.t[l], a.w[l]);
-        co_jacobi<1>(L, a.t[l], a.b[l], a.x[l], a.w[l]);
-      }
-    }
+    for (int k = 0; k < a.pre; k += 2) co_smooth(a, l);
     if (a.order[l] == 4) co_resid<2>(L, a.x[l], a.b[l], a.r[l]);
     else co_resid<1>(L, a.x[l], a.b[l], a.r[l]);
     const int nc = C.nx * C.ny;
@@ -352,15 +392,7 @@ __global__ void __launch_bounds__(kCT) k_mg_coarse(MgCoarse a) {
       a.x[l][(long long)j * F.py + i] += v;
     }
     __syncthreads();
-    for (int k = 0; k < a.post; k += 2) {
-      if (a.order[l] == 4) {
-        co_jacobi<2>(F, a.x[l], a.b[l], a.t[l], a.w[l]);
-        co_jacobi<2>(F, a.t[l], a.b[l], a.x[l], a.w[l]);
-      } else {
-        co_jacobi<1>(F, a.x[l], a.b[l], a.t[l], a.w[l]);
-        co_jacobi<1>(F, a.t[l], a.b[l], a.x[l], a.w[l]);
-      }
-    }
+    for (int k = 0; k < a.post; k += 2) co_smooth(a, l);
   }
 }
 
@@ -375,6 +407,14 @@ hipError_t launch_mg_jacobi(const MgLevel& L, int order, const double* x, const 
   const int nb = blocks_for((long long)L.nx * L.ny);
   if (order == 4) k_mg_jacobi<2><<<nb, kNT, 0, s>>>(L, x, b, y, w);
   else k_mg_jacobi<1><<<nb, kNT, 0, s>>>(L, x, b, y, w);
+  return hipGetLastError();
+}
+
+hipError_t launch_mg_cheb2(const MgLevel& L, int order, const double* t, const double* b,
+                           double* x, double c1, double c2, hipStream_t s) {
+  const int nb = blocks_for((long long)L.nx * L.ny);
+  if (order == 4) k_mg_cheb2<2><<<nb, kNT, 0, s>>>(L, t, b, x, c1, c2);
+  else k_mg_cheb2<1><<<nb, kNT, 0, s>>>(L, t, b, x, c1, c2);
   return hipGetLastError();
 }
 
