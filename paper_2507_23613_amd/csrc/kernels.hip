@@ -583,29 +583,40 @@ hipError_t launch_finalize(const Geom& g, int nf, const double* q, const double*
 }
 
 // points of nf caller arrays (full-grid layout) on the faces in `faces`
-// (bit 2a: lower, 2a+1: upper face of axis a) := data (same layout) or 0
+// (bit 2a: lower, 2a+1: upper face of axis a) := data (same layout) or 0.
+// blockIdx.y is the face; a point shared by two selected faces is written
+// twice with the same value.
 __global__ void __launch_bounds__(256) k_boundary_fill(int dim, int n0, int n1, int n2, int nf,
                                                        int faces, const double* __restrict__ data,
                                                        double* v) {
+  const int face = blockIdx.y;
+  if (!((faces >> face) & 1) || face >= 2 * dim) return;
+  const int a = face >> 1;
+  const int n[3] = {n0, n1, n2};
+  const long long st[3] = {1, n0, (long long)n0 * n1};
+  const int b = a == 0 ? 1 : 0, c = a == 2 ? 1 : 2;        // the face's own axes
+  const long long base = (face & 1) ? (long long)(n[a] - 1) * st[a] : 0;
+  const long long fpts = (long long)n[b] * n[c];
   const long long tot = (long long)n0 * n1 * n2;
-  for (long long p = (long long)blockIdx.x * 256 + threadIdx.x; p < tot * nf;
+  for (long long p = (long long)blockIdx.x * 256 + threadIdx.x; p < fpts * nf;
        p += (long long)gridDim.x * 256) {
-    const long long r = p % tot;
-    const int i = (int)(r % n0);
-    const int j = (int)((r / n0) % n1);
-    const int k = (int)(r / ((long long)n0 * n1));
-    const bool bnd = (i == 0 && (faces & 1)) || (i == n0 - 1 && (faces & 2)) ||
-                     (dim >= 2 && ((j == 0 && (faces & 4)) || (j == n1 - 1 && (faces & 8)))) ||
-                     (dim >= 3 && ((k == 0 && (faces & 16)) || (k == n2 - 1 && (faces & 32))));
-    if (bnd) v[p] = data ? data[p] : 0.0;
+    const int m = (int)(p / fpts);
+    const long long r = p - (long long)m * fpts;
+    const int ib = (int)(r % n[b]), ic = (int)(r / n[b]);
+    const long long o = m * tot + base + ib * st[b] + ic * st[c];
+    v[o] = data ? data[o] : 0.0;
   }
 }
 
 hipError_t launch_boundary_fill(int dim, const int* n, int nf, int faces, const double* data,
                                 double* v, hipStream_t s) {
-  const long long tot = (long long)n[0] * n[1] * n[2] * nf;
-  const int nb = (int)std::min<long long>((tot + 255) / 256, 4096);
-  k_boundary_fill<<<nb, 256, 0, s>>>(dim, n[0], n[1], n[2], nf, faces, data, v);
+  long long fmax = 0;
+  for (int a = 0; a < dim; ++a) {
+    const int b = a == 0 ? 1 : 0, c = a == 2 ? 1 : 2;
+    fmax = std::max<long long>(fmax, (long long)n[b] * n[c]);
+  }
+  const int nb = (int)std::max<long long>(1, std::min<long long>((fmax * nf + 255) / 256, 1024));
+  k_boundary_fill<<<dim3(nb, 6), 256, 0, s>>>(dim, n[0], n[1], n[2], nf, faces, data, v);
   return hipGetLastError();
 }
 

@@ -121,7 +121,7 @@ SHAPES_3D = [(64, 4, 1), (64, 4, 7), (64, 8, 3), (128, 2, 4), (32, 8, 2)]
 # the streamlined 3D kernel (MFWH_OPT_STEPS_PER_PASS 1) takes 64 x 4 and 64 x 8,
 # the two-step one (2) 64 x 16 and 32 x 16
 SHAPES_3D_LEAP = [(64, 4, 1), (64, 4, 5), (64, 8, 3), (64, 8, 200)]
-SHAPES_3D_X2 = [(64, 16, 1), (64, 16, 7), (32, 16, 3), (64, 16, 200)]
+SHAPES_3D_X2 = [(64, 16, 1), (64, 16, 7), (32, 16, 3), (64, 16, 200), (64, 16, 16), (32, 16, 16)]
 
 
 @pytest.mark.parametrize("shape", SHAPES_2D, ids=lambda s: f"bx{s[0]}-c{s[2]}")
@@ -162,6 +162,28 @@ def test_launch_shapes_3d(kernel, forcing, order):
         L.mfwh_set_launch_shape(0)
         L.mfwh_set_option(L.MFWH_OPT_STEPS_PER_PASS, 2)
     assert rel(out, ref) < tol64(pl)
+
+
+@pytest.mark.parametrize("shape", [(64, 16, 16), (32, 16, 16)], ids=["bx64", "bx32"])
+@pytest.mark.parametrize("forcing", [True, False], ids=["forced", "free"])
+@pytest.mark.parametrize("order", [2, 4])
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "fp32"])
+def test_x2_3d_whole_and_partial_chunks(shape, forcing, order, precision):
+    """The two-step 3D kernel with 8 filters on 38 interior planes: two whole
+    16-plane chunks and a partial one."""
+    L = _L()
+    w = inputs.small(seed=6, shape=(40, 21, 70), nf=8, order=order, varc=True, lo=4.0, hi=30.0)
+    prob, pl = workload.setup(w)
+    V = rand_v(w["shape"], 8, 9)
+    ref = omf.apply(prob, pl, w["f"], V, forcing)
+    try:
+        L.mfwh_set_option(L.MFWH_OPT_STEPS_PER_PASS, 2)
+        L.mfwh_set_launch_shape(*shape)
+        gp = _gp(w, precision=precision)
+        out = gp.apply(torch.as_tensor(V, device="cuda"), forcing=forcing).cpu().numpy()
+    finally:
+        L.mfwh_set_launch_shape(0)
+    assert rel(out, ref) < (tol64(pl) if precision == 0 else tol32(pl))
 
 
 def test_apply_in_place_and_deterministic():
