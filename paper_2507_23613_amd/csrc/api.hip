@@ -838,6 +838,7 @@ int apply_t(Problem& pr, const double* v, ExtLayout vl, bool forcing, const Out&
       ++nq;
     }
     la.nq = nq;
+    la.nf = nf;
     // unused slots repeat the last used accumulator (the kernels load every
     // slot unconditionally and store only the first nq)
     for (int j = nq; j < MFWH_MAX_NF; ++j) la.qm[j] = nq > 0 ? la.qm[nq - 1] : 0;

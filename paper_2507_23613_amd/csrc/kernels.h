@@ -107,6 +107,7 @@ struct LeapArgs {
   double kk[4][MFWH_MAX_NF];
   int qm[MFWH_MAX_NF];  // slots nq.. repeat slot nq-1 (they are loaded, never stored)
   int nq;               // active accumulators
+  int nf;               // forcing fields (phi1/phi2 slots past nf are 0)
   int force;
   int chunk, nchunk, ntx, nty, nblocks;
 };

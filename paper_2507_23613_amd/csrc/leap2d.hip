@@ -58,19 +58,20 @@ __device__ __forceinline__ int ext_src(int e, int n, T& sg) {
 // register sets, so the wait for a set's loads falls where the set is
 // consumed, one row after it was requested, with the next row's loads
 // already in flight.
-template <typename T, int QM>
+template <typename T, int QM, int FM>
 struct Row1 {
   T w, sw;        // new W^n value of the window and its extension factor
   T h, sh;        // x-halo value (edge lanes) and its factor
-  T p, c, f;      // W^{n-1}, c^2, forcing
+  T p, c;         // W^{n-1}, c^2
+  T fr[FM];       // forcing fields (raw; combined with phi where used)
   double q[QM];
 };
 
-template <typename T, int QM>
+template <typename T, int QM, int FM>
 struct Row2 {
   T w, sw;        // new W^n value of the window and its extension factor
   T p, c;         // W^{n-1} and c^2 at the first step's row
-  T f1, f2;       // forcing of both steps at the first step's row
+  T fr[FM];       // forcing fields at the first step's row (raw)
   double q[QM];   // accumulators at the second step's row
 };
 
@@ -124,22 +125,26 @@ __global__ void __launch_bounds__(BX) k_leap2d(LeapArgs<T> a) {
   const int hcol = hal ? ih : ix;
   const T hsx = hal ? hs : T(0);
   const T* __restrict__ c2p = a.c2 ? a.c2 : a.wp;    // read and ignored when c = 1
-  auto fetch = [&](Row1<T, QM>& o, int y) {
+  constexpr int FM = FORCE ? QM : 1;   // forcing slots (nf <= QM when forced)
+  auto fetch = [&](Row1<T, QM, FM>& o, int y) {
     o.w = ldw(y + R, ix, xs, o.sw);
     o.h = ldw(y, hcol, hsx, o.sh);
     const long long idx = (long long)y * py + ix;
     o.p = a.wp[idx];
     o.c = c2p[idx];
-    o.f = T(0);
     if (FORCE) {
 #pragma unroll
-      for (int m = 0; m < MFWH_MAX_NF; ++m)
-        if (a.phi1[m] != T(0)) o.f += a.phi1[m] * a.f[m * fs + idx];
+      for (int j = 0; j < FM; ++j) o.fr[j] = a.f[min(j, a.nf - 1) * fs + idx];
     }
 #pragma unroll
     for (int j = 0; j < QM; ++j) o.q[j] = a.q[a.qm[j] * fs + idx];
   };
-  auto process = [&](int y, const Row1<T, QM>& o, T* rb) {
+  auto process = [&](int y, const Row1<T, QM, FM>& o, T* rb) {
+    T F = T(0);                           // sum_m phi_m f_m (slots past nf: phi 0)
+    if (FORCE) {
+#pragma unroll
+      for (int j = 0; j < FM; ++j) F += a.phi1[j] * o.fr[j];
+    }
 #pragma unroll
     for (int k = 0; k < 2 * R; ++k) w[k] = w[k + 1];
     w[2 * R] = o.sw * o.w;
@@ -153,7 +158,7 @@ __global__ void __launch_bounds__(BX) k_leap2d(LeapArgs<T> a) {
       for (int k = 1; k <= R; ++k)
         lap += a.wx[k] * (rb[R + tid - k] + rb[R + tid + k]) + a.wy[k] * (w[R - k] + w[R + k]);
       const T c2v = a.c2 ? o.c : T(1);
-      const T wn = a.cA * w[R] + a.cB * o.p + a.cC * (c2v * lap - o.f);
+      const T wn = a.cA * w[R] + a.cB * o.p + a.cC * (c2v * lap - F);
       const long long idx = (long long)y * py + i;
       a.w1[idx] = wn;
       const double wd = (double)wn;
@@ -167,7 +172,7 @@ __global__ void __launch_bounds__(BX) k_leap2d(LeapArgs<T> a) {
   // before row y is computed.  Fetches past the last row re-read the last
   // row (valid, unused), which keeps every fetch unconditional.  PD is even,
   // so a row's LDS buffer parity is that of its set.
-  Row1<T, QM> rs[PD];
+  Row1<T, QM, FM> rs[PD];
 #pragma unroll
   for (int u = 0; u < PD - 1; ++u) fetch(rs[u], min(y0 + u, y1 - 1));
   for (int y = y0; y < y1; y += PD) {
@@ -237,22 +242,16 @@ __global__ void __launch_bounds__(BX) k_leap2d_x2(LeapArgs<T> a) {
   const int x0 = bx * OW;
   const int qcol = min(max(e, x0), min(x0 + OW, nxi) - 1);   // an owned column
   const T* __restrict__ c2p = a.c2 ? a.c2 : a.wp;            // read and ignored when c = 1
-  auto fetch = [&](Row2<T, QM>& o, int r) {
+  constexpr int FM = FORCE ? QM : 1;   // forcing slots (nf <= QM when forced)
+  auto fetch = [&](Row2<T, QM, FM>& o, int r) {
     o.w = ldw(r + 2 * R, o.sw);
     const int ey = min(max(r + R, 0), nyi - 1);   // row of the first step, clamped
     const long long i1 = (long long)ey * py + ix;
     o.p = a.wp[i1];
     o.c = c2p[i1];
-    o.f1 = o.f2 = T(0);
     if (FORCE) {
 #pragma unroll
-      for (int m = 0; m < MFWH_MAX_NF; ++m) {
-        if (a.phi1[m] != T(0) || a.phi2[m] != T(0)) {
-          const T fv = a.f[m * fs + i1];
-          if (a.phi1[m] != T(0)) o.f1 += a.phi1[m] * fv;
-          if (a.phi2[m] != T(0)) o.f2 += a.phi2[m] * fv;
-        }
-      }
+      for (int j = 0; j < FM; ++j) o.fr[j] = a.f[min(j, a.nf - 1) * fs + i1];
     }
     const long long i2 = (long long)max(r, y0) * py + qcol;
 #pragma unroll
@@ -262,7 +261,15 @@ __global__ void __launch_bounds__(BX) k_leap2d_x2(LeapArgs<T> a) {
   // x-neighbour rows are known when the iteration starts (W^n row r + R
   // arrived with the window, W^{n+1} row r was computed R iterations ago),
   // so both go to LDS before the iteration's single barrier.
-  auto process = [&](int r, const Row2<T, QM>& o, T* rb, T* r1b) {
+  auto process = [&](int r, const Row2<T, QM, FM>& o, T* rb, T* r1b) {
+    T f1 = T(0), f2 = T(0);               // forcing of both steps (slots past nf: phi 0)
+    if (FORCE) {
+#pragma unroll
+      for (int j = 0; j < FM; ++j) {
+        f1 += a.phi1[j] * o.fr[j];
+        f2 += a.phi2[j] * o.fr[j];
+      }
+    }
 #pragma unroll
     for (int k = 0; k < 2 * R; ++k) wn[k] = wn[k + 1];
     wn[2 * R] = o.sw * o.w;
@@ -289,13 +296,13 @@ __global__ void __launch_bounds__(BX) k_leap2d_x2(LeapArgs<T> a) {
       for (int k = 1; k <= R; ++k)
         lap += a.wx[k] * (rb[l - k] + rb[l + k]) + a.wy[k] * (wn[R - k] + wn[R + k]);
       const T c2v = a.c2 ? o.c : T(1);
-      v = a.cA * wn[R] + a.cB * o.p + a.cC * (c2v * lap - o.f1);
+      v = a.cA * wn[R] + a.cB * o.p + a.cC * (c2v * lap - f1);
     }
     if (R == 2 && ey == nyi + 1) v = -w1[2 * R - 2];   // ghost row: reflects row nyi-1
     w1[2 * R] = v;
     if (R == 2 && ey == 0) w1[2 * R - 2] = -v;         // ghost row -2 reflects row 0
     cw[R] = a.c2 ? o.c : T(1);
-    fw[R] = o.f2;
+    fw[R] = f2;
 
     // second step: W^{n+2} on row r
     if (r >= y0 && own) {
@@ -319,7 +326,7 @@ __global__ void __launch_bounds__(BX) k_leap2d_x2(LeapArgs<T> a) {
   // row (valid, unused), which keeps every fetch unconditional.  PD is even,
   // so a row's LDS buffer parity is that of its set.
   const int r0 = y0 - 2 * R;
-  Row2<T, QM> rs[PD];
+  Row2<T, QM, FM> rs[PD];
 #pragma unroll
   for (int u = 0; u < PD - 1; ++u) fetch(rs[u], min(r0 + u, y1 - 1));
   if constexpr (CH > 0) {
@@ -520,8 +527,9 @@ __global__ void __launch_bounds__(BX) k_leap2d_xk(LeapArgs<T> a) {
 
 template <typename T, int R, int BX, int PD>
 hipError_t launch_pd(LeapArgs<T>& a, int steps, int grid, hipStream_t s) {
-  const bool q4 = a.nq <= 4;
   const bool fo = a.force != 0;
+  // QM bounds the accumulator slots and, when forced, the forcing fields
+  const bool q4 = a.nq <= 4 && (!fo || a.nf <= 4);
   if (steps == 2) {
     // forcing-free passes (every matvec) with a chunk of 4, 8 or 16 rows run
     // the fully unrolled march

@@ -37,11 +37,12 @@ __device__ __forceinline__ int ext_src3(int e, int n, T& sg) {
   return in ? e : (e == n + 1 ? n - 1 : 0);
 }
 
-template <typename T, int QM, int HS>
+template <typename T, int QM, int HS, int FM>
 struct Plane {
   T w, sw;          // new z-window value and its factor
   T h[HS];          // raw halo values (factors fixed per slot)
-  T p, c, f;        // W^{n-1}, c^2, forcing
+  T p, c;           // W^{n-1}, c^2
+  T fr[FM];         // forcing fields (raw; combined with phi where used)
   double q[QM];
 };
 
@@ -110,7 +111,8 @@ __global__ void __launch_bounds__(BX * BY) k_leap3d(LeapArgs<T> a) {
     w[k + 1] = (sxy * sz) * wc[(long long)iz * pz + col];
   }
 
-  auto fetch = [&](Plane<T, QM, HS>& o, int z) {
+  constexpr int FM = FORCE ? QM : 1;   // forcing slots (nf <= QM when forced)
+  auto fetch = [&](Plane<T, QM, HS, FM>& o, int z) {
     T sz;
     const int iz = ext_src3(z + R, nzi, sz);
     o.sw = sxy * sz;
@@ -121,16 +123,14 @@ __global__ void __launch_bounds__(BX * BY) k_leap3d(LeapArgs<T> a) {
     const long long idx = zo + col;
     o.p = a.wp[idx];
     o.c = c2p[idx];
-    o.f = T(0);
     if (FORCE) {
 #pragma unroll
-      for (int m = 0; m < MFWH_MAX_NF; ++m)
-        if (a.phi1[m] != T(0)) o.f += a.phi1[m] * a.f[m * fs + idx];
+      for (int j = 0; j < FM; ++j) o.fr[j] = a.f[min(j, a.nf - 1) * fs + idx];
     }
 #pragma unroll
     for (int q = 0; q < QM; ++q) o.q[q] = a.q[a.qm[q] * fs + idx];
   };
-  auto process = [&](int z, const Plane<T, QM, HS>& o, int buf) {
+  auto process = [&](int z, const Plane<T, QM, HS, FM>& o, int buf) {
 #pragma unroll
     for (int k = 0; k < 2 * R; ++k) w[k] = w[k + 1];
     w[2 * R] = o.sw * o.w;
@@ -140,6 +140,11 @@ __global__ void __launch_bounds__(BX * BY) k_leap3d(LeapArgs<T> a) {
     for (int k = 0; k < HS; ++k)
       if (tid + k * NT < NH) tb[hr[k]][hc[k]] = hsg[k] * o.h[k];
     __syncthreads();
+    T F = T(0);                           // sum_m phi_m f_m (slots past nf: phi 0)
+    if (FORCE) {
+#pragma unroll
+      for (int j = 0; j < FM; ++j) F += a.phi1[j] * o.fr[j];
+    }
     if (act) {
       T lap = (a.wx[0] + a.wy[0] + a.wz[0]) * w[R];
 #pragma unroll
@@ -148,7 +153,7 @@ __global__ void __launch_bounds__(BX * BY) k_leap3d(LeapArgs<T> a) {
                a.wy[k] * (tb[R + ly - k][R + lx] + tb[R + ly + k][R + lx]) +
                a.wz[k] * (w[R - k] + w[R + k]);
       const T c2v = a.c2 ? o.c : T(1);
-      const T wn = a.cA * w[R] + a.cB * o.p + a.cC * (c2v * lap - o.f);
+      const T wn = a.cA * w[R] + a.cB * o.p + a.cC * (c2v * lap - F);
       const long long idx = (long long)z * pz + (long long)j * py + i;
       a.w1[idx] = wn;
       const double wd = (double)wn;
@@ -159,7 +164,7 @@ __global__ void __launch_bounds__(BX * BY) k_leap3d(LeapArgs<T> a) {
   };
 
   // fetches past the last plane re-read the last plane (valid, unused)
-  Plane<T, QM, HS> ra, rb;
+  Plane<T, QM, HS, FM> ra, rb;
   fetch(ra, z0);
   for (int z = z0; z < z1; z += 2) {
     fetch(rb, min(z + 1, z1 - 1));
@@ -181,11 +186,11 @@ __global__ void __launch_bounds__(BX * BY) k_leap3d(LeapArgs<T> a) {
 // steps.  Both x/y-neighbour planes (W^n on plane z+R for the first step,
 // W^{n+1} on plane z for the second) go to LDS before the iteration's one
 // barrier.
-template <typename T, int QM>
+template <typename T, int QM, int FM>
 struct Plane2 {
   T w, sw;          // new W^n value (plane z + 2R) and its factor
   T p, c;           // W^{n-1}, c^2 on plane z + R
-  T f1, f2;         // forcing of both steps on plane z + R
+  T fr[FM];         // forcing fields on plane z + R (raw)
   double q[QM];     // accumulators on plane z
 };
 
@@ -246,22 +251,16 @@ __global__ void __launch_bounds__(BX * BY) k_leap3d_x2(LeapArgs<T> a) {
     fw[k] = T(0);
   }
 
-  auto fetch = [&](Plane2<T, QM>& o, int z) {
+  constexpr int FM = FORCE ? QM : 1;   // forcing slots (nf <= QM when forced)
+  auto fetch = [&](Plane2<T, QM, FM>& o, int z) {
     o.w = ldw(z + 2 * R, o.sw);
     const int e1 = min(max(z + R, 0), nzi - 1);
     const long long i1 = (long long)e1 * pz + col;
     o.p = a.wp[i1];
     o.c = c2p[i1];
-    o.f1 = o.f2 = T(0);
     if (FORCE) {
 #pragma unroll
-      for (int m = 0; m < MFWH_MAX_NF; ++m) {
-        if (a.phi1[m] != T(0) || a.phi2[m] != T(0)) {
-          const T fv = a.f[m * fs + i1];
-          if (a.phi1[m] != T(0)) o.f1 += a.phi1[m] * fv;
-          if (a.phi2[m] != T(0)) o.f2 += a.phi2[m] * fv;
-        }
-      }
+      for (int j = 0; j < FM; ++j) o.fr[j] = a.f[min(j, a.nf - 1) * fs + i1];
     }
     // accumulators: only waves holding owned rows load them (a wave is one
     // or two whole rows ly, so the condition is uniform per wave and the
@@ -272,7 +271,7 @@ __global__ void __launch_bounds__(BX * BY) k_leap3d_x2(LeapArgs<T> a) {
       for (int q = 0; q < QM; ++q) o.q[q] = a.q[a.qm[q] * fs + i2];
     }
   };
-  auto process = [&](int z, const Plane2<T, QM>& o, int buf) {
+  auto process = [&](int z, const Plane2<T, QM, FM>& o, int buf) {
 #pragma unroll
     for (int k = 0; k < 2 * R; ++k) wn[k] = wn[k + 1];
     wn[2 * R] = o.sw * o.w;
@@ -295,6 +294,14 @@ __global__ void __launch_bounds__(BX * BY) k_leap3d_x2(LeapArgs<T> a) {
       if (ey == nyi - 1 && ly + 2 < BY) p1[buf][ly + 2][lx] = -w1[R];
     }
     __syncthreads();
+    T f1 = T(0), f2 = T(0);               // forcing of both steps (slots past nf: phi 0)
+    if (FORCE) {
+#pragma unroll
+      for (int j = 0; j < FM; ++j) {
+        f1 += a.phi1[j] * o.fr[j];
+        f2 += a.phi2[j] * o.fr[j];
+      }
+    }
     // first step: W^{n+1} on plane ez = z + R
     const int ez = z + R;
     T v = T(0);
@@ -306,13 +313,13 @@ __global__ void __launch_bounds__(BX * BY) k_leap3d_x2(LeapArgs<T> a) {
                a.wy[k] * (pn[buf][ly - k][lx] + pn[buf][ly + k][lx]) +
                a.wz[k] * (wn[R - k] + wn[R + k]);
       const T c2v = a.c2 ? o.c : T(1);
-      v = a.cA * wn[R] + a.cB * o.p + a.cC * (c2v * lap - o.f1);
+      v = a.cA * wn[R] + a.cB * o.p + a.cC * (c2v * lap - f1);
     }
     if (R == 2 && ez == nzi + 1) v = -w1[2 * R - 2];   // ghost plane: reflects plane nzi-1
     w1[2 * R] = v;
     if (R == 2 && ez == 0) w1[2 * R - 2] = -v;         // ghost plane -2 reflects plane 0
     cw[R] = a.c2 ? o.c : T(1);
-    fw[R] = o.f2;
+    fw[R] = f2;
     // second step: W^{n+2} on plane z
     if (z >= z0 && own) {
       T lap = (a.wx[0] + a.wy[0] + a.wz[0]) * w1[R];
@@ -333,7 +340,7 @@ __global__ void __launch_bounds__(BX * BY) k_leap3d_x2(LeapArgs<T> a) {
   };
 
   // fetches past the last plane re-read the last plane (valid, unused)
-  Plane2<T, QM> ra, rb;
+  Plane2<T, QM, FM> ra, rb;
   const int r0 = z0 - 2 * R;
   fetch(ra, r0);
   for (int z = r0; z < z1; z += 2) {
@@ -354,7 +361,8 @@ hipError_t launch_x2_3(LeapArgs<T>& a, hipStream_t s) {
   a.nblocks = a.ntx * a.nty * a.nchunk;
   const int grid = pad8(a.nblocks);
   const dim3 blk(BX, BY);
-  const bool q4 = a.nq <= 4;
+  // QM bounds the accumulator slots and, when forced, the forcing fields
+  const bool q4 = a.nq <= 4 && (!a.force || a.nf <= 4);
   if (a.force) {
     if (q4) k_leap3d_x2<T, R, BX, BY, 4, true><<<grid, blk, 0, s>>>(a);
     else k_leap3d_x2<T, R, BX, BY, 8, true><<<grid, blk, 0, s>>>(a);
@@ -374,7 +382,8 @@ hipError_t launch_shape3(LeapArgs<T>& a, hipStream_t s) {
   a.nblocks = a.ntx * a.nty * a.nchunk;
   const int grid = pad8(a.nblocks);
   const dim3 blk(BX, BY);
-  const bool q4 = a.nq <= 4;
+  // QM bounds the accumulator slots and, when forced, the forcing fields
+  const bool q4 = a.nq <= 4 && (!a.force || a.nf <= 4);
   if (a.force) {
     if (q4) k_leap3d<T, R, BX, BY, 4, true><<<grid, blk, 0, s>>>(a);
     else k_leap3d<T, R, BX, BY, 8, true><<<grid, blk, 0, s>>>(a);
