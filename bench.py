@@ -27,6 +27,7 @@ Extra fields:
     python bench.py --mode warmstart # learned warm start: data, training, evaluation
     python bench.py --mode implicit  # implicit scheme + multigrid: O(N) grid study
     python bench.py --mode bc        # Dirichlet data / Neumann faces at 1025^2
+    python bench.py --mode fpi       # 100 fixed-point iterations of the 1D workload
     python bench.py --mode apply --applies 3   # a few forcing-free float64
                                      # applications of the same workload (for
                                      # rocprofv3: the step kernel as the solver runs it)
@@ -50,8 +51,8 @@ HBM_PEAK_GBS = 8000.0
 # profiles/k_leap2d_xk3_fp64_2d-n1025-nf4.md).  Keyed by (steps per pass, bx,
 # chunk) and valid only for the kernel source it was measured on: reported
 # as null for another configuration or once leap2d.hip changes.
-TRAFFIC = {"leap2d_sha256_16": "2c7a8e7918e199b5",
-           "bytes": {(3, 128, 8): 33643.4 * 1024 * 2.0 + 48754.8 * 1024 * 1.0}}
+TRAFFIC = {"leap2d_sha256_16": "67e594947806f8ff",
+           "bytes": {(3, 128, 8): 33483.2 * 1024 * 2.0 + 48794.5 * 1024 * 1.0}}
 
 
 def measured_traffic(cfg):
@@ -250,6 +251,32 @@ def implicit_bench(args):
                       "rows": rows}), flush=True)
 
 
+def fpi_bench(args):
+    """The 1D workload (N = 201, order 2, omega = (5.3, 11.7), traditional
+    filter, N_p = 1): 100 plain fixed-point iterations (Algorithm 1) from
+    V = 0.  Reports wall time, time per iteration, the residual history's
+    end and its contraction over the last 20 iterations (the asymptotic
+    convergence rate of Theorem 1 is 0.839 for this plan)."""
+    import torch
+    from paper_2507_23613_amd import inputs
+    from paper_2507_23613_amd.problem import GpuProblem
+    w = inputs.config1(0)
+    gp = GpuProblem(w, restart=0)
+    gp.fixed_point(max_iter=2)                      # warm-up (graph recording)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, info = gp.fixed_point(max_iter=100)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    h = np.asarray(info["history"])
+    row = {"mode": "fpi", "workload": w["name"], "nt": gp.nt, "iterations": info["iterations"],
+           "s": round(el, 4), "ms_per_iteration": round(1e3 * el / info["iterations"], 3),
+           "r1": float(h[0]), "r100": float(h[-1]),
+           "contraction_last20": float((h[-1] / h[-21]) ** (1.0 / 20)),
+           "point_steps_x_nf_per_s": gp.interior_points * gp.nt * 2 * info["iterations"] / el}
+    print(json.dumps(row), flush=True)
+
+
 def bc_bench(args):
     """Other boundary conditions at the 2D workload's size (1025^2, order 4,
     4 frequencies, float64, forced applications): homogeneous Dirichlet (the
@@ -306,7 +333,8 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--mode", default="solve",
-                    choices=["solve", "copy", "apply", "batch", "warmstart", "implicit", "bc"])
+                    choices=["solve", "copy", "apply", "batch", "warmstart", "implicit", "bc",
+                             "fpi"])
     ap.add_argument("--train", type=int, default=2000)
     ap.add_argument("--test", type=int, default=200)
     ap.add_argument("--epochs", type=int, default=20)
@@ -350,6 +378,9 @@ def main():
         return
     if args.mode == "bc":
         bc_bench(args)
+        return
+    if args.mode == "fpi":
+        fpi_bench(args)
         return
 
     if args.mode == "apply" and args.config == 3:

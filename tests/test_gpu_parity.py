@@ -209,6 +209,30 @@ def test_fixed_point_matches_oracle_config1():
     assert np.allclose(info["history"], rref, rtol=1e-10)
 
 
+def test_fixed_point_config1_100_iterations():
+    """The 1D workload's 100 plain fixed-point iterations: the history follows
+    the oracle's, the iteration contracts at the asymptotic convergence rate
+    max |mu_d(lambda~)| over the discrete spectrum (Theorem 1), and the
+    iterate approaches the direct Helmholtz solution at that rate."""
+    w = inputs.config1(0)
+    gp = _gp(w)
+    prob, pl = workload.setup(w)
+    v, info = gp.fixed_point(max_iter=100)
+    Vref, rref = omf.fixed_point(prob, pl, w["f"], 100)
+    h = np.asarray(info["history"])
+    assert info["iterations"] == 100
+    assert np.allclose(h, rref, rtol=1e-9)
+    assert rel(v.cpu().numpy(), Vref) < 1e-11
+    lam = np.sqrt(-fd.laplacian_eigenvalues(w["shape"], prob.h, 2).ravel())
+    acr = pl.acr(lam)
+    rate = (h[-1] / h[-21]) ** (1.0 / 20)
+    print(f"config1 FPI: ACR {acr:.4f}, measured contraction {rate:.4f}, r100 {h[-1]:.2e}")
+    assert abs(rate - acr) < 0.02 * acr
+    U = np.stack([fd.helmholtz_direct(w["f"][m], w["omega"][m], prob.h, 2) for m in range(2)])
+    e = rel(v.cpu().numpy(), U)
+    assert e < 10 * acr ** 100          # from V = 0: relative error ~ ACR^k
+
+
 GMRES_CASES = [
     dict(seed=5, shape=(41,), nf=2, order=2),
     dict(seed=9, shape=(41,), nf=3, order=4, varc=True),
