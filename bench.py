@@ -16,6 +16,10 @@ Extra fields:
   roofline       the fused step kernel: algorithmic bytes per launch / the
                  launch duration measured with HIP events on its stream during
                  the timed steps, against the 8 TB/s HBM peak
+  roofline_3d    the same measurement for the two-step kernel on the 3D 256^3
+                 workload (float32 stencil, 8 filters; its 1.8 GB working set
+                 streams from HBM, while the 2D workload's fits the 256 MB
+                 Infinity Cache): two forcing-free applications
   cpu_baseline   the float64 oracle (NumPy, one core) stepping the same
                  workload for a bounded number of time steps
   time_to_1e8    wall time of one float64 GMRES solve and of one float32-
@@ -251,6 +255,61 @@ def implicit_bench(args):
                       "rows": rows}), flush=True)
 
 
+# HBM traffic per launch of the two-step 3D kernel on the 256^3 workload
+# (its 8-accumulator launches, 1991 of 2021 per application; FETCH_SIZE x 2.0 +
+# WRITE_SIZE x 1.0, profiles/k_leap3d_x2_fp32_3d-n256-nf8.md), valid only for
+# the leap3d.hip source it was measured on.
+TRAFFIC3 = {"leap3d_sha256_16": "399a400e7a68774e",
+            "bytes": 766126.9 * 1024 * 2.0 + 1182735.6 * 1024 * 1.0}
+
+
+def roofline_3d():
+    """The 3D 256^3 workload (float32 stencil, variable c, 8 filters): two
+    forcing-free applications with the two-step kernel; its algorithmic bytes
+    per launch over the event-timed launch duration against the 8 TB/s peak
+    (this is the workload whose kernel streams from HBM: 1.8 GB working set)."""
+    import hashlib
+    import torch
+    from paper_2507_23613_amd import _lib as L
+    from paper_2507_23613_amd import inputs
+    from paper_2507_23613_amd.problem import GpuProblem
+    w = inputs.config3(0)
+    L.mfwh_set_option(L.MFWH_OPT_STEPS_PER_PASS, 2)
+    L.mfwh_set_launch_shape(0)
+    gp = GpuProblem(w, precision=L.MFWH_FP32_STENCIL, restart=0)
+    nf = len(w["omega"])
+    v = torch.randn((nf,) + tuple(w["shape"]), dtype=torch.float64, device="cuda")
+    out = torch.empty_like(v)
+    L.mfwh_apply(gp.grid, gp.time, None, v, out, 0, gp.ws)          # warm-up
+    torch.cuda.synchronize()
+    L.mfwh_stats_read()
+    L.mfwh_stats_enable(1, 1)
+    t0 = time.perf_counter()
+    L.mfwh_apply(gp.grid, gp.time, None, v, out, 0, gp.ws)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    L.mfwh_stats_enable(0, 8)
+    launches, kms, kbytes = L.mfwh_stats_read()
+    achieved = kbytes / (kms * 1e6)
+    src = os.path.join(ROOT, "paper_2507_23613_amd", "csrc", "leap3d.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    traffic = round(TRAFFIC3["bytes"]) if sha == TRAFFIC3["leap3d_sha256_16"] else None
+    ps = gp.interior_points * gp.nt
+    return {"workload": w["name"] + "-fp32-stencil", "nt": gp.nt,
+            "kernel": "k_leap3d_x2<float, order 2, 64x16, default chunk>: 2 fused leapfrog steps + "
+                      "8 filter updates per launch (forcing-free)",
+            "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "avg_launch_us": round(1e3 * kms / max(1, launches), 2),
+            "bytes_per_launch": round(kbytes / max(1, launches)), "timed_launches": launches,
+            "ms_per_apply": round(1e3 * el, 1),
+            "point_steps_x_nf_per_s": ps * nf / el,
+            "one_step_equivalent": {"bytes_per_point_step": 144,
+                                    "achieved": round(144 * ps / (kms / 1e3) / 1e9, 1),
+                                    "frac": round(144 * ps / (kms / 1e3) / 1e9 / HBM_PEAK_GBS,
+                                                  4)}}
+
+
 def fpi_bench(args):
     """The 1D workload (N = 201, order 2, omega = (5.3, 11.7), traditional
     filter, N_p = 1): 100 plain fixed-point iterations (Algorithm 1) from
@@ -346,6 +405,7 @@ def main():
     ap.add_argument("--applies", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-fp32", action="store_true", help="skip the float32-stencil solve")
+    ap.add_argument("--no-3d", action="store_true", help="skip the 3D 256^3 kernel rate")
     ap.add_argument("--n", type=int, default=1025, help="grid points per axis")
     ap.add_argument("--config", type=int, default=2, choices=[2, 3],
                     help="apply mode: the 2D 1025^2 workload (float64) or the 3D 256^3 "
@@ -481,6 +541,11 @@ def main():
         t2e["fp32_outer"] = info32["outer"]
         log(f"fp32: {t2e}")
         del gp32
+    roof3 = None
+    if not args.no_3d:
+        log("3D 256^3 workload: two-step kernel rate (two applications)")
+        roof3 = roofline_3d()
+        log(f"3D: {roof3}")
     if not args.no_cpu:
         log("oracle baseline on the host (about 15 s)")
     cpu = None if args.no_cpu else cpu_baseline(w)
@@ -496,6 +561,7 @@ def main():
                    "launch_shape": list(shape) if shape else None,
                    "omega": np.round(w["omega"], 4).tolist()},
         "roofline": roof,
+        "roofline_3d": roof3,
         "cpu_baseline": cpu,
         "time_to_1e8": t2e,
     }
