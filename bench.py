@@ -259,8 +259,8 @@ def implicit_bench(args):
 # (its 8-accumulator launches, 1991 of 2021 per application; FETCH_SIZE x 2.0 +
 # WRITE_SIZE x 1.0, profiles/k_leap3d_x2_fp32_3d-n256-nf8.md), valid only for
 # the leap3d.hip source it was measured on.
-TRAFFIC3 = {"leap3d_sha256_16": "399a400e7a68774e",
-            "bytes": 766126.9 * 1024 * 2.0 + 1182735.6 * 1024 * 1.0}
+TRAFFIC3 = {"leap3d_sha256_16": "2768740c74429006",
+            "bytes": 778535.2 * 1024 * 2.0 + 1190961.7 * 1024 * 1.0}
 
 
 def roofline_3d():
@@ -296,8 +296,8 @@ def roofline_3d():
     traffic = round(TRAFFIC3["bytes"]) if sha == TRAFFIC3["leap3d_sha256_16"] else None
     ps = gp.interior_points * gp.nt
     return {"workload": w["name"] + "-fp32-stencil", "nt": gp.nt,
-            "kernel": "k_leap3d_x2<float, order 2, 64x16, default chunk>: 2 fused leapfrog steps + "
-                      "8 filter updates per launch (forcing-free)",
+            "kernel": "k_leap3d_x2<float, order 2, 64x8, chunk 64 (default shape)>: 2 fused "
+                      "leapfrog steps + 8 filter updates per launch (forcing-free)",
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "avg_launch_us": round(1e3 * kms / max(1, launches), 2),

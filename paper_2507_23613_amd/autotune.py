@@ -24,6 +24,7 @@ CAND_3D = [(64, 4, ch) for ch in (2, 4, 8, 16, 32)] + \
           [(32, 8, ch) for ch in (4, 8)]
 # 3D (steps-per-pass option, shape): 0 = general kernel, 1 = streamlined kernel
 CAND_3D_PASS = [(2, (bx, 16, ch)) for bx in (64, 32) for ch in (8, 16, 32, 64)] + \
+               [(2, (64, 8, ch)) for ch in (16, 32, 64)] + \
                [(1, (64, by, ch)) for by in (4, 8) for ch in (4, 8, 16, 32)] + \
                [(0, (64, 4, ch)) for ch in (4, 8, 16)]
 

@@ -352,15 +352,18 @@ int setup(Problem& pr, const mfwh_grid* g, const mfwh_time* t, int restart, void
   pr.spp = pr.G.dim == 2 ? g_steps_per_pass : pr.G.dim == 3 ? std::min(g_steps_per_pass, 2) : 0;
   if (pr.refl) pr.spp = 0;   // Neumann / Robin faces: general step kernels
   pr.depth = g_depth;
-  pr.leap = pr.G.dim == 3 ? default_leap3d_shape(pr.G, pr.spp) : default_leap_shape(pr.G, pr.spp);
-  pr.leap1 = default_leap3d_shape(pr.G, 1);
+  pr.leap = pr.G.dim == 3 ? default_leap3d_shape(pr.G, pr.spp, g->order)
+                          : default_leap_shape(pr.G, pr.spp);
+  pr.leap1 = default_leap3d_shape(pr.G, 1, g->order);
   if (g_shape_set) {
     const LaunchShape& o = g_shape_override;
     if (pr.G.dim == 3 && o.by == 16) {
       pr.leap = o;             // two-step 3D shape: the other kernels keep theirs
     } else {
       pr.shape64 = pr.shape32 = pr.leap1 = o;
-      if (!(pr.G.dim == 3 && pr.spp == 2)) pr.leap = o;
+      // 64 x 8 also suits the two-step 3D kernel with order 2
+      if (!(pr.G.dim == 3 && pr.spp == 2) || (o.bx == 64 && o.by == 8 && g->order == 2))
+        pr.leap = o;
     }
   }
   if (pr.implicit) {

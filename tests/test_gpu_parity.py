@@ -121,7 +121,8 @@ SHAPES_3D = [(64, 4, 1), (64, 4, 7), (64, 8, 3), (128, 2, 4), (32, 8, 2)]
 # the streamlined 3D kernel (MFWH_OPT_STEPS_PER_PASS 1) takes 64 x 4 and 64 x 8,
 # the two-step one (2) 64 x 16 and 32 x 16
 SHAPES_3D_LEAP = [(64, 4, 1), (64, 4, 5), (64, 8, 3), (64, 8, 200)]
-SHAPES_3D_X2 = [(64, 16, 1), (64, 16, 7), (32, 16, 3), (64, 16, 200), (64, 16, 16), (32, 16, 16)]
+SHAPES_3D_X2 = [(64, 16, 1), (64, 16, 7), (32, 16, 3), (64, 16, 200), (64, 16, 16), (32, 16, 16),
+                (64, 8, 5), (64, 8, 64)]   # 64 x 8: order 2 only
 
 
 @pytest.mark.parametrize("shape", SHAPES_2D, ids=lambda s: f"bx{s[0]}-c{s[2]}")
@@ -156,6 +157,8 @@ def test_launch_shapes_3d(kernel, forcing, order):
     try:
         L.mfwh_set_option(L.MFWH_OPT_STEPS_PER_PASS, spp)
         L.mfwh_set_launch_shape(*shape)
+        # (a 64 x 8 override with order 4 leaves the two-step kernel at its
+        # default shape: such a block would own no row)
         gp = _gp(w)
         out = gp.apply(torch.as_tensor(V, device="cuda"), forcing=forcing).cpu().numpy()
     finally:
