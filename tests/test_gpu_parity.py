@@ -375,6 +375,26 @@ def test_config2_full_size_helmholtz_fixed_point():
     assert rel(out, U) < 1e-9
 
 
+def test_large_grid_4097_helmholtz_fixed_point():
+    """A grid 16 times the 2D workload's (4097^2 points, 16.8M unknowns per
+    field, N_t ~ 16k, the autotuned three-step kernel): the DST-I Helmholtz
+    solution is still mapped to itself -- large-index addressing and
+    rounding over long windows."""
+    L = _L()
+    w = inputs.config2(0, n=4097)
+    try:
+        L.mfwh_set_option(L.MFWH_OPT_STEPS_PER_PASS, 3)
+        gp = _gp(w, restart=0)
+        prob, _ = workload.setup(dict(w, f=None), filt="traditional")
+        U = np.stack([fd.helmholtz_dst(w["f"][m], w["omega"][m], prob.h, 4) for m in range(4)])
+        out = gp.apply(torch.as_tensor(U, device="cuda"), True).cpu().numpy()
+    finally:
+        L.mfwh_set_option(L.MFWH_OPT_STEPS_PER_PASS, 2)
+    e = rel(out, U)
+    print(f"4097^2 fixed point: N_t={gp.nt} rel err {e:.2e}")
+    assert e < 1e-9
+
+
 def test_config2_full_size_gmres_matches_dst():
     w = inputs.config2(0)
     gp = _gp(w, restart=128)
