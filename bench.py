@@ -16,7 +16,7 @@ Extra fields:
   roofline       the fused step kernel: algorithmic bytes per launch / the
                  launch duration measured with HIP events on its stream during
                  the timed steps, against the 8 TB/s HBM peak
-  roofline_3d    the same measurement for the two-step kernel on the 3D 256^3
+  roofline_3d    the same measurement for the three-step kernel on the 3D 256^3
                  workload (float32 stencil, 8 filters; its 1.8 GB working set
                  streams from HBM, while the 2D workload's fits the 256 MB
                  Infinity Cache): two forcing-free applications
@@ -255,17 +255,17 @@ def implicit_bench(args):
                       "rows": rows}), flush=True)
 
 
-# HBM traffic per launch of the two-step 3D kernel on the 256^3 workload
-# (its 8-accumulator launches, 1991 of 2021 per application; FETCH_SIZE x 2.0 +
-# WRITE_SIZE x 1.0, profiles/k_leap3d_x2_fp32_3d-n256-nf8.md), valid only for
+# HBM traffic per launch of the three-step 3D kernel on the 256^3 workload
+# (its 8-accumulator launches; FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0,
+# profiles/k_leap3d_x3_fp32_3d-n256-nf8.md), valid only for
 # the leap3d.hip source it was measured on.
-TRAFFIC3 = {"leap3d_sha256_16": "2768740c74429006",
-            "bytes": 778535.2 * 1024 * 2.0 + 1190961.7 * 1024 * 1.0}
+TRAFFIC3 = {"leap3d_sha256_16": "39263f0d56592372",
+            "bytes": 978672.6 * 1024 * 2.0 + 1213269.1 * 1024 * 1.0}
 
 
 def roofline_3d():
     """The 3D 256^3 workload (float32 stencil, variable c, 8 filters): two
-    forcing-free applications with the two-step kernel; its algorithmic bytes
+    forcing-free applications with the three-step kernel; its algorithmic bytes
     per launch over the event-timed launch duration against the 8 TB/s peak
     (this is the workload whose kernel streams from HBM: 1.8 GB working set)."""
     import hashlib
@@ -274,7 +274,7 @@ def roofline_3d():
     from paper_2507_23613_amd import inputs
     from paper_2507_23613_amd.problem import GpuProblem
     w = inputs.config3(0)
-    L.mfwh_set_option(L.MFWH_OPT_STEPS_PER_PASS, 2)
+    L.mfwh_set_option(L.MFWH_OPT_STEPS_PER_PASS, L.MFWH_STEPS_AUTO)
     L.mfwh_set_launch_shape(0)
     gp = GpuProblem(w, precision=L.MFWH_FP32_STENCIL, restart=0)
     nf = len(w["omega"])
@@ -296,7 +296,7 @@ def roofline_3d():
     traffic = round(TRAFFIC3["bytes"]) if sha == TRAFFIC3["leap3d_sha256_16"] else None
     ps = gp.interior_points * gp.nt
     return {"workload": w["name"] + "-fp32-stencil", "nt": gp.nt,
-            "kernel": "k_leap3d_x2<float, order 2, 64x8, chunk 64 (default shape)>: 2 fused "
+            "kernel": "k_leap3d_x3<float, order 2, 64x16, chunk 16 (default shape)>: 3 fused "
                       "leapfrog steps + 8 filter updates per launch (forcing-free)",
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
@@ -410,8 +410,9 @@ def main():
     ap.add_argument("--config", type=int, default=2, choices=[2, 3],
                     help="apply mode: the 2D 1025^2 workload (float64) or the 3D 256^3 "
                          "workload (float32 stencil, variable c, 8 frequencies)")
-    ap.add_argument("--spp", type=int, default=2, choices=[0, 1, 2, 3, 4],
-                    help="2D step kernel: 0 general, 1..4 streamlined steps per launch")
+    ap.add_argument("--spp", type=int, default=-1, choices=[-1, 0, 1, 2, 3, 4],
+                    help="step kernel: -1 the library's choice (3), 0 general, "
+                         "1..4 streamlined steps per launch (3D: at most 3)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); multi-GPU slab "
@@ -454,7 +455,7 @@ def main():
     RESTART = 128
     gp = GpuProblem(w, precision=prec, restart=0 if args.mode == "apply" else RESTART)
     log(f"N_t={gp.nt} dt={gp.dt:.3e} interior={gp.interior_points}")
-    spp, shape = args.spp, None
+    spp, shape = (args.spp if args.spp >= 0 else 3), None   # -1: the library's choice (3)
     if not args.no_tune and args.mode == "solve":
         from paper_2507_23613_amd import autotune
         (spp, shape), _ = autotune.tune(gp, reps=2, log=log)

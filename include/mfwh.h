@@ -376,15 +376,18 @@ int mfwh_set_launch_shape(int bx, int by, int chunk);
  * replay it for every application; 0 launches every step from the host.
  * While step timing (mfwh_stats_enable) is on, a graph replay is timed as a
  * whole and counted as the number of step launches it holds.
- * MFWH_OPT_STEPS_PER_PASS (default 2): 2D grids: after the first step,
+ * MFWH_OPT_STEPS_PER_PASS (default -1 = automatic: 3, i.e. three steps per
+ * launch where the kernels have it, else two): 2D grids: after the first step,
  * 0 runs every step with the general step kernel, 1 with the streamlined 2D
  * kernel one step per launch, 2 with the streamlined kernel two steps per
  * launch (temporal blocking: W^{n+1} is recomputed on a halo and every filter
  * accumulator is read and written once per two steps), 3 or 4 that many
  * steps per launch for applications without forcing (with forcing: two).
  * 3D grids: 0 runs the general kernel, 1 the streamlined 3D kernel (one
- * step per launch, launch shapes 64 x 4 or 64 x 8), 2 or more two steps
- * per launch (launch shapes 64 x 16 or 32 x 16).  All compute the
+ * step per launch, launch shapes 64 x 4 or 64 x 8), 2 two steps per launch
+ * (64 x 8 with order 2, 64 x 16 or 32 x 16), 3 or more three steps per
+ * launch with order 2 for applications without forcing (64 x 16 or 32 x 16;
+ * with forcing, and with order 4: two).  All compute the
  * same values up to floating-point contraction; 1D grids always use the
  * general kernel.
  * MFWH_OPT_PREFETCH_DEPTH (2 or 4; default 4): register sets of row operands

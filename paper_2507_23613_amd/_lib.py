@@ -372,6 +372,7 @@ def mfwh_stats_read():
 
 MFWH_OPT_GRAPHS = 1
 MFWH_OPT_STEPS_PER_PASS = 2
+MFWH_STEPS_AUTO = -1          # MFWH_OPT_STEPS_PER_PASS value: the built-in choice
 MFWH_OPT_PREFETCH_DEPTH = 3
 
 

@@ -22,8 +22,11 @@ CAND_2D_PASS = [(2, (bx, 1, ch)) for bx in (64, 128) for ch in (2, 4, 8, 16)] + 
 CAND_3D = [(64, 4, ch) for ch in (2, 4, 8, 16, 32)] + \
           [(64, 8, ch) for ch in (4, 8, 16)] + [(128, 2, ch) for ch in (4, 8, 16)] + \
           [(32, 8, ch) for ch in (4, 8)]
-# 3D (steps-per-pass option, shape): 0 = general kernel, 1 = streamlined kernel
-CAND_3D_PASS = [(2, (bx, 16, ch)) for bx in (64, 32) for ch in (8, 16, 32, 64)] + \
+# 3D (steps-per-pass option, shape): 0 = general kernel, 1 = streamlined kernel,
+# 2 and 3 = two and three fused steps per pass (three with order 2 only; the
+# library runs two for order 4)
+CAND_3D_PASS = [(3, (bx, 16, ch)) for bx in (64, 32) for ch in (8, 16, 32)] + \
+               [(2, (bx, 16, ch)) for bx in (64, 32) for ch in (8, 16, 32, 64)] + \
                [(2, (64, 8, ch)) for ch in (16, 32, 64)] + \
                [(1, (64, by, ch)) for by in (4, 8) for ch in (4, 8, 16, 32)] + \
                [(0, (64, 4, ch)) for ch in (4, 8, 16)]
@@ -69,7 +72,7 @@ def tune(gp, reps=2, candidates=None, log=None):
                 log(f"autotune {c}: {times[c]:.3f} ms per application")
     finally:
         L.mfwh_set_launch_shape(0)
-        L.mfwh_set_option(L.MFWH_OPT_STEPS_PER_PASS, 2)
+        L.mfwh_set_option(L.MFWH_OPT_STEPS_PER_PASS, L.MFWH_STEPS_AUTO)
     best = min(times, key=times.get)
     install(best)
     return best, times

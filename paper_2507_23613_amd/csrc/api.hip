@@ -311,7 +311,7 @@ struct Problem {
 LaunchShape g_shape_override;   // bx == 0: use defaults
 bool g_shape_set = false;
 bool g_graphs = true;           // solvers record step sequences into graphs
-int g_steps_per_pass = 2;       // 2D step kernel selection (MFWH_OPT_STEPS_PER_PASS)
+int g_steps_per_pass = -1;      // steps per pass (MFWH_OPT_STEPS_PER_PASS; -1: automatic)
 int g_depth = 4;                // prefetch depth of the streamlined kernels (MFWH_OPT_PREFETCH_DEPTH)
 
 int setup(Problem& pr, const mfwh_grid* g, const mfwh_time* t, int restart, void* ws,
@@ -348,8 +348,13 @@ int setup(Problem& pr, const mfwh_grid* g, const mfwh_time* t, int restart, void
                                      " bytes, got " + std::to_string(ws_bytes));
   pr.shape64 = default_shape(pr.G, g->order, 8);
   pr.shape32 = default_shape(pr.G, g->order, 4);
-  // 2D: 0..4 steps per pass; 3D: 0 (general kernel), 1 or 2
-  pr.spp = pr.G.dim == 2 ? g_steps_per_pass : pr.G.dim == 3 ? std::min(g_steps_per_pass, 2) : 0;
+  // 2D: 0..4 steps per pass; 3D: 0..3 with order 2, 0..2 with order 4;
+  // automatic: the most that kernel family has (three steps per pass in 2D
+  // and in 3D with order 2: the fastest measured on the 1025^2, 4097^2 and
+  // 256^3 workloads)
+  const int spp_max3 = g->order == 2 ? 3 : 2;
+  const int want = g_steps_per_pass < 0 ? 3 : g_steps_per_pass;
+  pr.spp = pr.G.dim == 2 ? want : pr.G.dim == 3 ? std::min(want, spp_max3) : 0;
   if (pr.refl) pr.spp = 0;   // Neumann / Robin faces: general step kernels
   pr.depth = g_depth;
   pr.leap = pr.G.dim == 3 ? default_leap3d_shape(pr.G, pr.spp, g->order)
@@ -358,14 +363,19 @@ int setup(Problem& pr, const mfwh_grid* g, const mfwh_time* t, int restart, void
   if (g_shape_set) {
     const LaunchShape& o = g_shape_override;
     if (pr.G.dim == 3 && o.by == 16) {
-      pr.leap = o;             // two-step 3D shape: the other kernels keep theirs
+      pr.leap = o;             // multi-step 3D shape: the other kernels keep theirs
     } else {
       pr.shape64 = pr.shape32 = pr.leap1 = o;
       // 64 x 8 also suits the two-step 3D kernel with order 2
-      if (!(pr.G.dim == 3 && pr.spp == 2) || (o.bx == 64 && o.by == 8 && g->order == 2))
+      if (!(pr.G.dim == 3 && pr.spp >= 2) || (o.bx == 64 && o.by == 8 && g->order == 2))
         pr.leap = o;
     }
   }
+  // shapes the multi-step kernels do not take run fewer steps per pass: the
+  // three- and four-step 2D kernels need bx >= 128, the three-step 3D kernel
+  // by = 16
+  if (pr.G.dim == 2 && pr.spp >= 3 && pr.leap.bx < 128) pr.spp = 2;
+  if (pr.G.dim == 3 && pr.spp == 3 && pr.leap.by != 16) pr.spp = 2;
   if (pr.implicit) {
     pr.W.lev[0].c2 = pr.varc ? pr.W.c64 : nullptr;
     pr.W.mx[0] = nullptr;   // level 0 solves in place in the W buffers
@@ -846,7 +856,7 @@ int apply_t(Problem& pr, const double* v, ExtLayout vl, bool forcing, const Out&
     // slot unconditionally and store only the first nq)
     for (int j = nq; j < MFWH_MAX_NF; ++j) la.qm[j] = nq > 0 ? la.qm[nq - 1] : 0;
     if (pr.G.dim == 3)
-      return launch_leap3d<T>(la, pr.grid->order, ns, ns == 2 ? pr.leap : pr.leap1, s);
+      return launch_leap3d<T>(la, pr.grid->order, ns, ns >= 2 ? pr.leap : pr.leap1, s);
     return launch_leap2d<T>(la, pr.grid->order, ns, pr.depth, pr.leap, s);
   };
   double bytes_all = 0.0;          // algorithmic bytes of the whole sequence
@@ -1834,7 +1844,7 @@ int mfwh_set_option(int key, long long value) {
       g_graphs = value != 0;
       return MFWH_OK;
     case MFWH_OPT_STEPS_PER_PASS:
-      if (value < 0 || value > 4) return fail(MFWH_EINVAL, "steps per pass must be 0 .. 4");
+      if (value < -1 || value > 4) return fail(MFWH_EINVAL, "steps per pass must be -1 .. 4");
       g_steps_per_pass = (int)value;
       return MFWH_OK;
     case MFWH_OPT_PREFETCH_DEPTH:

@@ -394,8 +394,176 @@ hipError_t launch_shape3(LeapArgs<T>& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+// -------------------------------------------------------------------------
+// three steps per pass (order 2, forcing-free): the two-step scheme with one
+// more level.  A BX x BY block owns a (BX - 6) x (BY - 6) column tile;
+// thread (lx, ly) sits on column (x0 - 3 + lx, y0 - 3 + ly).  At iteration z
+// level 1 (W^{n+1}) is computed on plane z + 2 for lanes at least 1 from the
+// block edge, level 2 (W^{n+2}) on plane z + 1 at least 2 from it, level 3
+// (W^{n+3}) on plane z on the owned tile; the x/y-neighbour planes of the
+// three levels (W^n on z + 2, W^{n+1} on z + 1, W^{n+2} on z) go to LDS
+// before the iteration's one barrier.  Every accumulator is read and written
+// once per three steps; w1 / w2 receive W^{n+2} and W^{n+3}.
+template <typename T, int QM>
+struct Plane3 {
+  T w, sw;          // new W^n value (plane z + 3) and its factor
+  T p, c;           // W^{n-1}, c^2 on plane z + 2
+  double q[QM];     // accumulators on plane z
+};
+
+template <typename T, int BX, int BY, int QM>
+__global__ void __launch_bounds__(BX * BY) k_leap3d_x3(LeapArgs<T> a) {
+  constexpr int H = 3;                    // halo columns per side (3 steps x R = 1)
+  constexpr int OX = BX - 2 * H, OY = BY - 2 * H;
+  __shared__ T p0[2][BY][BX];             // W^n on plane z + 2
+  __shared__ T p1[2][BY][BX];             // W^{n+1} on plane z + 1
+  __shared__ T p2[2][BY][BX];             // W^{n+2} on plane z
+  const int lb = xcd_tile3(blockIdx.x, gridDim.x);
+  if (lb >= a.nblocks) return;
+  const int cz = lb % a.nchunk;
+  const int t2 = lb / a.nchunk;
+  const int tx = t2 % a.ntx;
+  const int ty = t2 / a.ntx;
+  const int lx = threadIdx.x, ly = threadIdx.y;
+  const int nxi = a.g.nxi, nyi = a.g.nyi, nzi = a.g.nzi;
+  const long long py = a.g.py, pz = a.g.pz, fs = a.g.fs;
+  const int x0 = tx * OX, y0 = ty * OY;
+  const int ex = x0 - H + lx, ey = y0 - H + ly;
+  T sx, sy;
+  const int ix = ext_src3(ex, nxi, sx), iy = ext_src3(ey, nyi, sy);
+  const T sxy = sx * sy;
+  const bool inxy = ex >= 0 && ex < nxi && ey >= 0 && ey < nyi;
+  auto inner = [&](int m) { return inxy && lx >= m && lx < BX - m && ly >= m && ly < BY - m; };
+  const bool m1 = inner(1), m2 = inner(2), own = inner(3);
+  const bool qrow = ly >= H && ly < BY - H;
+  static_assert(BX == 64 || BX == 32, "a wave covers one or two whole rows");
+  const long long col = (long long)iy * py + ix;
+  const int qx = min(max(ex, x0), min(x0 + OX, nxi) - 1);
+  const int qy = min(max(ey, y0), min(y0 + OY, nyi) - 1);
+  const long long qcol = (long long)qy * py + qx;       // an owned column
+  const T* __restrict__ c2p = a.c2 ? a.c2 : a.wp;       // read and ignored when c = 1
+  const int z0 = cz * a.chunk;
+  const int z1 = min(z0 + a.chunk, nzi);
+  const T* __restrict__ wc = a.wc;
+  auto ldw = [&](int z, T& sg) -> T {
+    T sz;
+    const int iz = ext_src3(z, nzi, sz);
+    sg = sxy * sz;
+    return wc[(long long)iz * pz + col];
+  };
+  const T dg = a.wx[0] + a.wy[0] + a.wz[0];
+  // one leapfrog step at this lane from the centre value `ce`, its LDS plane
+  // `pl` (x/y neighbours), the z-neighbours `zm`, `zp`, the previous level
+  // `pv` and c^2
+  auto step = [&](T ce, const T (*pl)[BX], T zm, T zp, T pv, T cc) {
+    const int cx = min(max(lx, 1), BX - 2), cy = min(max(ly, 1), BY - 2);
+    const T lap = dg * ce + a.wx[1] * (pl[cy][cx - 1] + pl[cy][cx + 1]) +
+                  a.wy[1] * (pl[cy - 1][cx] + pl[cy + 1][cx]) + a.wz[1] * (zm + zp);
+    return a.cA * ce + a.cB * pv + a.cC * (cc * lap);
+  };
+
+  T wn[3];             // W^n on planes z+1 .. z+3 at iteration z
+  T w1[3];             // W^{n+1} on planes z .. z+2
+  T w2[3];             // W^{n+2} on planes z-1 .. z+1
+  T cw[3];             // c^2 on planes z .. z+2
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    T sg;
+    const T v = ldw(z0 - 3 + k, sg);      // planes r0 + 1, r0 + 2 (r0 = z0 - 4)
+    wn[k + 1] = sg * v;
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    w1[k] = T(0);
+    w2[k] = T(0);
+    cw[k] = T(1);
+  }
+
+  auto fetch = [&](Plane3<T, QM>& o, int z) {
+    o.w = ldw(z + 3, o.sw);
+    const int e1 = min(max(z + 2, 0), nzi - 1);
+    const long long i1 = (long long)e1 * pz + col;
+    o.p = a.wp[i1];
+    o.c = c2p[i1];
+    if (qrow) {
+      const long long i2 = (long long)max(z, z0) * pz + qcol;
+#pragma unroll
+      for (int q = 0; q < QM; ++q) o.q[q] = a.q[a.qm[q] * fs + i2];
+    }
+  };
+  auto process = [&](int z, const Plane3<T, QM>& o, int buf) {
+    wn[0] = wn[1];
+    wn[1] = wn[2];
+    wn[2] = o.sw * o.w;
+    w1[0] = w1[1];
+    w1[1] = w1[2];
+    w2[0] = w2[1];
+    w2[1] = w2[2];
+    cw[0] = cw[1];
+    cw[1] = cw[2];
+    cw[2] = a.c2 ? o.c : T(1);
+    p0[buf][ly][lx] = wn[1];
+    p1[buf][ly][lx] = w1[1];
+    p2[buf][ly][lx] = w2[1];
+    __syncthreads();
+    // level 1: W^{n+1} on plane z + 2
+    const T v1 = step(wn[1], p0[buf], wn[0], wn[2], o.p, cw[2]);
+    w1[2] = (m1 && z + 2 >= 0 && z + 2 < nzi) ? v1 : T(0);
+    // level 2: W^{n+2} on plane z + 1
+    const T v2 = step(w1[1], p1[buf], w1[0], w1[2], wn[0], cw[1]);
+    w2[2] = (m2 && z + 1 >= 0 && z + 1 < nzi) ? v2 : T(0);
+    // level 3: W^{n+3} on plane z (owned)
+    const T v3 = step(w2[1], p2[buf], w2[0], w2[2], w1[0], cw[0]);
+    if (z >= z0 && own) {
+      const long long idx = (long long)z * pz + (long long)ey * py + ex;
+      a.w1[idx] = w2[1];
+      a.w2[idx] = v3;
+      const double d1 = (double)w1[0], d2 = (double)w2[1], d3 = (double)v3;
+#pragma unroll
+      for (int q = 0; q < QM; ++q)
+        if (q < a.nq)
+          a.q[a.qm[q] * fs + idx] = ((o.q[q] + a.kk[0][q] * d1) + a.kk[1][q] * d2) +
+                                    a.kk[2][q] * d3;
+    }
+  };
+
+  // fetches past the last plane re-read the last plane (valid, unused)
+  Plane3<T, QM> ra, rb;
+  const int r0 = z0 - 4;
+  fetch(ra, r0);
+  for (int z = r0; z < z1; z += 2) {
+    fetch(rb, min(z + 1, z1 - 1));
+    process(z, ra, 0);
+    if (z + 1 >= z1) break;
+    fetch(ra, min(z + 2, z1 - 1));
+    process(z + 1, rb, 1);
+  }
+}
+
+template <typename T, int BX, int BY>
+hipError_t launch_x3_3(LeapArgs<T>& a, hipStream_t s) {
+  const Geom& g = a.g;
+  a.ntx = (g.nxi + BX - 7) / (BX - 6);
+  a.nty = (g.nyi + BY - 7) / (BY - 6);
+  a.nchunk = (g.nzi + a.chunk - 1) / a.chunk;
+  a.nblocks = a.ntx * a.nty * a.nchunk;
+  const int grid = pad8(a.nblocks);
+  const dim3 blk(BX, BY);
+  if (a.force) return hipErrorInvalidValue;   // three steps per pass run forcing-free
+  if (a.nq <= 4) k_leap3d_x3<T, BX, BY, 4><<<grid, blk, 0, s>>>(a);
+  else k_leap3d_x3<T, BX, BY, 8><<<grid, blk, 0, s>>>(a);
+  return hipGetLastError();
+}
+
 template <typename T, int R>
 hipError_t launch_r3(LeapArgs<T>& a, int steps, const LaunchShape& ls, hipStream_t s) {
+  if (steps == 3) {
+    if constexpr (R == 1) {
+      if (ls.bx == 64 && ls.by == 16) return launch_x3_3<T, 64, 16>(a, s);
+      if (ls.bx == 32 && ls.by == 16) return launch_x3_3<T, 32, 16>(a, s);
+    }
+    return hipErrorInvalidValue;
+  }
   if (steps == 2) {
     if (ls.bx == 64 && ls.by == 16) return launch_x2_3<T, R, 64, 16>(a, s);
     if (ls.bx == 32 && ls.by == 16) return launch_x2_3<T, R, 32, 16>(a, s);
@@ -414,9 +582,10 @@ hipError_t launch_r3(LeapArgs<T>& a, int steps, const LaunchShape& ls, hipStream
 template <typename T>
 hipError_t launch_leap3d(LeapArgs<T>& a, int order, int steps, const LaunchShape& ls,
                          hipStream_t s) {
-  if (a.g.dim != 3 || a.nq < 0 || a.nq > MFWH_MAX_NF || (steps != 1 && steps != 2))
+  if (a.g.dim != 3 || a.nq < 0 || a.nq > MFWH_MAX_NF || steps < 1 || steps > 3 ||
+      (steps == 3 && order != 2))
     return hipErrorInvalidValue;
-  if (steps == 2 && (a.w1 == a.wc || a.w1 == a.wp || a.w2 == a.wc || a.w2 == a.wp ||
+  if (steps >= 2 && (a.w1 == a.wc || a.w1 == a.wp || a.w2 == a.wc || a.w2 == a.wp ||
                      a.w1 == a.w2 || !a.w2))
     return hipErrorInvalidValue;
   a.chunk = std::max(1, ls.chunk);
@@ -431,14 +600,18 @@ LaunchShape default_leap3d_shape(const Geom& g, int steps, int order) {
   LaunchShape ls;
   ls.bx = 64;
   // two steps: 64 x 8 with order 2 (60 x 4 owned columns; two blocks per CU,
-  // measured 4 % faster on 256^3 than 64 x 16), 64 x 16 with order 4
-  ls.by = steps == 2 ? (order == 2 ? 8 : 16) : 4;
-  const int h = steps == 2 ? 2 * order : 0;                  // 4R columns of halo
+  // measured 4 % faster on 256^3 than 64 x 16), 64 x 16 with order 4;
+  // three steps (order 2): 64 x 16
+  ls.by = steps == 3 ? 16 : steps == 2 ? (order == 2 ? 8 : 16) : 4;
+  const int h = steps >= 2 ? steps * order : 0;              // 2 x steps x R halo columns
   const int ox = 64 - h, oy = ls.by - h;
   const long long tiles = ((g.nxi + ox - 1) / ox) * (long long)((g.nyi + oy - 1) / oy);
   const long long target_waves = 256LL * 16;
   long long ch = tiles * (ls.bx * ls.by / 64) * g.nzi / target_waves;
-  ls.chunk = (int)std::min<long long>(std::max<long long>(ch, steps == 2 ? 8 : 4), 64);
+  ls.chunk = (int)std::min<long long>(std::max<long long>(ch, steps >= 2 ? 8 : 4), 64);
+  // three steps: 16 planes (256^3: 0.259 ms per step against 0.269 for 32
+  // and 0.282 for 64; the 4 recomputed planes per chunk buy more blocks)
+  if (steps == 3) ls.chunk = 16;
   return ls;
 }
 

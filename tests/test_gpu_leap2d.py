@@ -64,7 +64,7 @@ def _apply(w, V, forcing, spp, precision=0, shape=None, depth=4):
         gp = GpuProblem(w, precision=precision)
         out = gp.apply(torch.as_tensor(V, device="cuda"), forcing=forcing).cpu().numpy()
     finally:
-        L.mfwh_set_option(L.MFWH_OPT_STEPS_PER_PASS, 2)
+        L.mfwh_set_option(L.MFWH_OPT_STEPS_PER_PASS, L.MFWH_STEPS_AUTO)
         L.mfwh_set_option(L.MFWH_OPT_PREFETCH_DEPTH, 4)
         L.mfwh_set_launch_shape(0)
     return out, gp.nt
@@ -172,7 +172,7 @@ def test_two_step_gmres_matches_general_kernel():
             gp = GpuProblem(w, restart=40)
             v, info = gp.gmres(max_iter=300, tol=1e-11)
         finally:
-            L.mfwh_set_option(L.MFWH_OPT_STEPS_PER_PASS, 2)
+            L.mfwh_set_option(L.MFWH_OPT_STEPS_PER_PASS, L.MFWH_STEPS_AUTO)
         res[spp] = (v.cpu().numpy(), info)
     assert res[0][1]["converged"] and res[2][1]["converged"]
     assert abs(res[0][1]["iterations"] - res[2][1]["iterations"]) <= 1

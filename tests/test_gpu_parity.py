@@ -123,6 +123,9 @@ SHAPES_3D = [(64, 4, 1), (64, 4, 7), (64, 8, 3), (128, 2, 4), (32, 8, 2)]
 SHAPES_3D_LEAP = [(64, 4, 1), (64, 4, 5), (64, 8, 3), (64, 8, 200)]
 SHAPES_3D_X2 = [(64, 16, 1), (64, 16, 7), (32, 16, 3), (64, 16, 200), (64, 16, 16), (32, 16, 16),
                 (64, 8, 5), (64, 8, 64)]   # 64 x 8: order 2 only
+# three steps per pass (3): order 2, forcing-free passes (order 4 and forced
+# passes run the two-step kernel with the same shape)
+SHAPES_3D_X3 = [(64, 16, 1), (64, 16, 5), (32, 16, 3), (64, 16, 64), (64, 16, 300)]
 
 
 @pytest.mark.parametrize("shape", SHAPES_2D, ids=lambda s: f"bx{s[0]}-c{s[2]}")
@@ -143,8 +146,8 @@ def test_launch_shapes_2d(shape, order):
 
 
 @pytest.mark.parametrize("kernel", [(0, s) for s in SHAPES_3D] + [(1, s) for s in SHAPES_3D_LEAP] +
-                         [(2, s) for s in SHAPES_3D_X2],
-                         ids=lambda k: f"{['general', 'leap', 'x2'][k[0]]}-bx{k[1][0]}-by{k[1][1]}-c{k[1][2]}")
+                         [(2, s) for s in SHAPES_3D_X2] + [(3, s) for s in SHAPES_3D_X3],
+                         ids=lambda k: f"{['general', 'leap', 'x2', 'x3'][k[0]]}-bx{k[1][0]}-by{k[1][1]}-c{k[1][2]}")
 @pytest.mark.parametrize("forcing", [True, False], ids=["forced", "free"])
 @pytest.mark.parametrize("order", [2, 4])
 def test_launch_shapes_3d(kernel, forcing, order):
@@ -163,7 +166,7 @@ def test_launch_shapes_3d(kernel, forcing, order):
         out = gp.apply(torch.as_tensor(V, device="cuda"), forcing=forcing).cpu().numpy()
     finally:
         L.mfwh_set_launch_shape(0)
-        L.mfwh_set_option(L.MFWH_OPT_STEPS_PER_PASS, 2)
+        L.mfwh_set_option(L.MFWH_OPT_STEPS_PER_PASS, L.MFWH_STEPS_AUTO)
     assert rel(out, ref) < tol64(pl)
 
 
@@ -180,12 +183,34 @@ def test_x2_3d_whole_and_partial_chunks(shape, forcing, order, precision):
     V = rand_v(w["shape"], 8, 9)
     ref = omf.apply(prob, pl, w["f"], V, forcing)
     try:
-        L.mfwh_set_option(L.MFWH_OPT_STEPS_PER_PASS, 2)
+        L.mfwh_set_option(L.MFWH_OPT_STEPS_PER_PASS, L.MFWH_STEPS_AUTO)
         L.mfwh_set_launch_shape(*shape)
         gp = _gp(w, precision=precision)
         out = gp.apply(torch.as_tensor(V, device="cuda"), forcing=forcing).cpu().numpy()
     finally:
         L.mfwh_set_launch_shape(0)
+    assert rel(out, ref) < (tol64(pl) if precision == 0 else tol32(pl))
+
+
+@pytest.mark.parametrize("chunk", [16, 64])
+@pytest.mark.parametrize("forcing", [True, False], ids=["forced", "free"])
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "fp32"])
+def test_x3_3d_eight_filters(chunk, forcing, precision):
+    """Three steps per pass in 3D (order 2) with 8 filters on 38 interior
+    planes (whole and partial chunks); forced passes run two steps."""
+    L = _L()
+    w = inputs.small(seed=6, shape=(40, 21, 70), nf=8, order=2, varc=True, lo=4.0, hi=30.0)
+    prob, pl = workload.setup(w)
+    V = rand_v(w["shape"], 8, 9)
+    ref = omf.apply(prob, pl, w["f"], V, forcing)
+    try:
+        L.mfwh_set_option(L.MFWH_OPT_STEPS_PER_PASS, 3)
+        L.mfwh_set_launch_shape(64, 16, chunk)
+        gp = _gp(w, precision=precision)
+        out = gp.apply(torch.as_tensor(V, device="cuda"), forcing=forcing).cpu().numpy()
+    finally:
+        L.mfwh_set_launch_shape(0)
+        L.mfwh_set_option(L.MFWH_OPT_STEPS_PER_PASS, L.MFWH_STEPS_AUTO)
     assert rel(out, ref) < (tol64(pl) if precision == 0 else tol32(pl))
 
 
@@ -389,7 +414,7 @@ def test_large_grid_4097_helmholtz_fixed_point():
         U = np.stack([fd.helmholtz_dst(w["f"][m], w["omega"][m], prob.h, 4) for m in range(4)])
         out = gp.apply(torch.as_tensor(U, device="cuda"), True).cpu().numpy()
     finally:
-        L.mfwh_set_option(L.MFWH_OPT_STEPS_PER_PASS, 2)
+        L.mfwh_set_option(L.MFWH_OPT_STEPS_PER_PASS, L.MFWH_STEPS_AUTO)
     e = rel(out, U)
     print(f"4097^2 fixed point: N_t={gp.nt} rel err {e:.2e}")
     assert e < 1e-9
