@@ -415,8 +415,8 @@ def main():
                          "1..4 streamlined steps per launch (3D: at most 3)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); multi-GPU slab "
-              "decomposition is a design, not part of this build", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU slab "
+              "decomposition is a design that is not implemented", file=sys.stderr)
         sys.exit(2)
     import torch
     if args.mode == "copy":
