@@ -251,3 +251,24 @@ def test_robin_stability_limit():
     """A large Robin coefficient raises the spectral radius of Delta_h beyond
     what the planned dt allows: rejected before any device work."""
     _bad(-3, grid=L.make_grid((17, 17), order=2, bc=[(("R", 1000.0), ("N",)), (("D",), ("D",))]))
+
+
+def test_option_and_launch_shape_validation():
+    """mfwh_set_option and mfwh_set_launch_shape check their arguments and
+    leave the library's state unchanged on a rejected value."""
+    key = L.MFWH_OPT_STEPS_PER_PASS
+    for bad in (-2, 5, 100):
+        with pytest.raises(L.MfwhError):
+            L.mfwh_set_option(key, bad)
+    for ok in (L.MFWH_STEPS_AUTO, 0, 1, 2, 3, 4):
+        L.mfwh_set_option(key, ok)
+    L.mfwh_set_option(key, L.MFWH_STEPS_AUTO)
+    with pytest.raises(L.MfwhError):
+        L.mfwh_set_option(L.MFWH_OPT_PREFETCH_DEPTH, 3)
+    L.mfwh_set_option(L.MFWH_OPT_PREFETCH_DEPTH, 4)
+    with pytest.raises(L.MfwhError):
+        L.mfwh_set_option(99, 1)
+    for bad in ((48, 1, 8), (64, 0, 8), (64, 4, 0)):
+        with pytest.raises(L.MfwhError):
+            L.mfwh_set_launch_shape(*bad)
+    L.mfwh_set_launch_shape(0)
