@@ -384,7 +384,7 @@ struct RowK {
   double q[QM];   // accumulators at row r
 };
 
-template <typename T, int R, int BX, int QM, int KS, int PD>
+template <typename T, int R, int BX, int QM, int KS, int PD, int CH>
 __global__ void __launch_bounds__(BX) k_leap2d_xk(LeapArgs<T> a) {
   using S = XkShape<R, KS>;
   constexpr int OW = BX - 2 * KS * R;
@@ -515,12 +515,23 @@ __global__ void __launch_bounds__(BX) k_leap2d_xk(LeapArgs<T> a) {
   RowK<T, QM> rs[PD];
 #pragma unroll
   for (int u = 0; u < PD - 1; ++u) fetch(rs[u], min(r0 + u, y1 - 1));
-  for (int r = r0; r < y1; r += PD) {
+  if constexpr (CH > 0) {
+    // chunk fixed at compile time: straight-line march, no loop back-edge
+    // to make the in-flight prefetches complete early
 #pragma unroll
-    for (int u = 0; u < PD; ++u) {
-      if (r + u >= y1) break;
-      fetch(rs[(u + PD - 1) % PD], min(r + u + PD - 1, y1 - 1));
-      process(r + u, rs[u], u & 1);
+    for (int it = 0; it < CH + 2 * (KS - 1) * R; ++it) {
+      if (r0 + it >= y1) break;
+      fetch(rs[(it + PD - 1) % PD], min(r0 + it + PD - 1, y1 - 1));
+      process(r0 + it, rs[it % PD], it & 1);
+    }
+  } else {
+    for (int r = r0; r < y1; r += PD) {
+#pragma unroll
+      for (int u = 0; u < PD; ++u) {
+        if (r + u >= y1) break;
+        fetch(rs[(u + PD - 1) % PD], min(r + u + PD - 1, y1 - 1));
+        process(r + u, rs[u], u & 1);
+      }
     }
   }
 }
@@ -578,12 +589,24 @@ hipError_t launch_bx(LeapArgs<T>& a, int steps, int depth, hipStream_t s) {
     if constexpr (BX >= 128) {
       const bool q4 = a.nq <= 4;
       if (depth != 4 || a.force) return hipErrorInvalidValue;
+      // 128 lanes with the default chunk of 8 rows: the unrolled march
+      const bool ch8 = BX == 128 && a.chunk == 8;
       if (steps == 3) {
-        if (q4) k_leap2d_xk<T, R, BX, 4, 3, 4><<<grid, BX, 0, s>>>(a);
-        else k_leap2d_xk<T, R, BX, 8, 3, 4><<<grid, BX, 0, s>>>(a);
+        if (ch8) {
+          if (q4) k_leap2d_xk<T, R, BX, 4, 3, 4, 8><<<grid, BX, 0, s>>>(a);
+          else k_leap2d_xk<T, R, BX, 8, 3, 4, 8><<<grid, BX, 0, s>>>(a);
+        } else {
+          if (q4) k_leap2d_xk<T, R, BX, 4, 3, 4, 0><<<grid, BX, 0, s>>>(a);
+          else k_leap2d_xk<T, R, BX, 8, 3, 4, 0><<<grid, BX, 0, s>>>(a);
+        }
       } else {
-        if (q4) k_leap2d_xk<T, R, BX, 4, 4, 4><<<grid, BX, 0, s>>>(a);
-        else k_leap2d_xk<T, R, BX, 8, 4, 4><<<grid, BX, 0, s>>>(a);
+        if (ch8) {
+          if (q4) k_leap2d_xk<T, R, BX, 4, 4, 4, 8><<<grid, BX, 0, s>>>(a);
+          else k_leap2d_xk<T, R, BX, 8, 4, 4, 8><<<grid, BX, 0, s>>>(a);
+        } else {
+          if (q4) k_leap2d_xk<T, R, BX, 4, 4, 4, 0><<<grid, BX, 0, s>>>(a);
+          else k_leap2d_xk<T, R, BX, 8, 4, 4, 0><<<grid, BX, 0, s>>>(a);
+        }
       }
       return hipGetLastError();
     }
