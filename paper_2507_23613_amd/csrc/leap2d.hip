@@ -590,6 +590,8 @@ hipError_t launch_bx(LeapArgs<T>& a, int steps, int depth, hipStream_t s) {
       const bool q4 = a.nq <= 4;
       if (depth != 4 || a.force) return hipErrorInvalidValue;
       // 128 lanes with the default chunk of 8 rows: the unrolled march
+      // (1025^2, three steps: 34.9 ms per application against 37.0 ms for
+      // the loop; chunks 6, 12 and 16 unrolled: 38.2, 36.2 and 42.9 ms)
       const bool ch8 = BX == 128 && a.chunk == 8;
       if (steps == 3) {
         if (ch8) {
