@@ -389,11 +389,27 @@ __global__ void __launch_bounds__(BX) k_leap2d_xk(LeapArgs<T> a) {
   using S = XkShape<R, KS>;
   constexpr int OW = BX - 2 * KS * R;
   __shared__ T lds[2][KS][BX];            // x-neighbour rows of levels 0 .. KS-1
+  // filter weights of the pass, read from LDS where they are used: held in
+  // scalar registers for the whole march they crowd them out (the unrolled
+  // march spilled them to vector-register lanes and read them back per row)
+  // (the same for the stencil and leapfrog coefficients: cs[0] = wx0 + wy0,
+  // cs[k] = wx_k, cs[R + k] = wy_k, then cA, cB, cC)
+  __shared__ double kks[KS][QM];
+  __shared__ T cs[2 * R + 4];
   const int lb = xcd_tile(blockIdx.x, gridDim.x);
   if (lb >= a.nblocks) return;
   const int bx = lb / a.nchunk;
   const int by = lb - bx * a.nchunk;
   const int l = threadIdx.x;
+  // both tables are visible after the first barrier of the march
+  if (l < KS * QM) kks[l / QM][l % QM] = a.kk[l / QM][l % QM];
+  if (l < 2 * R + 4)
+    cs[l] = l == 0           ? a.wx[0] + a.wy[0]
+            : l <= R         ? a.wx[l]
+            : l <= 2 * R     ? a.wy[l - R]
+            : l == 2 * R + 1 ? a.cA
+            : l == 2 * R + 2 ? a.cB
+                             : a.cC;
   const int nxi = a.g.nxi, nyi = a.g.nyi;
   const long long py = a.g.py, fs = a.g.fs;
   const int x0 = bx * OW;
@@ -472,17 +488,17 @@ __global__ void __launch_bounds__(BX) k_leap2d_xk(LeapArgs<T> a) {
       const bool comp = inx && l >= j * R && l < BX - j * R && ej >= 0 && ej < nyi;
       if (comp) {
         const T cen = wv[b0 + (cj - b0)];
-        T lap = (a.wx[0] + a.wy[0]) * cen;
+        T lap = cs[0] * cen;
 #pragma unroll
         for (int k = 1; k <= R; ++k)
-          lap += a.wx[k] * (rb[l - k] + rb[l + k]) + a.wy[k] * (wv[cj - k] + wv[cj + k]);
+          lap += cs[k] * (rb[l - k] + rb[l + k]) + cs[R + k] * (wv[cj - k] + wv[cj + k]);
         // W^{n+j-2} on row ej: W^{n-1} (prefetched), W^n (level 0 oldest) or
         // level j-2, 2R rows behind its newest
         const T prev = j == 1 ? o.p
                      : j == 2 ? wv[0]
                               : wv[S::off(j - 2) + S::len(j - 2) - 1 - 2 * R];
         const T c2v = cw[S::clen - 1 - (j - 1) * R];
-        v = a.cA * cen + a.cB * prev + a.cC * (c2v * lap);
+        v = cs[2 * R + 1] * cen + cs[2 * R + 2] * prev + cs[2 * R + 3] * (c2v * lap);
       }
       if (j < KS) {
         const int base = S::off(j), last = base + S::len(j) - 1;
@@ -504,8 +520,8 @@ __global__ void __launch_bounds__(BX) k_leap2d_xk(LeapArgs<T> a) {
           double acc = o.q[q];
 #pragma unroll
           for (int j = 1; j < KS; ++j)
-            acc += a.kk[j - 1][q] * (double)wv[S::off(j) + S::len(j) - 1 - (KS - j) * R];
-          acc += a.kk[KS - 1][q] * (double)vk;
+            acc += kks[j - 1][q] * (double)wv[S::off(j) + S::len(j) - 1 - (KS - j) * R];
+          acc += kks[KS - 1][q] * (double)vk;
           a.q[a.qm[q] * fs + idx] = acc;
         }
       }
