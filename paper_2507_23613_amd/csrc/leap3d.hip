@@ -418,6 +418,11 @@ __global__ void __launch_bounds__(BX * BY) k_leap3d_x3(LeapArgs<T> a) {
   __shared__ T p0[2][BY][BX];             // W^n on plane z + 2
   __shared__ T p1[2][BY][BX];             // W^{n+1} on plane z + 1
   __shared__ T p2[2][BY][BX];             // W^{n+2} on plane z
+  // filter weights and stencil/leapfrog coefficients (dg, wx1, wy1, wz1, cA,
+  // cB, cC) read from LDS where they are used: held in scalar registers
+  // across the march they spill to vector-register lanes
+  __shared__ double kks[3][QM];
+  __shared__ T cs[7];
   const int lb = xcd_tile3(blockIdx.x, gridDim.x);
   if (lb >= a.nblocks) return;
   const int cz = lb % a.nchunk;
@@ -425,6 +430,19 @@ __global__ void __launch_bounds__(BX * BY) k_leap3d_x3(LeapArgs<T> a) {
   const int tx = t2 % a.ntx;
   const int ty = t2 / a.ntx;
   const int lx = threadIdx.x, ly = threadIdx.y;
+  {
+    // both tables are visible after the first barrier of the march
+    const int t = ly * BX + lx;
+    if (t < 3 * QM) kks[t / QM][t % QM] = a.kk[t / QM][t % QM];
+    if (t < 7)
+      cs[t] = t == 0 ? a.wx[0] + a.wy[0] + a.wz[0]
+            : t == 1 ? a.wx[1]
+            : t == 2 ? a.wy[1]
+            : t == 3 ? a.wz[1]
+            : t == 4 ? a.cA
+            : t == 5 ? a.cB
+                     : a.cC;
+  }
   const int nxi = a.g.nxi, nyi = a.g.nyi, nzi = a.g.nzi;
   const long long py = a.g.py, pz = a.g.pz, fs = a.g.fs;
   const int x0 = tx * OX, y0 = ty * OY;
@@ -451,15 +469,14 @@ __global__ void __launch_bounds__(BX * BY) k_leap3d_x3(LeapArgs<T> a) {
     sg = sxy * sz;
     return wc[(long long)iz * pz + col];
   };
-  const T dg = a.wx[0] + a.wy[0] + a.wz[0];
   // one leapfrog step at this lane from the centre value `ce`, its LDS plane
   // `pl` (x/y neighbours), the z-neighbours `zm`, `zp`, the previous level
   // `pv` and c^2
   auto step = [&](T ce, const T (*pl)[BX], T zm, T zp, T pv, T cc) {
     const int cx = min(max(lx, 1), BX - 2), cy = min(max(ly, 1), BY - 2);
-    const T lap = dg * ce + a.wx[1] * (pl[cy][cx - 1] + pl[cy][cx + 1]) +
-                  a.wy[1] * (pl[cy - 1][cx] + pl[cy + 1][cx]) + a.wz[1] * (zm + zp);
-    return a.cA * ce + a.cB * pv + a.cC * (cc * lap);
+    const T lap = cs[0] * ce + cs[1] * (pl[cy][cx - 1] + pl[cy][cx + 1]) +
+                  cs[2] * (pl[cy - 1][cx] + pl[cy + 1][cx]) + cs[3] * (zm + zp);
+    return cs[4] * ce + cs[5] * pv + cs[6] * (cc * lap);
   };
 
   T wn[3];             // W^n on planes z+1 .. z+3 at iteration z
@@ -522,8 +539,8 @@ __global__ void __launch_bounds__(BX * BY) k_leap3d_x3(LeapArgs<T> a) {
 #pragma unroll
       for (int q = 0; q < QM; ++q)
         if (q < a.nq)
-          a.q[a.qm[q] * fs + idx] = ((o.q[q] + a.kk[0][q] * d1) + a.kk[1][q] * d2) +
-                                    a.kk[2][q] * d3;
+          a.q[a.qm[q] * fs + idx] = ((o.q[q] + kks[0][q] * d1) + kks[1][q] * d2) +
+                                    kks[2][q] * d3;
     }
   };
 
