@@ -52,11 +52,11 @@ HBM_PEAK_GBS = 8000.0
 # HBM traffic per launch of the dominant step kernel, from two rocprofv3
 # --pmc runs (FETCH_SIZE, WRITE_SIZE) on `python bench.py --mode apply`, each
 # scaled by the same counter on a plain 1 GiB copy (factors 2.0 and 1.0;
-# profiles/k_leap2d_xk3_fp64_2d-n1025-nf4.md).  Keyed by (steps per pass, bx,
+# profiles/k_leap2d_xk4_fp64_2d-n1025-nf4.md).  Keyed by (steps per pass, bx,
 # chunk) and valid only for the kernel source it was measured on: reported
 # as null for another configuration or once leap2d.hip changes.
-TRAFFIC = {"leap2d_sha256_16": "556074ed62fc6801",
-           "bytes": {(3, 128, 8): 33746.4 * 1024 * 2.0 + 48763.8 * 1024 * 1.0}}
+TRAFFIC = {"leap2d_sha256_16": "b0c3f37fc386cd5e",
+           "bytes": {(4, 128, 8): 32904.5 * 1024 * 2.0 + 48688.1 * 1024 * 1.0}}
 
 
 def measured_traffic(cfg):
@@ -411,7 +411,7 @@ def main():
                     help="apply mode: the 2D 1025^2 workload (float64) or the 3D 256^3 "
                          "workload (float32 stencil, variable c, 8 frequencies)")
     ap.add_argument("--spp", type=int, default=-1, choices=[-1, 0, 1, 2, 3, 4],
-                    help="step kernel: -1 the library's choice (3), 0 general, "
+                    help="step kernel: -1 the library's choice (2D 4, 3D 3), 0 general, "
                          "1..4 streamlined steps per launch (3D: at most 3)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -455,7 +455,8 @@ def main():
     RESTART = 128
     gp = GpuProblem(w, precision=prec, restart=0 if args.mode == "apply" else RESTART)
     log(f"N_t={gp.nt} dt={gp.dt:.3e} interior={gp.interior_points}")
-    spp, shape = (args.spp if args.spp >= 0 else 3), None   # -1: the library's choice (3)
+    # -1: the library's choice (four steps per pass in 2D, three in 3D)
+    spp, shape = (args.spp if args.spp >= 0 else 4 if len(w["shape"]) == 2 else 3), None
     if not args.no_tune and args.mode == "solve":
         from paper_2507_23613_amd import autotune
         (spp, shape), _ = autotune.tune(gp, reps=2, log=log)

@@ -376,8 +376,9 @@ int mfwh_set_launch_shape(int bx, int by, int chunk);
  * replay it for every application; 0 launches every step from the host.
  * While step timing (mfwh_stats_enable) is on, a graph replay is timed as a
  * whole and counted as the number of step launches it holds.
- * MFWH_OPT_STEPS_PER_PASS (default -1 = automatic: 3, i.e. three steps per
- * launch where the kernels have it, else two): 2D grids: after the first step,
+ * MFWH_OPT_STEPS_PER_PASS (default -1 = automatic: four steps per launch on
+ * 2D grids, three on 3D grids with order 2, two with order 4): 2D grids:
+ * after the first step,
  * 0 runs every step with the general step kernel, 1 with the streamlined 2D
  * kernel one step per launch, 2 with the streamlined kernel two steps per
  * launch (temporal blocking: W^{n+1} is recomputed on a halo and every filter

@@ -193,11 +193,44 @@ __global__ void __launch_bounds__(BX) k_leap2d_x2(LeapArgs<T> a) {
   constexpr int OW = BX - 4 * R;          // owned columns per block
   __shared__ T rn[2][BX];                 // W^n row of the first step
   __shared__ T r1[2][BX];                 // W^{n+1} row of the second step
+  constexpr int FM = FORCE ? QM : 1;      // forcing slots (nf <= QM when forced)
+  // forcing-free passes read the uniform coefficients from LDS where they
+  // are used (held in scalar registers across the unrolled march they spill
+  // to vector-register lanes): filter weights, and cs[0] = wx0 + wy0,
+  // cs[k] = wx_k, cs[R + k] = wy_k, then cA, cB, cC.  Forced passes keep
+  // them in scalar registers (from LDS they cost 14 more VGPRs, past the
+  // limit of three waves per SIMD).
+  __shared__ double kks[2][QM];
+  __shared__ T cs[2 * R + 4];
+  auto cf = [&](int i) -> T {
+    if constexpr (FORCE)
+      return i == 0           ? a.wx[0] + a.wy[0]
+             : i <= R         ? a.wx[i]
+             : i <= 2 * R     ? a.wy[i - R]
+             : i == 2 * R + 1 ? a.cA
+             : i == 2 * R + 2 ? a.cB
+                              : a.cC;
+    else
+      return cs[i];
+  };
+  auto kf = [&](int st, int j) -> double {
+    if constexpr (FORCE) return a.kk[st][j];
+    else return kks[st][j];
+  };
   const int lb = xcd_tile(blockIdx.x, gridDim.x);
   if (lb >= a.nblocks) return;
   const int bx = lb / a.nchunk;
   const int by = lb - bx * a.nchunk;
   const int l = threadIdx.x;
+  // the tables are visible after the first barrier of the march
+  if (!FORCE && l < 2 * QM) kks[l / QM][l % QM] = a.kk[l / QM][l % QM];
+  if (!FORCE && l < 2 * R + 4)
+    cs[l] = l == 0           ? a.wx[0] + a.wy[0]
+            : l <= R         ? a.wx[l]
+            : l <= 2 * R     ? a.wy[l - R]
+            : l == 2 * R + 1 ? a.cA
+            : l == 2 * R + 2 ? a.cB
+                             : a.cC;
   const int nxi = a.g.nxi, nyi = a.g.nyi;
   const long long py = a.g.py, fs = a.g.fs;
   const int e = bx * OW - 2 * R + l;      // column of this lane
@@ -242,7 +275,6 @@ __global__ void __launch_bounds__(BX) k_leap2d_x2(LeapArgs<T> a) {
   const int x0 = bx * OW;
   const int qcol = min(max(e, x0), min(x0 + OW, nxi) - 1);   // an owned column
   const T* __restrict__ c2p = a.c2 ? a.c2 : a.wp;            // read and ignored when c = 1
-  constexpr int FM = FORCE ? QM : 1;   // forcing slots (nf <= QM when forced)
   auto fetch = [&](Row2<T, QM, FM>& o, int r) {
     o.w = ldw(r + 2 * R, o.sw);
     const int ey = min(max(r + R, 0), nyi - 1);   // row of the first step, clamped
@@ -291,12 +323,12 @@ __global__ void __launch_bounds__(BX) k_leap2d_x2(LeapArgs<T> a) {
     const int ey = r + R;
     T v = T(0);
     if (mid && ey >= 0 && ey < nyi) {
-      T lap = (a.wx[0] + a.wy[0]) * wn[R];
+      T lap = cf(0) * wn[R];
 #pragma unroll
       for (int k = 1; k <= R; ++k)
-        lap += a.wx[k] * (rb[l - k] + rb[l + k]) + a.wy[k] * (wn[R - k] + wn[R + k]);
+        lap += cf(k) * (rb[l - k] + rb[l + k]) + cf(R + k) * (wn[R - k] + wn[R + k]);
       const T c2v = a.c2 ? o.c : T(1);
-      v = a.cA * wn[R] + a.cB * o.p + a.cC * (c2v * lap - f1);
+      v = cf(2 * R + 1) * wn[R] + cf(2 * R + 2) * o.p + cf(2 * R + 3) * (c2v * lap - f1);
     }
     if (R == 2 && ey == nyi + 1) v = -w1[2 * R - 2];   // ghost row: reflects row nyi-1
     w1[2 * R] = v;
@@ -306,18 +338,19 @@ __global__ void __launch_bounds__(BX) k_leap2d_x2(LeapArgs<T> a) {
 
     // second step: W^{n+2} on row r
     if (r >= y0 && own) {
-      T lap = (a.wx[0] + a.wy[0]) * w1[R];
+      T lap = cf(0) * w1[R];
 #pragma unroll
       for (int k = 1; k <= R; ++k)
-        lap += a.wx[k] * (r1b[l - k] + r1b[l + k]) + a.wy[k] * (w1[R - k] + w1[R + k]);
-      const T v2 = a.cA * w1[R] + a.cB * wn[0] + a.cC * (cw[0] * lap - fw[0]);
+        lap += cf(k) * (r1b[l - k] + r1b[l + k]) + cf(R + k) * (w1[R - k] + w1[R + k]);
+      const T v2 = cf(2 * R + 1) * w1[R] + cf(2 * R + 2) * wn[0] +
+                   cf(2 * R + 3) * (cw[0] * lap - fw[0]);
       const long long idx = (long long)r * py + e;
       a.w1[idx] = w1[R];
       a.w2[idx] = v2;
       const double d1 = (double)w1[R], d2 = (double)v2;
 #pragma unroll
       for (int j = 0; j < QM; ++j)
-        if (j < a.nq) a.q[a.qm[j] * fs + idx] = (o.q[j] + a.kk[0][j] * d1) + a.kk[1][j] * d2;
+        if (j < a.nq) a.q[a.qm[j] * fs + idx] = (o.q[j] + kf(0, j) * d1) + kf(1, j) * d2;
     }
   };
 
@@ -680,6 +713,10 @@ LaunchShape default_leap_shape(const Geom& g, int steps) {
   // longer chunks leave a 1023^2 grid too few blocks (measured: 8 is best)
   const long long lo = steps >= 3 ? 8 : 4;
   ls.chunk = (int)std::min<long long>(std::max<long long>(ch, lo), 64);
+  // four steps: 8 rows, the unrolled march, on every size (ms per
+  // application with chunk 8 / the rule above: 2049^2 194 / 223, 4097^2
+  // 1844 / 1888)
+  if (steps == 4) ls.chunk = 8;
   return ls;
 }
 

@@ -180,8 +180,10 @@ def test_two_step_gmres_matches_general_kernel():
 
 
 # three and four steps per pass (forcing-free passes): bx 128 or 256; chunks
-# below, at and above the 2 (KS - 1) R recomputed rows, one chunk for all rows
-SHAPES_K = [(128, 1, 1), (128, 1, 5), (128, 1, 16), (256, 1, 7), (256, 1, 64), (128, 1, 1000)]
+# below, at and above the 2 (KS - 1) R recomputed rows, one chunk for all rows;
+# bx 128 with 8 rows is the unrolled march (ragged last chunk on both grids)
+SHAPES_K = [(128, 1, 1), (128, 1, 5), (128, 1, 8), (128, 1, 16), (256, 1, 7), (256, 1, 64),
+            (128, 1, 1000)]
 
 
 @pytest.mark.parametrize("spp", [3, 4])
