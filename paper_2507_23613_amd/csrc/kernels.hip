@@ -662,11 +662,15 @@ __global__ void __launch_bounds__(256) k_multidot(const double* __restrict__ X, 
   const long long start = (long long)blockIdx.x * 256 + threadIdx.x;
   for (int k0 = 0; k0 < K; k0 += 8) {
     double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    // vectors past K re-read the last one (same addresses, unused sums):
+    // every load is unconditional, so none waits behind a branch
+    const double* xs[8];
+#pragma unroll
+    for (int kk = 0; kk < 8; ++kk) xs[kk] = X + (long long)min(k0 + kk, K - 1) * ldx;
     for (long long p = start; p < n; p += stride) {
       const double yv = y[p];
 #pragma unroll
-      for (int kk = 0; kk < 8; ++kk)
-        if (k0 + kk < K) acc[kk] += X[(k0 + kk) * ldx + p] * yv;
+      for (int kk = 0; kk < 8; ++kk) acc[kk] += xs[kk][p] * yv;
     }
 #pragma unroll
     for (int kk = 0; kk < 8; ++kk) {
