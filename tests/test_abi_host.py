@@ -272,3 +272,24 @@ def test_option_and_launch_shape_validation():
         with pytest.raises(L.MfwhError):
             L.mfwh_set_launch_shape(*bad)
     L.mfwh_set_launch_shape(0)
+
+
+def test_product_path_does_not_use_the_oracle():
+    """The package and its HIP sources never import or include the oracle,
+    and importing the package (binding, problem set-up, autotuner, warm
+    start) loads no module of it."""
+    pkg = os.path.join(ROOT, "paper_2507_23613_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for fn in files:
+            if fn.endswith((".py", ".hip", ".cpp", ".h")):
+                txt = open(os.path.join(dirpath, fn)).read()
+                assert not re.search(r"^\s*(from\s+oracle\b|import\s+oracle\b)", txt, re.M), fn
+                assert "oracle/" not in txt, fn
+    import subprocess
+    import sys
+    code = ("import sys; sys.path.insert(0, %r); import paper_2507_23613_amd; "
+            "from paper_2507_23613_amd import _lib, problem, autotune, warmstart, inputs; "
+            "bad = [m for m in sys.modules if m == 'oracle' or m.startswith('oracle.')]; "
+            "print(bad); sys.exit(1 if bad else 0)") % ROOT
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stdout + r.stderr
