@@ -364,9 +364,12 @@ int mfwh_stats_read(long long* launches, double* total_ms, double* total_bytes);
  * streamlined 2D kernels take 64, 128 or 256), by threads along y (3D: 4, 8
  * or 2 with bx 64/64/128; 8 with bx 32), chunk rows (2D) or planes (3D)
  * marched per block.  In 3D a shape with by = 16 (bx 64 or 32) sets only the
- * two-step kernel; 64 x 8 sets every kernel with order 2 (the two-step kernel
- * then owns 60 x 4 columns per block); any other shape sets the one-step
- * kernels (and the two-step kernel keeps its default).  bx = 0 restores the
+ * multi-step kernels (two and three steps per launch); 64 x 8 sets every
+ * kernel with order 2 except the three-step one (the two-step kernel then
+ * owns 60 x 4 columns per block, and three steps per pass fall back to two);
+ * any other shape sets the one-step kernels (and the multi-step kernels keep
+ * their defaults).  The three- and four-step 2D kernels run an unrolled
+ * march when bx = 128 and chunk = 8 (their default).  bx = 0 restores the
  * built-in heuristics. */
 int mfwh_set_launch_shape(int bx, int by, int chunk);
 
