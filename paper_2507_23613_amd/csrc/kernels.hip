@@ -653,31 +653,44 @@ int blas_blocks(long long n) {
 }
 
 // partial[k*nb + b] = sum over the block's grid-stride elements of X_k . y
+// for the G vectors X_k0 .. X_k0+G-1: G unconditional loads per element, so
+// none waits behind a branch
+template <int G>
+__device__ __forceinline__ void multidot_group(const double* __restrict__ X, long long ldx,
+                                               int k0, const double* __restrict__ y, long long n,
+                                               double* __restrict__ partial, double* sh) {
+  const int nb = gridDim.x;
+  const long long stride = (long long)nb * 256;
+  double acc[G];
+#pragma unroll
+  for (int kk = 0; kk < G; ++kk) acc[kk] = 0.0;
+  const double* __restrict__ xs = X + (long long)k0 * ldx;
+  for (long long p = (long long)blockIdx.x * 256 + threadIdx.x; p < n; p += stride) {
+    const double yv = y[p];
+#pragma unroll
+    for (int kk = 0; kk < G; ++kk) acc[kk] += xs[kk * ldx + p] * yv;
+  }
+#pragma unroll
+  for (int kk = 0; kk < G; ++kk) {
+    const double s = block_sum<256>(acc[kk], sh);
+    if (threadIdx.x == 0) partial[(long long)(k0 + kk) * nb + blockIdx.x] = s;
+  }
+}
+
 __global__ void __launch_bounds__(256) k_multidot(const double* __restrict__ X, long long ldx,
                                                   int K, const double* __restrict__ y,
                                                   long long n, double* __restrict__ partial) {
   __shared__ double sh[4];
-  const int nb = gridDim.x;
-  const long long stride = (long long)nb * 256;
-  const long long start = (long long)blockIdx.x * 256 + threadIdx.x;
   for (int k0 = 0; k0 < K; k0 += 8) {
-    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    // vectors past K re-read the last one (same addresses, unused sums):
-    // every load is unconditional, so none waits behind a branch
-    const double* xs[8];
-#pragma unroll
-    for (int kk = 0; kk < 8; ++kk) xs[kk] = X + (long long)min(k0 + kk, K - 1) * ldx;
-    for (long long p = start; p < n; p += stride) {
-      const double yv = y[p];
-#pragma unroll
-      for (int kk = 0; kk < 8; ++kk) acc[kk] += xs[kk][p] * yv;
-    }
-#pragma unroll
-    for (int kk = 0; kk < 8; ++kk) {
-      if (k0 + kk < K) {
-        const double s = block_sum<256>(acc[kk], sh);
-        if (threadIdx.x == 0) partial[(long long)(k0 + kk) * nb + blockIdx.x] = s;
-      }
+    switch (min(8, K - k0)) {   // uniform: the group size of this pass
+      case 8: multidot_group<8>(X, ldx, k0, y, n, partial, sh); break;
+      case 7: multidot_group<7>(X, ldx, k0, y, n, partial, sh); break;
+      case 6: multidot_group<6>(X, ldx, k0, y, n, partial, sh); break;
+      case 5: multidot_group<5>(X, ldx, k0, y, n, partial, sh); break;
+      case 4: multidot_group<4>(X, ldx, k0, y, n, partial, sh); break;
+      case 3: multidot_group<3>(X, ldx, k0, y, n, partial, sh); break;
+      case 2: multidot_group<2>(X, ldx, k0, y, n, partial, sh); break;
+      default: multidot_group<1>(X, ldx, k0, y, n, partial, sh); break;
     }
   }
 }
