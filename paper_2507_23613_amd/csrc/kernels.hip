@@ -117,7 +117,9 @@ __global__ void __launch_bounds__(256) k_step1d(StepArgs<T> a) {
 // -------------------------------------------------------------------------
 // 2D: y-march, register window in y, LDS row exchange in x
 // -------------------------------------------------------------------------
-template <typename T, int R, int BX>
+// REFL: the grid may have Neumann / Robin faces (a.refl); without it the
+// face rules reduce to the Dirichlet ones at compile time
+template <typename T, int R, int BX, bool REFL>
 __device__ __forceinline__ void body2d(const StepArgs<T>& a, int lb, T (*row)[BX + 2 * R]) {
   const int bx = lb / a.nchunk;
   const int by = lb - bx * a.nchunk;
@@ -132,8 +134,8 @@ __device__ __forceinline__ void body2d(const StepArgs<T>& a, int lb, T (*row)[BX
   const T* __restrict__ wc = a.wc;
   auto col = [&](int k) { return wc[(long long)k * py + ic]; };
 
-  const int xl = a.refl & 1, xh = (a.refl >> 1) & 1, yl = (a.refl >> 2) & 1,
-            yh = (a.refl >> 3) & 1;
+  const int rf = REFL ? a.refl : 0;
+  const int xl = rf & 1, xh = (rf >> 1) & 1, yl = (rf >> 2) & 1, yh = (rf >> 3) & 1;
   T w[2 * R + 1];
 #pragma unroll
   for (int k = 0; k < 2 * R; ++k)
@@ -164,18 +166,18 @@ __device__ __forceinline__ void body2d(const StepArgs<T>& a, int lb, T (*row)[BX
   }
 }
 
-template <typename T, int R, int BX>
+template <typename T, int R, int BX, bool REFL>
 __global__ void __launch_bounds__(BX) k_step2d(StepArgs<T> a) {
   __shared__ T row[2][BX + 2 * R];
   const int lb = xcd_remap(blockIdx.x, gridDim.x);
   if (lb >= a.nblocks) return;
-  body2d<T, R, BX>(a, lb, row);
+  body2d<T, R, BX, REFL>(a, lb, row);
 }
 
 // -------------------------------------------------------------------------
 // 3D: z-march (2.5D), register window in z, LDS plane tile for x/y
 // -------------------------------------------------------------------------
-template <typename T, int R, int BX, int BY>
+template <typename T, int R, int BX, int BY, bool REFL>
 __device__ __forceinline__ void body3d(const StepArgs<T>& a, int lb,
                                        T (*tile)[BY + 2 * R][BX + 2 * R]) {
   const int cz = lb % a.nchunk;
@@ -195,7 +197,7 @@ __device__ __forceinline__ void body3d(const StepArgs<T>& a, int lb,
   const long long colbase = (long long)jc * py + ic;
   auto zcol = [&](int k) { return wc[(long long)k * pz + colbase]; };
 
-  const int rf = a.refl;
+  const int rf = REFL ? a.refl : 0;
   T w[2 * R + 1];
 #pragma unroll
   for (int k = 0; k < 2 * R; ++k)
@@ -247,12 +249,12 @@ __device__ __forceinline__ void body3d(const StepArgs<T>& a, int lb,
   }
 }
 
-template <typename T, int R, int BX, int BY>
+template <typename T, int R, int BX, int BY, bool REFL>
 __global__ void __launch_bounds__(BX * BY) k_step3d(StepArgs<T> a) {
   __shared__ T tile[2][BY + 2 * R][BX + 2 * R];
   const int lb = xcd_remap(blockIdx.x, gridDim.x);
   if (lb >= a.nblocks) return;
-  body3d<T, R, BX, BY>(a, lb, tile);
+  body3d<T, R, BX, BY, REFL>(a, lb, tile);
 }
 
 // -------------------------------------------------------------------------
@@ -301,9 +303,9 @@ __global__ void __launch_bounds__(BX * BY) k_step_batched(BatchArgs<T> b) {
   }
   a.mask = mask;
   if constexpr (DIM == 2) {
-    body2d<T, R, BX>(a, lb - P.tile0, reinterpret_cast<T(*)[BX + 2 * R]>(smem));
+    body2d<T, R, BX, false>(a, lb - P.tile0, reinterpret_cast<T(*)[BX + 2 * R]>(smem));
   } else {
-    body3d<T, R, BX, BY>(a, lb - P.tile0,
+    body3d<T, R, BX, BY, false>(a, lb - P.tile0,
                          reinterpret_cast<T(*)[BY + 2 * R][BX + 2 * R]>(smem));
   }
 }
@@ -323,9 +325,18 @@ hipError_t launch_step_r(StepArgs<T> a, const LaunchShape& ls, hipStream_t s) {
     a.nblocks = a.ntx * a.nchunk;
     const int grid = pad8(a.nblocks);
     switch (ls.bx) {
-      case 64: k_step2d<T, R, 64><<<grid, 64, 0, s>>>(a); break;
-      case 128: k_step2d<T, R, 128><<<grid, 128, 0, s>>>(a); break;
-      case 256: k_step2d<T, R, 256><<<grid, 256, 0, s>>>(a); break;
+      case 64:
+        if (a.refl) k_step2d<T, R, 64, true><<<grid, 64, 0, s>>>(a);
+        else k_step2d<T, R, 64, false><<<grid, 64, 0, s>>>(a);
+        break;
+      case 128:
+        if (a.refl) k_step2d<T, R, 128, true><<<grid, 128, 0, s>>>(a);
+        else k_step2d<T, R, 128, false><<<grid, 128, 0, s>>>(a);
+        break;
+      case 256:
+        if (a.refl) k_step2d<T, R, 256, true><<<grid, 256, 0, s>>>(a);
+        else k_step2d<T, R, 256, false><<<grid, 256, 0, s>>>(a);
+        break;
       default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -336,11 +347,22 @@ hipError_t launch_step_r(StepArgs<T> a, const LaunchShape& ls, hipStream_t s) {
   a.nty = (g.nyi + ls.by - 1) / ls.by;
   a.nblocks = a.ntx * a.nty * a.nchunk;
   const int grid = pad8(a.nblocks);
-  if (ls.bx == 64 && ls.by == 4) k_step3d<T, R, 64, 4><<<grid, dim3(64, 4), 0, s>>>(a);
-  else if (ls.bx == 64 && ls.by == 8) k_step3d<T, R, 64, 8><<<grid, dim3(64, 8), 0, s>>>(a);
-  else if (ls.bx == 128 && ls.by == 2) k_step3d<T, R, 128, 2><<<grid, dim3(128, 2), 0, s>>>(a);
-  else if (ls.bx == 32 && ls.by == 8) k_step3d<T, R, 32, 8><<<grid, dim3(32, 8), 0, s>>>(a);
-  else return hipErrorInvalidValue;
+  const bool rf = a.refl != 0;
+  if (ls.bx == 64 && ls.by == 4) {
+    if (rf) k_step3d<T, R, 64, 4, true><<<grid, dim3(64, 4), 0, s>>>(a);
+    else k_step3d<T, R, 64, 4, false><<<grid, dim3(64, 4), 0, s>>>(a);
+  } else if (ls.bx == 64 && ls.by == 8) {
+    if (rf) k_step3d<T, R, 64, 8, true><<<grid, dim3(64, 8), 0, s>>>(a);
+    else k_step3d<T, R, 64, 8, false><<<grid, dim3(64, 8), 0, s>>>(a);
+  } else if (ls.bx == 128 && ls.by == 2) {
+    if (rf) k_step3d<T, R, 128, 2, true><<<grid, dim3(128, 2), 0, s>>>(a);
+    else k_step3d<T, R, 128, 2, false><<<grid, dim3(128, 2), 0, s>>>(a);
+  } else if (ls.bx == 32 && ls.by == 8) {
+    if (rf) k_step3d<T, R, 32, 8, true><<<grid, dim3(32, 8), 0, s>>>(a);
+    else k_step3d<T, R, 32, 8, false><<<grid, dim3(32, 8), 0, s>>>(a);
+  } else {
+    return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
