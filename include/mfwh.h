@@ -239,7 +239,11 @@ int mfwh_apply(const mfwh_grid* g, const mfwh_time* t, const double* f, const do
 /* Fixed-point iteration v <- W_h(v) (Algorithm 1) starting from the given v
  * (device [nf][grid], updated in place).  res_hist (host, may be NULL) gets
  * r^(k) of eq. residual for k = 1..iterations.  Stops when r^(k) <= tol *
- * r^(1) or after max_iter iterations; info->rel_residual = r^(last)/r^(1). */
+ * r^(1) or after max_iter iterations; info->rel_residual = r^(last)/r^(1).
+ * On 2D and 3D grids, when ws_bytes >= mfwh_workspace_bytes(g, t, 1), the map
+ * is evaluated as W_h(v) = S v + b (Section 7): b = W_h(0) once, then one
+ * forcing-free application per iteration (info->applies = iterations + 1);
+ * otherwise each iteration is one application with forcing. */
 int mfwh_solve_fixed_point(const mfwh_grid* g, const mfwh_time* t, const double* f, double* v,
                            const mfwh_solve_opts* opts, double* res_hist, mfwh_solve_info* info,
                            void* ws, size_t ws_bytes, void* stream);

@@ -1396,23 +1396,36 @@ int mfwh_apply(const mfwh_grid* g, const mfwh_time* t, const double* f, const do
 int mfwh_solve_fixed_point(const mfwh_grid* g, const mfwh_time* t, const double* f, double* v,
                            const mfwh_solve_opts* opts, double* res_hist, mfwh_solve_info* info,
                            void* ws, size_t ws_bytes, void* stream) {
+  // The map is affine, W_h(v) = S v + b with b = W_h(0) (Section 7).  In 2D
+  // and 3D, when the workspace has room for the GMRES(1) layout, b is computed
+  // once and every iteration applies S, forcing-free, which runs the
+  // multi-step kernels; otherwise (1D, smaller workspace) every iteration is
+  // one forced application.
+  const bool affine = g && t && g->dim >= 2 && ws_bytes >= mfwh_workspace_bytes(g, t, 1);
   Problem pr;
-  CHK(setup(pr, g, t, 0, ws, ws_bytes, stream));
+  CHK(setup(pr, g, t, affine ? 1 : 0, ws, ws_bytes, stream));
   if (!v || !f) return fail(MFWH_EINVAL, "null array");
   mfwh_solve_opts o;
   fill_opts(opts, &o);
   pr.graphs = g_graphs;
   CHK(prepare(pr, f));
-  const ExtLayout al = abi_layout(g);
+  const ExtLayout al = abi_layout(g), il = int_layout(pr.G);
   HIPCHK(launch_boundary_fill(g->dim, g->n, t->nf, dirichlet_faces(g), g->g, v, pr.s));
+  double* bvec = nullptr;
+  if (affine) {
+    bvec = pr.W.vec;                       // b = W_h(0), interior layout
+    Out ob{bvec, il};
+    CHK(apply_any(pr, pr.fp32, nullptr, il, true, ob));
+  }
   const double denom = (double)t->nf * (double)pr.G.npts();
   double r1 = 0.0, r = 0.0;
   int k = 0;
   int status = MFWH_NOT_CONVERGED;
   const int nb = (int)std::min<long long>((pr.G.npts() + 255) / 256, kRedBlocks);
   for (k = 1; k <= o.max_iter; ++k) {
-    Out out{v, al, nullptr, {}, 0.0, 1.0, pr.W.partial};
-    CHK(apply_any(pr, pr.fp32, v, al, true, out));
+    Out out = affine ? Out{v, al, bvec, il, 1.0, 1.0, pr.W.partial}
+                     : Out{v, al, nullptr, {}, 0.0, 1.0, pr.W.partial};
+    CHK(apply_any(pr, pr.fp32, v, al, !affine, out));
     HIPCHK(launch_reduce(pr.W.partial, nb, 1, pr.W.scal, pr.s));
     double s2;
     HIPCHK(hipMemcpyAsync(&s2, pr.W.scal, sizeof(double), hipMemcpyDeviceToHost, pr.s));

@@ -578,11 +578,12 @@ __global__ void __launch_bounds__(256) k_finalize(Geom g, int nf, const double* 
 #pragma unroll
       for (int jj = 0; jj < MFWH_MAX_NF; ++jj)
         if (jj < nf) v += B.b[m * MFWH_MAX_NF + jj] * qv[jj];
+      const double nv = xin ? alpha * xin[m * xl.sf + xo] + beta * v : v;
       if (partial) {
-        const double d = v - out[m * ol.sf + oo];
+        const double d = nv - out[m * ol.sf + oo];   // new minus old output
         acc += d * d;
       }
-      out[m * ol.sf + oo] = xin ? alpha * xin[m * xl.sf + xo] + beta * v : v;
+      out[m * ol.sf + oo] = nv;
     }
   }
   if (partial) {
