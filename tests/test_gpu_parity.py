@@ -237,6 +237,28 @@ def test_fixed_point_matches_oracle_config1():
     assert np.allclose(info["history"], rref, rtol=1e-10)
 
 
+@pytest.mark.parametrize("restart", [0, 1], ids=["forced", "affine"])
+@pytest.mark.parametrize("case", [dict(seed=3, shape=(37, 269), nf=3, order=4, varc=True),
+                                  dict(seed=4, shape=(13, 14, 21), nf=2, order=2)],
+                         ids=["2d", "3d"])
+def test_fixed_point_forced_and_affine_forms(case, restart):
+    """In 2D and 3D the fixed-point iteration runs as S v + b when the
+    workspace has room (restart >= 1), else as one forced application per
+    iteration: both match the oracle's Algorithm 1 iterates and residuals.
+    Bar: the single-application bar (1e-12, scaled by cond(B) / 10) once per
+    iteration, since each application adds its rounding to an iterate that
+    the contractive map carries forward."""
+    w = inputs.small(**case)
+    gp = _gp(w, restart=restart)
+    prob, pl = workload.setup(w)
+    k = 6
+    v, info = gp.fixed_point(max_iter=k)
+    Vref, rref = omf.fixed_point(prob, pl, w["f"], k)
+    assert info["iterations"] == k and info["applies"] == k + restart
+    assert rel(v.cpu().numpy(), Vref) < k * 1e-12 * max(1.0, np.linalg.cond(pl.B) / 10)
+    assert np.allclose(info["history"], rref, rtol=1e-10)
+
+
 def test_fixed_point_config1_100_iterations():
     """The 1D workload's 100 plain fixed-point iterations: the history follows
     the oracle's, the iteration contracts at the asymptotic convergence rate
