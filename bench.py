@@ -259,8 +259,8 @@ def implicit_bench(args):
 # (its 8-accumulator launches; FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0,
 # profiles/k_leap3d_x3_fp32_3d-n256-nf8.md), valid only for
 # the leap3d.hip source it was measured on.
-TRAFFIC3 = {"leap3d_sha256_16": "659fb359fdba3a7b",
-            "bytes": 982937.0 * 1024 * 2.0 + 1212487.6 * 1024 * 1.0}
+TRAFFIC3 = {"leap3d_sha256_16": "633db7e588afc68c",
+            "bytes": 982943.3 * 1024 * 2.0 + 1212496.8 * 1024 * 1.0}
 
 
 def roofline_3d():

@@ -627,8 +627,11 @@ LaunchShape default_leap3d_shape(const Geom& g, int steps, int order) {
   long long ch = tiles * (ls.bx * ls.by / 64) * g.nzi / target_waves;
   ls.chunk = (int)std::min<long long>(std::max<long long>(ch, steps >= 2 ? 8 : 4), 64);
   // three steps: 16 planes (256^3: 0.259 ms per step against 0.269 for 32
-  // and 0.282 for 64; the 4 recomputed planes per chunk buy more blocks)
-  if (steps == 3) ls.chunk = 16;
+  // and 0.282 for 64; the 4 recomputed planes per chunk buy more blocks), or
+  // 8 where 16-plane chunks leave fewer than two blocks per CU (ms per
+  // application with 16 / 8 planes: 97^3 21.2 / 16.5, 129^3 59.5 / 55.5,
+  // 193^3 314 / 329)
+  if (steps == 3) ls.chunk = tiles * ((g.nzi + 15) / 16) >= 512 ? 16 : 8;
   return ls;
 }
 
