@@ -411,7 +411,7 @@ def main():
                     help="apply mode: the 2D 1025^2 workload (float64) or the 3D 256^3 "
                          "workload (float32 stencil, variable c, 8 frequencies)")
     ap.add_argument("--spp", type=int, default=-1, choices=[-1, 0, 1, 2, 3, 4],
-                    help="step kernel: -1 the library's choice (2D 4, 3D 3), 0 general, "
+                    help="step kernel: -1 the library's choice (2D 3 or 4, 3D 3), 0 general, "
                          "1..4 streamlined steps per launch (3D: at most 3)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -455,8 +455,10 @@ def main():
     RESTART = 128
     gp = GpuProblem(w, precision=prec, restart=0 if args.mode == "apply" else RESTART)
     log(f"N_t={gp.nt} dt={gp.dt:.3e} interior={gp.interior_points}")
-    # -1: the library's choice (four steps per pass in 2D, three in 3D)
-    spp, shape = (args.spp if args.spp >= 0 else 4 if len(w["shape"]) == 2 else 3), None
+    # -1: the library's choice (2D: four steps per pass from 10^6 interior
+    # points, else three; 3D: three)
+    auto = (4 if gp.interior_points >= 1000000 else 3) if len(w["shape"]) == 2 else 3
+    spp, shape = (args.spp if args.spp >= 0 else auto), None
     if not args.no_tune and args.mode == "solve":
         from paper_2507_23613_amd import autotune
         (spp, shape), _ = autotune.tune(gp, reps=2, log=log)

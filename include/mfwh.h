@@ -384,7 +384,8 @@ int mfwh_set_launch_shape(int bx, int by, int chunk);
  * While step timing (mfwh_stats_enable) is on, a graph replay is timed as a
  * whole and counted as the number of step launches it holds.
  * MFWH_OPT_STEPS_PER_PASS (default -1 = automatic: four steps per launch on
- * 2D grids, three on 3D grids with order 2, two with order 4): 2D grids:
+ * 2D grids of at least 10^6 interior points, three on smaller ones, three on
+ * 3D grids with order 2, two with order 4): 2D grids:
  * after the first step,
  * 0 runs every step with the general step kernel, 1 with the streamlined 2D
  * kernel one step per launch, 2 with the streamlined kernel two steps per
