@@ -547,7 +547,7 @@ def main():
         del gp32
     roof3 = None
     if not args.no_3d:
-        log("3D 256^3 workload: two-step kernel rate (two applications)")
+        log("3D 256^3 workload: three-step kernel rate (two applications)")
         roof3 = roofline_3d()
         log(f"3D: {roof3}")
     if not args.no_cpu:

@@ -548,7 +548,9 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 
 // -------------------------------------------------------------------------
 // finalize: v'_m = sum_j Binv[m][j] q_j;  out_m = alpha x_m + beta v'_m
-// (x may be null: alpha ignored); optional partial sums of (v'_m - out_m_old)^2
+// (x may be null: alpha ignored); optional partial sums of (out_m_new -
+// out_m_old)^2, the squared change of the output array (with alpha = 0,
+// beta = 1: (v'_m - out_m_old)^2)
 // -------------------------------------------------------------------------
 struct BinvArg {
   double b[MFWH_MAX_NF * MFWH_MAX_NF];

@@ -381,20 +381,42 @@ def test_workspace_errors():
 # ----------------------------------------------------------------------------
 # full-size workloads in the launch configuration the benchmark times
 # ----------------------------------------------------------------------------
-def _short_window(w):
+def _short_window(w, reps=1):
     """Same grid, stencil and dt as the real workload, but frequencies whose
     windows fit in a few steps: omega~_m dt = 2 pi m / N with N = 2 N_f + 2,
-    so frequency m completes exactly m periods in N steps and B is well
-    conditioned.  Lets the oracle follow the full-size field step by step."""
+    so frequency m completes exactly m periods in N steps (reps * m periods
+    in the reps * N steps of the window) and B is the identity up to
+    rounding.  Lets the oracle follow the full-size field step by step."""
     L = _L()
     cmax = 1.0 if w["c"] is None else float(np.max(w["c"]))
     g = L.make_grid(w["shape"], w["lengths"], w["order"])
     _, dt, _ = L.mfwh_plan_time(g, cmax, float(w["omega"][0]), int(w["np"]), float(w["cfl"]))
     nf = len(w["omega"])
-    nsteps = 2 * nf + 2
-    wt = 2 * np.pi * np.arange(1, nf + 1) / nsteps          # omega~ dt
+    period = 2 * nf + 2
+    nsteps = reps * period
+    wt = 2 * np.pi * np.arange(1, nf + 1) / period          # omega~ dt
     omega = 2 * np.sin(wt / 2) / dt                         # invert eq. omegaImplicit
     return dict(w, omega=omega, filter="traditional"), (nsteps * dt, dt, nsteps)
+
+
+def rel_max(a, b):
+    """Largest pointwise error relative to the largest entry of b."""
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+def _step_launches(fn):
+    """Run fn() with every step launch timed; returns (fn's value, number of
+    step-kernel launches it made)."""
+    L = _L()
+    L.mfwh_stats_read()
+    L.mfwh_stats_enable(1, 1)
+    try:
+        out = fn()
+        torch.cuda.synchronize()
+    finally:
+        L.mfwh_stats_enable(0, 1)
+    n, _, _ = L.mfwh_stats_read()
+    return out, n
 
 
 @pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "fp32"])
@@ -411,35 +433,81 @@ def test_config2_full_size_short_window(precision):
     assert rel(out, ref) < (tol64(pl) if precision == 0 else tol32(pl))
 
 
-def test_config2_full_size_helmholtz_fixed_point():
-    """All N_t steps at 1025^2: the discrete Helmholtz solution (DST-I) is
-    mapped to itself (eq. discreteHelmholtz) -- a property at any size."""
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "fp32"])
+def test_config2_full_size_forcing_free_four_step(precision):
+    """1025^2, order 4, N_f = 4, the real dt, forcing-free: the launch
+    configuration of every GMRES application the benchmark times.  With
+    10^6 interior points the automatic choice is four steps per pass; a
+    20-step window runs the first step, four four-step passes (8-row chunks,
+    the last one ragged), a two-step and a one-step tail -- 7 step launches
+    (three steps per pass would make 8, two 11).  Whole field against the
+    oracle's step-by-step leapfrog, relative L2 and largest pointwise error,
+    at the stated bars: 1e-12 (float64) and 1e-5 (float32 stencil)."""
+    from oracle import plan as P
+    L = _L()
+    L.mfwh_set_option(L.MFWH_OPT_STEPS_PER_PASS, L.MFWH_STEPS_AUTO)
+    w, (T, dt, nt) = _short_window(inputs.config2(0), reps=2)
+    gp = _gp(w, precision=precision, time=(T, dt, nt))
+    prob = omf.Problem(w["shape"], w["order"], w["lengths"], w["c"])
+    pl = P.Plan(w["omega"], T, dt)
+    assert np.linalg.cond(pl.B) < 1.0 + 1e-9
+    V = rand_v(w["shape"], 4, 12)
+    out, launches = _step_launches(
+        lambda: gp.apply(torch.as_tensor(V, device="cuda"), False).cpu().numpy())
+    assert launches == 7, launches
+    ref = omf.apply(prob, pl, w["f"], V, False)
+    bar = 1e-12 if precision == 0 else 1e-5
+    e2, emax = rel(out, ref), rel_max(out, ref)
+    print(f"1025^2 four-step forcing-free ({'fp64' if precision == 0 else 'fp32'}): "
+          f"rel L2 {e2:.2e}, max {emax:.2e}")
+    assert e2 < bar and emax < bar
+    for m in range(4):
+        e2m = rel(out[m], ref[m])
+        assert e2m < bar, (m, e2m)
+
+
+@pytest.mark.parametrize("form", ["forced", "affine"])
+def test_config2_full_size_helmholtz_fixed_point(form):
+    """All N_t = 3939 steps at 1025^2: the discrete Helmholtz solution U
+    (DST-I) is mapped to itself (eq. discreteHelmholtz) -- a property at any
+    size.  "forced": one application with forcing (the first step, then
+    two-step passes).  "affine": S U + b with b = W_h(0) (Section 7), where
+    S U is a forcing-free application on the four-step kernel the benchmark
+    times (984 four-step passes)."""
     w = inputs.config2(0)
     gp = _gp(w)
     prob, _ = workload.setup(dict(w, f=None), filt="traditional")
     U = np.stack([fd.helmholtz_dst(w["f"][m], w["omega"][m], prob.h, 4) for m in range(4)])
-    out = gp.apply(torch.as_tensor(U, device="cuda"), True).cpu().numpy()
-    assert rel(out, U) < 1e-9
+    Ut = torch.as_tensor(U, device="cuda")
+    if form == "forced":
+        out = gp.apply(Ut, True).cpu().numpy()
+    else:
+        b = gp.apply(torch.zeros_like(Ut), True)
+        out = (gp.apply(Ut, False) + b).cpu().numpy()
+    e2, emax = rel(out, U), rel_max(out, U)
+    print(f"1025^2 fixed point ({form}): rel L2 {e2:.2e}, max {emax:.2e}")
+    assert e2 < 1e-9 and emax < 1e-9
 
 
 def test_large_grid_4097_helmholtz_fixed_point():
     """A grid 16 times the 2D workload's (4097^2 points, 16.8M unknowns per
-    field, N_t ~ 16k, the autotuned three-step kernel): the DST-I Helmholtz
-    solution is still mapped to itself -- large-index addressing and
-    rounding over long windows."""
+    field, N_t = 15753, beyond the Infinity Cache): the DST-I Helmholtz
+    solution U is still mapped to itself, evaluated as S U + b with b =
+    W_h(0) (Section 7), so that S U runs on the four-step kernel (the
+    automatic choice for this grid; 3938 four-step passes) -- large-index
+    addressing and rounding over long windows."""
     L = _L()
+    L.mfwh_set_option(L.MFWH_OPT_STEPS_PER_PASS, L.MFWH_STEPS_AUTO)
     w = inputs.config2(0, n=4097)
-    try:
-        L.mfwh_set_option(L.MFWH_OPT_STEPS_PER_PASS, 3)
-        gp = _gp(w, restart=0)
-        prob, _ = workload.setup(dict(w, f=None), filt="traditional")
-        U = np.stack([fd.helmholtz_dst(w["f"][m], w["omega"][m], prob.h, 4) for m in range(4)])
-        out = gp.apply(torch.as_tensor(U, device="cuda"), True).cpu().numpy()
-    finally:
-        L.mfwh_set_option(L.MFWH_OPT_STEPS_PER_PASS, L.MFWH_STEPS_AUTO)
-    e = rel(out, U)
-    print(f"4097^2 fixed point: N_t={gp.nt} rel err {e:.2e}")
-    assert e < 1e-9
+    gp = _gp(w, restart=0)
+    prob, _ = workload.setup(dict(w, f=None), filt="traditional")
+    U = np.stack([fd.helmholtz_dst(w["f"][m], w["omega"][m], prob.h, 4) for m in range(4)])
+    Ut = torch.as_tensor(U, device="cuda")
+    b = gp.apply(torch.zeros_like(Ut), True)
+    out = (gp.apply(Ut, False) + b).cpu().numpy()
+    e2, emax = rel(out, U), rel_max(out, U)
+    print(f"4097^2 fixed point: N_t={gp.nt} rel L2 {e2:.2e}, max {emax:.2e}")
+    assert e2 < 1e-9 and emax < 1e-9
 
 
 def test_config2_full_size_gmres_matches_dst():
@@ -468,6 +536,41 @@ def test_config3_full_size_short_window(precision):
     torch.cuda.empty_cache()
     ref = omf.apply(prob, pl, w["f"], V, True)
     assert rel(out, ref) < (tol64(pl) if precision == 0 else tol32(pl))
+
+
+@pytest.mark.parametrize("precision", [1, 0], ids=["fp32", "fp64"])
+def test_config3_full_size_forcing_free_three_step(precision):
+    """The 3D workload exactly as the benchmark runs it -- 256^3, order 2,
+    variable c, N_f = 8, the real dt, float32 stencil (and float64) --
+    forcing-free: three steps per pass (the automatic choice with order 2;
+    64x16 blocks, 16-plane chunks).  An 18-step window runs the first step,
+    five three-step passes and a two-step tail: 7 step launches (two steps
+    per pass would make 10).  Whole field against the oracle, relative L2
+    and largest pointwise error, at 1e-12 (float64) and 1e-5 (float32)."""
+    from oracle import plan as P
+    L = _L()
+    L.mfwh_set_option(L.MFWH_OPT_STEPS_PER_PASS, L.MFWH_STEPS_AUTO)
+    w, (T, dt, nt) = _short_window(inputs.config3(0))
+    assert nt == 18
+    gp = _gp(w, precision=precision, time=(T, dt, nt), restart=0)
+    prob = omf.Problem(w["shape"], w["order"], w["lengths"], w["c"])
+    pl = P.Plan(w["omega"], T, dt)
+    assert np.linalg.cond(pl.B) < 1.0 + 1e-9
+    V = rand_v(w["shape"], 8, 13)
+    out, launches = _step_launches(
+        lambda: gp.apply(torch.as_tensor(V, device="cuda"), False).cpu().numpy())
+    del gp
+    torch.cuda.empty_cache()
+    assert launches == 7, launches
+    ref = omf.apply(prob, pl, w["f"], V, False)
+    bar = 1e-12 if precision == 0 else 1e-5
+    e2, emax = rel(out, ref), rel_max(out, ref)
+    print(f"256^3 three-step forcing-free ({'fp64' if precision == 0 else 'fp32'}): "
+          f"rel L2 {e2:.2e}, max {emax:.2e}")
+    assert e2 < bar and emax < bar
+    for m in range(8):
+        e2m = rel(out[m], ref[m])
+        assert e2m < bar, (m, e2m)
 
 
 def test_config3_full_size_eigenmode_transfer():

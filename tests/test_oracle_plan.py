@@ -220,3 +220,49 @@ def test_plan_rejects_bad_input():
         P.Plan([5.0, 5.0], 1.0, 0.01)
     with pytest.raises(ValueError):
         P.Plan([5.0], 1.0, 0.0123)      # not an integer number of steps
+
+
+def _config3_frequencies():
+    """The 3D workload's eight frequencies (the generator's first draw) and its
+    explicit time grid (256^3 points, order 2, c <= 1.3, CFL 0.5)."""
+    from paper_2507_23613_amd import inputs
+    om, np_ = inputs.draw_frequencies(np.random.default_rng(0), 8, 15.0, 40.0)
+    h = 1.0 / 255
+    Tf, dt, nt = P.time_step_explicit(om[0], np_, (h, h, h), 3, 2, 1.3, 0.5)
+    return om, np_, Tf, dt, nt
+
+
+def test_optimiser_truncated_least_squares_branch():
+    """The rcond > 0 branch of the optimiser (minimum-norm least squares with
+    small singular values dropped) on the 3D workload's eight close
+    frequencies (N_p = 9), where plain least squares gives parameters ~1e6.
+    Pinned by what holds for ANY x~_a: the constraints of eqs. coneT and
+    ctwoT (sum_m beta~_m(omega~_j) = 1 and mu_d'(omega~_j) = 0, evaluated
+    through the Plan's own quadrature, not the optimiser's matrices); and by
+    the two monotonicity properties of truncated-SVD least squares: keeping
+    fewer singular values never lowers the objective (the midpoint-rule
+    integral of mu_d^2 over Lambda, Algorithm 2) and never raises the norm
+    of x~_a.  Also |p~| = O(1) and |mu_d| <= 1 on Lambda at rcond = 1e-2."""
+    om, np_, Tf, dt, nt = _config3_frequencies()
+    om_t = P.omega_tilde(om, dt)
+    J, na = [], []
+    for rc in (1e-1, 1e-2, 1e-3, 0.0):
+        p, lmax, nlam = P.optimise_filter_discrete(om_t, np_, nt, rcond=rc)
+        pl = P.Plan(om, Tf, dt, params=p)
+        # eq. coneT: unit column sums of B~ (then gamma = 1 and mu_d = sum beta~)
+        assert np.allclose(pl.B.sum(axis=0), 1.0, atol=1e-9), rc
+        eps = 1e-5
+        d = (pl.mu_d(om_t + eps) - pl.mu_d(om_t - eps)) / (2 * eps)
+        if rc > 0:                           # eq. ctwoT (well conditioned p~)
+            assert np.max(np.abs(d)) < 1e-8 * Tf, (rc, d)
+        lam = (np.arange(1, nlam + 1) - 0.5) * lmax / nlam
+        mu = sum(pl.beta_d(m, lam) for m in range(len(om)))
+        J.append(float(np.sum(mu ** 2)) * lmax / nlam)
+        na.append(float(np.linalg.norm(p[:, 0])))
+        if rc == 1e-2:
+            assert np.max(np.abs(p)) < 10.0
+            assert np.max(np.abs(mu)) <= 1.0 + 1e-8
+            assert np.linalg.cond(pl.B) < 10.0
+    assert all(J[k] >= J[k + 1] - 1e-12 for k in range(3)), J
+    assert all(na[k] <= na[k + 1] + 1e-12 for k in range(3)), na
+    assert na[-1] > 1e5          # plain least squares: the ill-conditioned solution
