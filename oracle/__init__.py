@@ -14,7 +14,9 @@ fd        the discrete operator L_h (order 2/4, Dirichlet), its sparse matrix,
           sparse direct and DST-I Helmholtz solves (Section 6, eq.
           discreteHelmholtz).
 mfwh      one MFWH application (Algorithm 1 with the discrete scheme of
-          Section 6), fixed-point iteration and restarted GMRES (Section 7).
+          Section 6), fixed-point iteration and restarted GMRES (Section 7),
+          plain or with deflated restarting.
+krylov    GMRES with deflated restarting (Morgan 2002) on a generic operator.
 checks    error / residual measures of Section 8 and leapfrog energy.
 cnn       FP64 reference for the warm-start convolutional network.
 

@@ -261,3 +261,21 @@ def gmres(prob, plan, f, restart=30, tol=1e-10, max_iter=500, V0=None, g=None):
         for i in range(k):
             x = x + y[i] * Q[i]
     return _unpack(prob, x, nf, b_full), np.array(hist)
+
+
+def gmres_deflated(prob, plan, f, restart=30, deflate=10, tol=1e-10, max_iter=500, V0=None):
+    """GMRES-DR(restart, deflate) on A_h V = b_h (Section 7; the restart keeps
+    approximate eigenvectors of the eigenvalues of A_h nearest zero, see
+    ``oracle/krylov.py``).  Unknowns and stopping as in ``gmres``.  Returns
+    (V, history, applications of S)."""
+    from . import krylov
+    nf = plan.nf
+    b_full = apply(prob, plan, f, np.zeros((nf,) + prob.shape), True)
+    b = _pack(prob, b_full)
+
+    def A(x):
+        return x - _pack(prob, apply(prob, plan, f, _unpack(prob, x, nf), False))
+
+    x0 = None if V0 is None else _pack(prob, V0)
+    x, hist, napply = krylov.gmres_dr(A, b, restart, deflate, tol, max_iter, x0)
+    return _unpack(prob, x, nf, b_full), hist, napply
