@@ -46,6 +46,7 @@ extern "C" {
 
 #define MFWH_MAX_NF 8          /* maximum number of frequencies per problem   */
 #define MFWH_MAX_RESTART 512   /* maximum GMRES restart length                */
+#define MFWH_MAX_DEFLATE 62    /* maximum harmonic Ritz vectors kept by GMRES-DR */
 
 typedef enum {
   MFWH_OK = 0,
@@ -146,7 +147,22 @@ typedef struct mfwh_solve_opts {
                             alpha = <A v0, b> / <A v0, A v0>, the scaling that
                             minimises ||b - alpha A v0|| (never worse than the
                             zero start); costs no extra application          [0]   */
+  int deflate;           /* GMRES with deflated restarting, GMRES-DR(restart, k)
+                            (R. B. Morgan, SIAM J. Sci. Comput. 24 (2002)): at
+                            each restart keep the harmonic Ritz vectors of the
+                            k eigenvalues of A_h of smallest modulus (a complex
+                            pair is never split, so k+1 may be kept) and the
+                            residual as the first k+1 basis vectors of the next
+                            cycle; 0 <= k <= min(MFWH_MAX_DEFLATE, restart-2);
+                            0 = plain restarted GMRES(restart)                 [0] */
+  int inner_max_iter;    /* MFWH_FP32_STENCIL: Arnoldi steps of each inner solve
+                            of iterative refinement at most (<= 0: the remaining
+                            max_iter budget)                                   [0] */
+  int fpi_form;          /* mfwh_solve_fixed_point: MFWH_FPI_AUTO, MFWH_FPI_FORCED
+                            or MFWH_FPI_AFFINE (see there)                      [0] */
 } mfwh_solve_opts;
+
+enum { MFWH_FPI_AUTO = 0, MFWH_FPI_FORCED = 1, MFWH_FPI_AFFINE = 2 };
 
 /* Solver report (host struct filled on return). */
 typedef struct mfwh_solve_info {
@@ -160,6 +176,7 @@ typedef struct mfwh_solve_info {
   double initial_scale;    /* alpha applied by scale_initial (1 otherwise)          */
   long long implicit_solves; /* MFWH_IMPLICIT: step-matrix solves performed          */
   long long mg_cycles;     /* MFWH_IMPLICIT: multigrid V-cycles over those solves    */
+  int deflated_restarts;   /* GMRES-DR restarts that kept harmonic Ritz vectors      */
 } mfwh_solve_info;
 
 /* Description of the last error on the calling thread ("" if none). */
@@ -217,6 +234,25 @@ int mfwh_optimize_filter(int nf, const double* omega_in, int np, int nt, int nde
                          double cdelta, double rcond, double* filt_out, double* lambda_max,
                          int* n_lambda);
 
+/* The host step of a deflated GMRES restart (the GPU solver calls the same
+ * code; exposed for inspection, no GPU needed).  From the (m+1) x m upper
+ * Hessenberg matrix of an Arnoldi cycle, A V_m = V_{m+1} Hbar (Section 7's
+ * Krylov iteration on A_h), and the coordinates rho (m+1) of its
+ * least-squares residual in V_{m+1}: the harmonic Ritz values theta of
+ * (H_m + h_{m+1,m}^2 H_m^{-T} e_m e_m^T) g = theta g of smallest modulus,
+ * k of them (a complex pair kept whole: at most k+1), and the orthonormal
+ * (m+1) x (kk+1) matrix P whose columns span [[g_1 .. g_kk; 0], rho] (real
+ * and imaginary parts of complex g; the residual's column last).  The next
+ * cycle starts from V_{kk+1} = V_{m+1} P with Hbar_new = P^T Hbar P_kk and
+ * coordinates c_new = P^T rho.
+ *   hbar: host (m+1) x m row-major; rho: host m+1; 1 <= k < m <= MFWH_MAX_RESTART.
+ *   theta: host 2 (k+1) doubles (re, im pairs) or NULL; P: host (m+1) (k+2)
+ *   doubles, row-major with row length kk+1; hnew: host (k+2) (k+1) doubles,
+ *   row-major (kk+1) x kk; cnew: host k+2 doubles; kk: host int.
+ * Returns MFWH_ESINGULAR if H_m is singular or the eigenproblem fails. */
+int mfwh_deflation_step(int m, const double* hbar, const double* rho, int k, double* theta,
+                        double* P, double* hnew, double* cnew, int* kk);
+
 /* ------------------------------------------------------------------------- *
  * GPU entry points
  * ------------------------------------------------------------------------- */
@@ -240,10 +276,16 @@ int mfwh_apply(const mfwh_grid* g, const mfwh_time* t, const double* f, const do
  * (device [nf][grid], updated in place).  res_hist (host, may be NULL) gets
  * r^(k) of eq. residual for k = 1..iterations.  Stops when r^(k) <= tol *
  * r^(1) or after max_iter iterations; info->rel_residual = r^(last)/r^(1).
- * On 2D and 3D grids, when ws_bytes >= mfwh_workspace_bytes(g, t, 1), the map
- * is evaluated as W_h(v) = S v + b (Section 7): b = W_h(0) once, then one
- * forcing-free application per iteration (info->applies = iterations + 1);
- * otherwise each iteration is one application with forcing. */
+ * opts->fpi_form chooses how W_h is evaluated:
+ *   MFWH_FPI_FORCED: every iteration is one application with forcing, as
+ *     Algorithm 1 prints it (info->applies = iterations);
+ *   MFWH_FPI_AFFINE: W_h(v) = S v + b (Section 7): b = W_h(0) once, then one
+ *     forcing-free application per iteration (info->applies = iterations + 1),
+ *     which runs the multi-step kernels; needs a 2D or 3D grid and
+ *     ws_bytes >= mfwh_workspace_bytes(g, t, 1), else MFWH_EINVAL /
+ *     MFWH_EWORKSPACE;
+ *   MFWH_FPI_AUTO (default): the affine form when it is available, else the
+ *     forced form. */
 int mfwh_solve_fixed_point(const mfwh_grid* g, const mfwh_time* t, const double* f, double* v,
                            const mfwh_solve_opts* opts, double* res_hist, mfwh_solve_info* info,
                            void* ws, size_t ws_bytes, void* stream);
@@ -253,6 +295,8 @@ int mfwh_solve_fixed_point(const mfwh_grid* g, const mfwh_time* t, const double*
  * Gram-Schmidt with re-orthogonalisation in float64, initial guess v (device
  * [nf][grid], zero allowed), solution written to v.  Stops when
  * ||b - A v||_2 <= tol ||b||_2 (true residual, float64).
+ * opts->deflate > 0 keeps approximate eigenvectors across restarts
+ * (GMRES-DR, see mfwh_solve_opts).
  * With MFWH_FP32_STENCIL the inner Krylov solves use float32-stencil
  * applications on corrections and an outer float64 residual drives iterative
  * refinement.  res_hist (host, may be NULL, max_iter entries) gets the

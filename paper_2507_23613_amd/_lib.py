@@ -24,6 +24,8 @@ MFWH_FP64 = 0
 MFWH_FP32_STENCIL = 1
 MFWH_MAX_NF = 8
 MFWH_MAX_RESTART = 512
+MFWH_MAX_DEFLATE = 62
+MFWH_FPI_AUTO, MFWH_FPI_FORCED, MFWH_FPI_AFFINE = 0, 1, 2
 STATUS = {0: "MFWH_OK", 1: "MFWH_NOT_CONVERGED", -1: "MFWH_EINVAL", -2: "MFWH_EUNSORTED",
           -3: "MFWH_ECFL", -4: "MFWH_ESINGULAR", -5: "MFWH_ENT", -6: "MFWH_EHIP",
           -7: "MFWH_EWORKSPACE", -8: "MFWH_ENONFINITE",
@@ -51,14 +53,16 @@ class mfwh_time(ctypes.Structure):
 class mfwh_solve_opts(ctypes.Structure):
     _fields_ = [("restart", c_int), ("max_iter", c_int), ("tol", c_double),
                 ("inner_tol", c_double), ("max_outer", c_int), ("zero_fallback", c_int),
-                ("scale_initial", c_int)]
+                ("scale_initial", c_int), ("deflate", c_int), ("inner_max_iter", c_int),
+                ("fpi_form", c_int)]
 
 
 class mfwh_solve_info(ctypes.Structure):
     _fields_ = [("iterations", c_int), ("applies", c_int), ("outer", c_int),
                 ("rel_residual", c_double), ("point_steps", c_longlong), ("fell_back", c_int),
                 ("initial_rel_residual", c_double), ("initial_scale", c_double),
-                ("implicit_solves", c_longlong), ("mg_cycles", c_longlong)]
+                ("implicit_solves", c_longlong), ("mg_cycles", c_longlong),
+                ("deflated_restarts", c_int)]
 
 
 class mfwh_problem(ctypes.Structure):
@@ -85,6 +89,8 @@ def _load():
         "mfwh_filter_adjusted": (c_int, [c_int, P_double, c_double, c_int, P_double]),
         "mfwh_optimize_filter": (c_int, [c_int, P_double, c_int, c_int, c_int, c_double,
                                          c_double, P_double, P_double, P_int]),
+        "mfwh_deflation_step": (c_int, [c_int, P_double, P_double, c_int, P_double, P_double,
+                                        P_double, P_double, P_int]),
         "mfwh_workspace_bytes": (c_size_t, [ctypes.POINTER(mfwh_grid),
                                             ctypes.POINTER(mfwh_time), c_int]),
         "mfwh_apply": (c_int, [ctypes.POINTER(mfwh_grid), ctypes.POINTER(mfwh_time), c_void_p,
@@ -228,12 +234,14 @@ def make_time(omega, T, dt, filt=None, scheme=MFWH_EXPLICIT, imp_tol=0.0, imp_ma
 
 
 def make_opts(restart=30, max_iter=1000, tol=1e-8, inner_tol=1e-5, max_outer=20,
-              zero_fallback=0, scale_initial=0):
+              zero_fallback=0, scale_initial=0, deflate=0, inner_max_iter=0,
+              fpi_form=MFWH_FPI_AUTO):
     o = mfwh_solve_opts()
     o.restart, o.max_iter, o.tol = int(restart), int(max_iter), float(tol)
     o.inner_tol, o.max_outer = float(inner_tol), int(max_outer)
     o.zero_fallback = int(zero_fallback)
     o.scale_initial = int(scale_initial)
+    o.deflate, o.inner_max_iter, o.fpi_form = int(deflate), int(inner_max_iter), int(fpi_form)
     return o
 
 
@@ -290,6 +298,28 @@ def mfwh_optimize_filter(omega_in, np_, nt, ndelta=20, cdelta=2.0, rcond=0.0):
     return out, lmax.value, nlam.value
 
 
+def mfwh_deflation_step(hbar, rho, k):
+    """hbar: (m+1, m) array, rho: (m+1,) -> (theta complex array, P (m+1, kk+1),
+    hnew (kk+1, kk), cnew (kk+1,))."""
+    hb = np.ascontiguousarray(hbar, dtype=np.float64)
+    r = np.ascontiguousarray(rho, dtype=np.float64)
+    m = hb.shape[1]
+    th = np.zeros(2 * (k + 1))
+    P = np.zeros((m + 1) * (k + 2))
+    hn = np.zeros((k + 2) * (k + 1))
+    cn = np.zeros(k + 2)
+    kk = c_int()
+    _check(LIB.mfwh_deflation_step(m, hb.ctypes.data_as(P_double), r.ctypes.data_as(P_double),
+                                   int(k), th.ctypes.data_as(P_double),
+                                   P.ctypes.data_as(P_double), hn.ctypes.data_as(P_double),
+                                   cn.ctypes.data_as(P_double), ctypes.byref(kk)))
+    n = kk.value
+    nth = n if n <= k + 1 else k + 1
+    theta = th[0:2 * nth:2] + 1j * th[1:2 * nth:2]
+    return (theta, P[:(m + 1) * (n + 1)].reshape(m + 1, n + 1),
+            hn[:(n + 1) * n].reshape(n + 1, n), cn[:n + 1].copy())
+
+
 def mfwh_workspace_bytes(grid, time, restart=0):
     return int(LIB.mfwh_workspace_bytes(ctypes.byref(grid), ctypes.byref(time), int(restart)))
 
@@ -313,7 +343,8 @@ def _solve(fn, grid, time, f, v, opts, ws, stream, hist_len):
                 point_steps=info.point_steps, fell_back=bool(info.fell_back),
                 initial_rel_residual=info.initial_rel_residual,
                 initial_scale=info.initial_scale, implicit_solves=info.implicit_solves,
-                mg_cycles=info.mg_cycles, history=hist[:info.iterations].copy())
+                mg_cycles=info.mg_cycles, deflated_restarts=info.deflated_restarts,
+                history=hist[:info.iterations].copy())
 
 
 def mfwh_solve_fixed_point(grid, time, f, v, opts, ws, stream=None):

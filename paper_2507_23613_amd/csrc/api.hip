@@ -11,6 +11,7 @@
 #include <map>
 #include <memory>
 #include <cmath>
+#include <complex>
 #include <cstdio>
 #include <cstring>
 #include <mutex>
@@ -19,6 +20,7 @@
 
 #include "../../include/mfwh.h"
 #include "kernels.h"
+#include "krylov.h"
 #include "plan.h"
 
 namespace mfwh {
@@ -163,6 +165,7 @@ struct Workspace {
   double* partial = nullptr;   // (restart+2) * kRedBlocks doubles
   double* scal = nullptr;      // device scalars: 4 (restart+2) + 16 doubles
   double* vec = nullptr;       // nvec vectors of nf*fs doubles
+  double* defl = nullptr;      // GMRES-DR change of basis, (restart+1) x (MFWH_MAX_DEFLATE+2)
   int nvec = 0;
   int nscal = 0;
   // implicit scheme: multigrid levels (level 0 uses w64c/w64d/... as x and b)
@@ -240,6 +243,7 @@ Workspace carve(const Geom& G, int nf, bool fp32, bool varc, int restart, char* 
   if (restart > 0) {
     w.nvec = restart + 1 + 5;
     w.vec = (double*)take((size_t)w.nvec * fs * nf * 8);
+    w.defl = (double*)take((size_t)(restart + 1) * (MFWH_MAX_DEFLATE + 2) * 8);
   }
   if (mg) {
     w.nlev = nlev;
@@ -964,53 +968,126 @@ int norm2(Vecs& V, const double* x, double* out) {
 // ---------------------------------------------------------------------------
 // restarted GMRES on A x = rhs, A = I - S (S in float64 or float32 stencil),
 // x updated in place.  Vector slots: 0..m basis, m+1 work.
+//
+// kdef > 0: deflated restarting, GMRES-DR(m, kdef) (R. B. Morgan, SIAM J.
+// Sci. Comput. 24 (2002)).  A cycle that ends without convergence keeps the
+// harmonic Ritz vectors of the kdef eigenvalues of smallest modulus and the
+// least-squares residual: the host computes the (m+1) x (kk+1) change of
+// basis P (krylov.cpp), the device rewrites V_{kk+1} = V_{m+1} P in place,
+// and Arnoldi continues from v_{kk+1} with Hbar's leading (kk+1) x kk block
+// P^T Hbar P_kk.  Without deflation, and whenever the estimate meets the
+// tolerance, the cycle ends by recomputing the true residual b - A x.
 // ---------------------------------------------------------------------------
 struct KrylovResult {
   int its = 0;
   double res = 0.0;   // last true residual norm
   bool converged = false;
+  int deflated = 0;   // deflated restarts
+};
+
+// Least squares min |c - Hbar y| by Givens rotations applied column by
+// column: the leading block after a deflated restart is full, later columns
+// are Hessenberg.  Rotations act on rows (i, i+1) and are replayed on every
+// new column.
+struct GivensLS {
+  int m = 0;
+  std::vector<double> R;               // (m+1) x m row-major, rotated Hbar
+  std::vector<double> g;               // rotated c
+  std::vector<int> ri;                 // rotation rows
+  std::vector<double> rc, rs;
+  void reset(int m_, const std::vector<double>& c) {
+    m = m_;
+    R.assign((size_t)(m + 1) * m, 0.0);
+    g = c;
+    ri.clear();
+    rc.clear();
+    rs.clear();
+  }
+  void rotate(int i, double c, double s, int col) {
+    double* a = &R[(size_t)i * m + col];
+    double* b = &R[(size_t)(i + 1) * m + col];
+    const double x = c * *a + s * *b, y = -s * *a + c * *b;
+    *a = x;
+    *b = y;
+  }
+  // add column j (entries rows 0..last of Hbar) and zero it below the diagonal
+  void add_column(const std::vector<double>& Hb, int j, int last) {
+    for (int i = 0; i <= last; ++i) R[(size_t)i * m + j] = Hb[(size_t)i * m + j];
+    for (size_t r = 0; r < ri.size(); ++r) rotate(ri[r], rc[r], rs[r], j);
+    for (int i = last; i > j; --i) {
+      const double a = R[(size_t)(i - 1) * m + j], b = R[(size_t)i * m + j];
+      if (b == 0.0) continue;
+      const double d = std::hypot(a, b);
+      const double c = a / d, s = b / d;
+      rotate(i - 1, c, s, j);
+      R[(size_t)i * m + j] = 0.0;
+      ri.push_back(i - 1);
+      rc.push_back(c);
+      rs.push_back(s);
+      const double x = c * g[i - 1] + s * g[i], y = -s * g[i - 1] + c * g[i];
+      g[i - 1] = x;
+      g[i] = y;
+    }
+  }
+  void solve(int k, std::vector<double>* y) const {
+    y->assign(k, 0.0);
+    for (int i = k - 1; i >= 0; --i) {
+      double s = g[i];
+      for (int c = i + 1; c < k; ++c) s -= R[(size_t)i * m + c] * (*y)[c];
+      const double d = R[(size_t)i * m + i];
+      (*y)[i] = d != 0.0 ? s / d : 0.0;
+    }
+  }
 };
 
 int gmres_core(Vecs& V, bool use32, const double* rhs, double* x, bool xzero, double tol_abs,
-               int m, int max_its, double bnorm, double* hist, int hist_off, KrylovResult* kr) {
+               int m, int kdef, int max_its, double bnorm, double* hist, int hist_off,
+               KrylovResult* kr) {
   Problem& pr = *V.pr;
   const ExtLayout il = int_layout(pr.G);
   double* work = V.vec(m + 1);
-  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+  std::vector<double> Hb((size_t)(m + 1) * m), c(m + 1), y;
   std::vector<double> hh(2 * (m + 1) + 1);
+  GivensLS ls;
   const int rs = m + 2;
   double* dh1 = pr.W.scal;               // device: first CGS pass coefficients
   double* dh2 = pr.W.scal + rs;          // second pass
   double* dnr = pr.W.scal + 2 * rs;      // |w|^2
   double* dy = pr.W.scal + 3 * rs;       // solution coefficients
   int its = 0;
+  int j0 = 0;                            // basis vectors carried into the cycle - 1
+  bool fresh = true;                     // start the cycle from the true residual
   while (true) {
-    double* v0 = V.vec(0);
-    if (xzero) {
-      HIPCHK(hipMemcpyAsync(v0, rhs, V.N * sizeof(double), hipMemcpyDeviceToDevice, pr.s));
-    } else {
-      Out o{v0, il, x, il, 1.0, -1.0, nullptr};   // v0 = x - S x = A x
-      CHK(apply_any(pr, use32, x, il, false, o));
-      HIPCHK(launch_axpby(1.0, rhs, -1.0, v0, V.N, pr.s));   // v0 = rhs - A x
+    if (fresh) {
+      double* v0 = V.vec(0);
+      if (xzero) {
+        HIPCHK(hipMemcpyAsync(v0, rhs, V.N * sizeof(double), hipMemcpyDeviceToDevice, pr.s));
+      } else {
+        Out o{v0, il, x, il, 1.0, -1.0, nullptr};   // v0 = x - S x = A x
+        CHK(apply_any(pr, use32, x, il, false, o));
+        HIPCHK(launch_axpby(1.0, rhs, -1.0, v0, V.N, pr.s));   // v0 = rhs - A x
+      }
+      double beta;
+      CHK(norm2(V, v0, &beta));
+      if (!std::isfinite(beta)) return fail(MFWH_ENONFINITE, "non-finite residual in GMRES");
+      kr->res = beta;
+      if (beta <= tol_abs) { kr->converged = true; break; }
+      if (its >= max_its) break;
+      {
+        double b2 = beta * beta;
+        HIPCHK(hipMemcpyAsync(dnr, &b2, sizeof(double), hipMemcpyHostToDevice, pr.s));
+        HIPCHK(launch_scale_by_rnorm(v0, dnr, v0, V.N, pr.s));
+        HIPCHK(hipStreamSynchronize(pr.s));
+      }
+      std::fill(Hb.begin(), Hb.end(), 0.0);
+      std::fill(c.begin(), c.end(), 0.0);
+      c[0] = beta;
+      j0 = 0;
+      ls.reset(m, c);
     }
-    double beta;
-    CHK(norm2(V, v0, &beta));
-    if (!std::isfinite(beta)) return fail(MFWH_ENONFINITE, "non-finite residual in GMRES");
-    kr->res = beta;
-    if (beta <= tol_abs) { kr->converged = true; break; }
-    if (its >= max_its) break;
-    {
-      double b2 = beta * beta;
-      HIPCHK(hipMemcpyAsync(dnr, &b2, sizeof(double), hipMemcpyHostToDevice, pr.s));
-      HIPCHK(launch_scale_by_rnorm(v0, dnr, v0, V.N, pr.s));
-      HIPCHK(hipStreamSynchronize(pr.s));
-    }
-    std::fill(H.begin(), H.end(), 0.0);
-    std::fill(g.begin(), g.end(), 0.0);
-    g[0] = beta;
-    int k = 0;
-    bool done = false;
-    for (int j = 0; j < m && its < max_its; ++j) {
+    int k = j0;
+    bool stop = false;
+    for (int j = j0; j < m && its < max_its; ++j) {
       double* vj = V.vec(j);
       Out o{work, il, vj, il, 1.0, -1.0, nullptr};
       CHK(apply_any(pr, use32, vj, il, false, o));           // work = A v_j
@@ -1031,43 +1108,59 @@ int gmres_core(Vecs& V, bool use32, const double* rhs, double* x, bool xzero, do
       HIPCHK(hipStreamSynchronize(pr.s));
       const double hnext = std::sqrt(hh[2 * (m + 1)]);
       if (!std::isfinite(hnext)) return fail(MFWH_ENONFINITE, "non-finite Arnoldi vector");
-      for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hh[i] + hh[(m + 1) + i];
-      H[(size_t)(j + 1) * m + j] = hnext;
+      for (int i = 0; i <= j; ++i) Hb[(size_t)i * m + j] = hh[i] + hh[(m + 1) + i];
+      Hb[(size_t)(j + 1) * m + j] = hnext;
       if (hnext > 0.0) HIPCHK(launch_scale_by_rnorm(work, dnr, V.vec(j + 1), V.N, pr.s));
-      // Givens rotations
-      for (int i = 0; i < j; ++i) {
-        const double a0 = H[(size_t)i * m + j], a1 = H[(size_t)(i + 1) * m + j];
-        H[(size_t)i * m + j] = cs[i] * a0 + sn[i] * a1;
-        H[(size_t)(i + 1) * m + j] = -sn[i] * a0 + cs[i] * a1;
-      }
-      const double a0 = H[(size_t)j * m + j], a1 = H[(size_t)(j + 1) * m + j];
-      const double den = std::hypot(a0, a1);
-      cs[j] = den > 0 ? a0 / den : 1.0;
-      sn[j] = den > 0 ? a1 / den : 0.0;
-      H[(size_t)j * m + j] = den;
-      H[(size_t)(j + 1) * m + j] = 0.0;
-      g[j + 1] = -sn[j] * g[j];
-      g[j] = cs[j] * g[j];
+      ls.add_column(Hb, j, j + 1);
       ++its;
       k = j + 1;
-      const double est = std::fabs(g[j + 1]);
+      const double est = std::fabs(ls.g[j + 1]);
       if (hist) hist[hist_off + its - 1] = est / bnorm;
-      if (est <= tol_abs || hnext == 0.0) { done = true; break; }
+      if (est <= tol_abs || hnext == 0.0) { stop = true; break; }
     }
+    if (its >= max_its) stop = true;
     // y = R^{-1} g ; x += V y
-    for (int i = k - 1; i >= 0; --i) {
-      double s = g[i];
-      for (int c = i + 1; c < k; ++c) s -= H[(size_t)i * m + c] * y[c];
-      y[i] = H[(size_t)i * m + i] != 0.0 ? s / H[(size_t)i * m + i] : 0.0;
-    }
+    ls.solve(k, &y);
     if (k > 0) {
       HIPCHK(hipMemcpyAsync(dy, y.data(), k * sizeof(double), hipMemcpyHostToDevice, pr.s));
       HIPCHK(launch_multiaxpy(V.vec(0), V.N, k, dy, 1.0, x, V.N, nullptr, V.nb, pr.s));
       HIPCHK(hipStreamSynchronize(pr.s));
       xzero = false;
     }
-    (void)done;
-    // loop: the true residual is recomputed at the top
+    if (stop || kdef <= 0 || k < m) {
+      fresh = true;                      // the true residual is recomputed at the top
+      continue;
+    }
+    // deflated restart: residual coordinates rho = c - Hbar y in V_{m+1}
+    std::vector<double> rho(m + 1);
+    for (int i = 0; i <= m; ++i) {
+      double acc = c[i];
+      for (int j = 0; j < m; ++j) acc -= Hb[(size_t)i * m + j] * y[j];
+      rho[i] = acc;
+    }
+    std::vector<std::complex<double>> theta;
+    std::vector<double> P, hnew, cnew;
+    int kk = 0;
+    std::string err;
+    if (deflation_step(m, Hb.data(), rho.data(), kdef, &theta, &P, &hnew, &cnew, &kk, &err) != 0) {
+      fresh = true;                      // fall back to a plain restart
+      continue;
+    }
+    HIPCHK(hipMemcpyAsync(pr.W.defl, P.data(), P.size() * sizeof(double), hipMemcpyHostToDevice,
+                          pr.s));
+    HIPCHK(launch_basis_combine(V.vec(0), V.N, m + 1, kk + 1, pr.W.defl, V.N, pr.s));
+    HIPCHK(hipStreamSynchronize(pr.s));
+    std::fill(Hb.begin(), Hb.end(), 0.0);
+    std::fill(c.begin(), c.end(), 0.0);
+    for (int i = 0; i <= kk; ++i) {
+      c[i] = cnew[i];
+      for (int j = 0; j < kk; ++j) Hb[(size_t)i * m + j] = hnew[(size_t)i * kk + j];
+    }
+    ls.reset(m, c);
+    for (int j = 0; j < kk; ++j) ls.add_column(Hb, j, kk);
+    j0 = kk;
+    fresh = false;
+    kr->deflated += 1;
   }
   kr->its += its;
   return MFWH_OK;
@@ -1264,9 +1357,15 @@ void fill_opts(const mfwh_solve_opts* in, mfwh_solve_opts* o) {
   o->max_outer = 20;
   o->zero_fallback = 0;
   o->scale_initial = 0;
+  o->deflate = 0;
+  o->inner_max_iter = 0;
+  o->fpi_form = MFWH_FPI_AUTO;
   if (in) {
     o->zero_fallback = in->zero_fallback;
     o->scale_initial = in->scale_initial;
+    o->deflate = in->deflate;
+    o->inner_max_iter = in->inner_max_iter;
+    o->fpi_form = in->fpi_form;
     if (in->restart > 0) o->restart = in->restart;
     if (in->max_iter > 0) o->max_iter = in->max_iter;
     if (in->tol > 0) o->tol = in->tol;
@@ -1366,6 +1465,29 @@ int mfwh_optimize_filter(int nf, const double* omega_in, int np, int nt, int nde
   return rc == MFWH_OK ? rc : fail(rc, err);
 }
 
+int mfwh_deflation_step(int m, const double* hbar, const double* rho, int k, double* theta,
+                        double* P, double* hnew, double* cnew, int* kk) {
+  if (m < 2 || m > MFWH_MAX_RESTART || k < 1 || k >= m || !hbar || !rho || !P || !hnew ||
+      !cnew || !kk)
+    return fail(MFWH_EINVAL, "mfwh_deflation_step: bad arguments");
+  std::vector<std::complex<double>> th;
+  std::vector<double> Pv, hv, cv;
+  int k2 = 0;
+  std::string err;
+  if (deflation_step(m, hbar, rho, k, &th, &Pv, &hv, &cv, &k2, &err) != 0)
+    return fail(MFWH_ESINGULAR, err);
+  std::copy(Pv.begin(), Pv.end(), P);
+  std::copy(hv.begin(), hv.end(), hnew);
+  std::copy(cv.begin(), cv.end(), cnew);
+  if (theta)
+    for (size_t i = 0; i < th.size(); ++i) {
+      theta[2 * i] = th[i].real();
+      theta[2 * i + 1] = th[i].imag();
+    }
+  *kk = k2;
+  return MFWH_OK;
+}
+
 size_t mfwh_workspace_bytes(const mfwh_grid* g, const mfwh_time* t, int restart) {
   Geom G;
   if (make_geom(g, &G) != MFWH_OK || !t || t->nf < 1 || t->nf > MFWH_MAX_NF) return 0;
@@ -1403,12 +1525,20 @@ int mfwh_solve_fixed_point(const mfwh_grid* g, const mfwh_time* t, const double*
   // once and every iteration applies S, forcing-free, which runs the
   // multi-step kernels; otherwise (1D, smaller workspace) every iteration is
   // one forced application.
-  const bool affine = g && t && g->dim >= 2 && ws_bytes >= mfwh_workspace_bytes(g, t, 1);
+  mfwh_solve_opts o;
+  fill_opts(opts, &o);
+  if (o.fpi_form < MFWH_FPI_AUTO || o.fpi_form > MFWH_FPI_AFFINE)
+    return fail(MFWH_EINVAL, "unknown fpi_form");
+  if (!g || !t) return fail(MFWH_EINVAL, "null grid or time");
+  const bool can_affine = g->dim >= 2 && ws_bytes >= mfwh_workspace_bytes(g, t, 1);
+  if (o.fpi_form == MFWH_FPI_AFFINE && g->dim < 2)
+    return fail(MFWH_EINVAL, "the affine fixed-point form needs a 2D or 3D grid");
+  if (o.fpi_form == MFWH_FPI_AFFINE && !can_affine)
+    return fail(MFWH_EWORKSPACE, "the affine fixed-point form needs mfwh_workspace_bytes(g, t, 1)");
+  const bool affine = o.fpi_form == MFWH_FPI_AFFINE || (o.fpi_form == MFWH_FPI_AUTO && can_affine);
   Problem pr;
   CHK(setup(pr, g, t, affine ? 1 : 0, ws, ws_bytes, stream));
   if (!v || !f) return fail(MFWH_EINVAL, "null array");
-  mfwh_solve_opts o;
-  fill_opts(opts, &o);
   pr.graphs = g_graphs;
   CHK(prepare(pr, f));
   const ExtLayout al = abi_layout(g), il = int_layout(pr.G);
@@ -1450,6 +1580,7 @@ int mfwh_solve_fixed_point(const mfwh_grid* g, const mfwh_time* t, const double*
     info->initial_scale = 1.0;
     info->implicit_solves = pr.imp_solves;
     info->mg_cycles = pr.mg_cycles;
+    info->deflated_restarts = 0;
   }
   return status;
 }
@@ -1460,6 +1591,8 @@ int mfwh_solve_gmres(const mfwh_grid* g, const mfwh_time* t, const double* f, do
   mfwh_solve_opts o;
   fill_opts(opts, &o);
   if (o.restart > MFWH_MAX_RESTART) return fail(MFWH_EINVAL, "restart too large");
+  if (o.deflate < 0 || o.deflate > MFWH_MAX_DEFLATE || (o.deflate > 0 && o.deflate > o.restart - 2))
+    return fail(MFWH_EINVAL, "deflate must be in 0..min(MFWH_MAX_DEFLATE, restart - 2)");
   Problem pr;
   CHK(setup(pr, g, t, o.restart, ws, ws_bytes, stream));
   if (!v || !f) return fail(MFWH_EINVAL, "null array");
@@ -1524,7 +1657,8 @@ int mfwh_solve_gmres(const mfwh_grid* g, const mfwh_time* t, const double* f, do
   int outer = 0;
   double relres = 1.0;
   if (!pr.fp32) {
-    CHK(gmres_core(V, false, B, X, xzero, o.tol * bnorm, m, o.max_iter, bnorm, res_hist, 0, &kr));
+    CHK(gmres_core(V, false, B, X, xzero, o.tol * bnorm, m, o.deflate, o.max_iter, bnorm,
+                   res_hist, 0, &kr));
     relres = kr.res / bnorm;
     if (kr.converged) status = MFWH_OK;
   } else {
@@ -1546,7 +1680,9 @@ int mfwh_solve_gmres(const mfwh_grid* g, const mfwh_time* t, const double* f, do
       HIPCHK(launch_fill(D, V.N, 0.0, pr.s));
       KrylovResult ki;
       const double tol_in = std::max(o.inner_tol * rn, 0.3 * o.tol * bnorm);
-      CHK(gmres_core(V, true, R, D, true, tol_in, m, o.max_iter - kr.its, bnorm, res_hist,
+      int budget = o.max_iter - kr.its;
+      if (o.inner_max_iter > 0) budget = std::min(budget, o.inner_max_iter);
+      CHK(gmres_core(V, true, R, D, true, tol_in, m, o.deflate, budget, bnorm, res_hist,
                      kr.its, &ki));
       kr.its += ki.its;
       HIPCHK(launch_axpby(1.0, D, 1.0, X, V.N, pr.s));
@@ -1567,6 +1703,7 @@ int mfwh_solve_gmres(const mfwh_grid* g, const mfwh_time* t, const double* f, do
     info->initial_scale = init_scale;
     info->implicit_solves = pr.imp_solves;
     info->mg_cycles = pr.mg_cycles;
+    info->deflated_restarts = kr.deflated;
   }
   return status;
 }
@@ -1587,6 +1724,8 @@ int mfwh_solve_gmres_batched(int nprob, const mfwh_problem* probs, const mfwh_so
   mfwh_solve_opts o;
   fill_opts(opts, &o);
   if (o.restart > MFWH_MAX_RESTART) return fail(MFWH_EINVAL, "restart too large");
+  if (o.deflate != 0)
+    return fail(MFWH_EINVAL, "batched solves restart plainly (deflate must be 0)");
   const auto t0 = std::chrono::steady_clock::now();
   auto ms_since = [&]() {
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -1810,6 +1949,7 @@ int mfwh_solve_gmres_batched(int nprob, const mfwh_problem* probs, const mfwh_so
       infos[i].fell_back = S[i].fell_back;
       infos[i].implicit_solves = 0;
       infos[i].mg_cycles = 0;
+      infos[i].deflated_restarts = 0;
       infos[i].initial_rel_residual = S[i].init_rel;
       infos[i].initial_scale = S[i].scale;
     }

@@ -265,5 +265,9 @@ hipError_t launch_scale_by_rnorm(const double* x, const double* nrm2, double* y,
                                  hipStream_t s);
 hipError_t launch_axpby(double a, const double* x, double b, double* y, long long n,
                         hipStream_t s);
+// V[:, 0..kout) <- V[:, 0..nin) P in place (P device, row-major nin x kout,
+// 1 <= kout <= 64, kout <= nin); vectors of n doubles at stride ldv
+hipError_t launch_basis_combine(double* V, long long ldv, int nin, int kout, const double* P,
+                                long long n, hipStream_t s);
 
 }  // namespace mfwh

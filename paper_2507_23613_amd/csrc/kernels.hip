@@ -800,4 +800,47 @@ hipError_t launch_axpby(double a, const double* x, double b, double* y, long lon
   return hipGetLastError();
 }
 
+// In-place change of Krylov basis of a deflated restart: for every element
+// p, (V_0 .. V_{kout-1})[p] <- sum_{i < nin} V_i[p] P[i][j]  (P row-major
+// nin x kout, kout <= KB).  Each thread reads all nin entries of its element
+// before writing any, and no other thread touches that element, so the
+// update is safe in place.  P is read with wave-uniform indices.
+template <int KB>
+__global__ void __launch_bounds__(256) k_basis_combine(double* __restrict__ V, long long ldv,
+                                                       int nin, int kout,
+                                                       const double* __restrict__ P,
+                                                       long long n) {
+  for (long long p = (long long)blockIdx.x * 256 + threadIdx.x; p < n;
+       p += (long long)gridDim.x * 256) {
+    double acc[KB];
+#pragma unroll
+    for (int j = 0; j < KB; ++j) acc[j] = 0.0;
+    for (int i = 0; i < nin; ++i) {
+      const double v = V[(long long)i * ldv + p];
+      const double* __restrict__ row = P + (long long)i * kout;
+#pragma unroll
+      for (int j = 0; j < KB; ++j)
+        if (j < kout) acc[j] += row[j] * v;
+    }
+#pragma unroll
+    for (int j = 0; j < KB; ++j)
+      if (j < kout) V[(long long)j * ldv + p] = acc[j];
+  }
+}
+
+hipError_t launch_basis_combine(double* V, long long ldv, int nin, int kout, const double* P,
+                                long long n, hipStream_t s) {
+  if (kout < 1 || kout > 64 || nin < kout) return hipErrorInvalidValue;
+  const int nb = (int)std::max<long long>(1, std::min<long long>((n + 255) / 256, 8192));
+  if (kout <= 8)
+    k_basis_combine<8><<<nb, 256, 0, s>>>(V, ldv, nin, kout, P, n);
+  else if (kout <= 16)
+    k_basis_combine<16><<<nb, 256, 0, s>>>(V, ldv, nin, kout, P, n);
+  else if (kout <= 32)
+    k_basis_combine<32><<<nb, 256, 0, s>>>(V, ldv, nin, kout, P, n);
+  else
+    k_basis_combine<64><<<nb, 256, 0, s>>>(V, ldv, nin, kout, P, n);
+  return hipGetLastError();
+}
+
 }  // namespace mfwh

@@ -87,16 +87,17 @@ class GpuProblem:
         return out
 
     def gmres(self, v=None, restart=None, max_iter=1000, tol=1e-8, inner_tol=1e-5,
-              max_outer=20, zero_fallback=0, scale_initial=0):
+              max_outer=20, zero_fallback=0, scale_initial=0, deflate=0, inner_max_iter=0):
+        """deflate > 0: GMRES-DR(restart, deflate)."""
         v = self.zeros() if v is None else v
         opts = L.make_opts(restart or self.restart, max_iter, tol, inner_tol, max_outer,
-                           zero_fallback, scale_initial)
+                           zero_fallback, scale_initial, deflate, inner_max_iter)
         info = L.mfwh_solve_gmres(self.grid, self.time, self.f, v, opts, self.ws)
         return v, info
 
-    def fixed_point(self, v=None, max_iter=100, tol=1e-300):
+    def fixed_point(self, v=None, max_iter=100, tol=1e-300, form=L.MFWH_FPI_AUTO):
         v = self.zeros() if v is None else v
-        opts = L.make_opts(1, max_iter, tol)
+        opts = L.make_opts(1, max_iter, tol, fpi_form=form)
         info = L.mfwh_solve_fixed_point(self.grid, self.time, self.f, v, opts, self.ws)
         return v, info
 

@@ -293,3 +293,110 @@ def test_product_path_does_not_use_the_oracle():
             "print(bad); sys.exit(1 if bad else 0)") % ROOT
     r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
     assert r.returncode == 0, r.stdout + r.stderr
+
+
+def _arnoldi(A, b, m):
+    n = b.size
+    V = np.zeros((n, m + 1))
+    H = np.zeros((m + 1, m))
+    V[:, 0] = b / np.linalg.norm(b)
+    for j in range(m):
+        w = A @ V[:, j]
+        for i in range(j + 1):
+            H[i, j] = V[:, i] @ w
+            w -= H[i, j] * V[:, i]
+        H[j + 1, j] = np.linalg.norm(w)
+        V[:, j + 1] = w / H[j + 1, j]
+    return V, H
+
+
+@pytest.mark.parametrize("cycle", ["first", "after-restart"])
+@pytest.mark.parametrize("kind", ["sym", "nonsym", "mfwh-like"])
+@pytest.mark.parametrize("m,k", [(12, 5), (30, 15), (40, 30)])
+def test_deflation_step_matches_oracle(kind, m, k, cycle):
+    """The library's host step of a deflated GMRES restart (Hessenberg
+    reduction, Francis QR eigenvalues, inverse-iteration eigenvectors,
+    Gram-Schmidt) against the oracle's (numpy.linalg.eig): the same harmonic
+    Ritz values, the same subspace spanned by the kept vectors (compared
+    through projectors, which do not depend on the basis chosen inside it),
+    the same residual column, and the same P P^T Hbar P_k P_k^T and P c_new.
+    "after-restart": the Hbar of the cycle that follows a deflated restart,
+    whose leading block is full (H_m is then not Hessenberg)."""
+    from oracle import krylov
+    rng = np.random.default_rng(m * 100 + k)
+    n = 200
+    if kind == "sym":
+        Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+        A = (Q * np.concatenate([[1e-5, 3e-4, 2e-3], rng.uniform(0.05, 2, n - 3)])) @ Q.T
+    elif kind == "nonsym":
+        A = np.eye(n) + 0.9 * rng.standard_normal((n, n)) / np.sqrt(n)
+    else:   # I - (rank-one blocks): the structure of A_h = I - S_h
+        d = np.concatenate([[1 - 1e-4, 1 - 3e-3, 0.9], rng.uniform(-0.5, 0.8, n // 2 - 3)])
+        g = rng.standard_normal(2)
+        A = np.eye(n)
+        for i in range(n // 2):
+            beta = rng.standard_normal(2)
+            beta *= d[i] / (g @ beta)
+            A[2 * i:2 * i + 2, 2 * i:2 * i + 2] -= np.outer(beta, g)   # eigenvalues 1, 1 - d_i
+        S = np.linalg.qr(rng.standard_normal((n, n)))[0]
+        A = S @ A @ S.T
+    b = rng.standard_normal(n)
+    V, H = _arnoldi(A, b, m)
+    c = np.zeros(m + 1)
+    c[0] = np.linalg.norm(b)
+    y, *_ = np.linalg.lstsq(H, c, rcond=None)
+    rho = c - H @ y
+    if cycle == "after-restart":
+        _, cols = krylov.harmonic_ritz(H, k)
+        Q = np.array(krylov._orthonormalise([np.concatenate([g_, [0.0]]) for g_ in cols] +
+                                            [rho])).T
+        k0 = Q.shape[1] - 1
+        H2 = np.zeros((m + 1, m))
+        H2[:k0 + 1, :k0] = Q.T @ H @ Q[:m, :k0]
+        V2 = np.zeros((n, m + 1))
+        V2[:, :k0 + 1] = V @ Q
+        for j in range(k0, m):                   # Arnoldi continued, twice-orthogonalised
+            w = A @ V2[:, j]
+            for _ in range(2):
+                h = V2[:, :j + 1].T @ w
+                w -= V2[:, :j + 1] @ h
+                H2[:j + 1, j] += h
+            H2[j + 1, j] = np.linalg.norm(w)
+            V2[:, j + 1] = w / H2[j + 1, j]
+        c = np.zeros(m + 1)
+        c[:k0 + 1] = Q.T @ rho
+        y, *_ = np.linalg.lstsq(H2, c, rcond=None)
+        V, H, rho = V2, H2, c - H2 @ y
+        assert np.linalg.norm(np.tril(H[:m, :m], -2)) > 0      # not Hessenberg
+    theta, P, hnew, cnew = L.mfwh_deflation_step(H, rho, k)
+    kk = hnew.shape[1]
+    assert k <= kk <= k + 1
+    assert np.allclose(P.T @ P, np.eye(kk + 1), atol=1e-11)
+    th_o, cols = krylov.harmonic_ritz(H, k)
+    assert len(th_o) == kk
+    for t in th_o:
+        assert np.min(np.abs(theta - t)) <= 1e-9 * max(1.0, abs(t)), (t, theta)
+    Qo = np.array(krylov._orthonormalise([np.concatenate([g_, [0.0]]) for g_ in cols] +
+                                         [rho])).T
+    assert Qo.shape == P.shape
+    Pk, Ok = P[:, :kk], Qo[:, :kk]
+    assert np.linalg.norm(Pk @ Pk.T - Ok @ Ok.T) <= 1e-8
+    assert np.linalg.norm(np.abs(P[:, -1]) - np.abs(Qo[:, -1])) <= 1e-8
+    assert np.allclose(P[:, -1] * np.sign(P[:, -1] @ rho), Qo[:, -1] * np.sign(Qo[:, -1] @ rho),
+                       atol=1e-8)
+    lhs = P @ hnew @ P[:m, :kk].T
+    rhs = P @ P.T @ H @ P[:m, :kk] @ P[:m, :kk].T
+    assert np.linalg.norm(lhs - rhs) <= 1e-10 * np.linalg.norm(H)
+    assert np.allclose(P @ cnew, P @ P.T @ rho, atol=1e-10 * np.linalg.norm(rho))
+    # and it is the right matrix: Arnoldi-like relation of the new basis (to
+    # the accuracy of this test's single-pass Gram-Schmidt Arnoldi)
+    Vn = V @ P
+    assert np.linalg.norm(A @ Vn[:, :kk] - Vn @ hnew) <= 1e-7 * np.linalg.norm(A @ Vn[:, :kk])
+
+
+def test_deflation_step_rejects_bad_arguments():
+    H = np.triu(np.ones((6, 5)), -1)
+    with pytest.raises(L.MfwhError):
+        L.mfwh_deflation_step(H, np.ones(6), 5)       # k >= m
+    with pytest.raises(L.MfwhError):
+        L.mfwh_deflation_step(H, np.ones(6), 0)

@@ -237,26 +237,46 @@ def test_fixed_point_matches_oracle_config1():
     assert np.allclose(info["history"], rref, rtol=1e-10)
 
 
-@pytest.mark.parametrize("restart", [0, 1], ids=["forced", "affine"])
+@pytest.mark.parametrize("form,restart", [("auto", 0), ("auto", 1), ("forced", 1),
+                                          ("affine", 1)])
 @pytest.mark.parametrize("case", [dict(seed=3, shape=(37, 269), nf=3, order=4, varc=True),
                                   dict(seed=4, shape=(13, 14, 21), nf=2, order=2)],
                          ids=["2d", "3d"])
-def test_fixed_point_forced_and_affine_forms(case, restart):
-    """In 2D and 3D the fixed-point iteration runs as S v + b when the
-    workspace has room (restart >= 1), else as one forced application per
-    iteration: both match the oracle's Algorithm 1 iterates and residuals.
-    Bar: the single-application bar (1e-12, scaled by cond(B) / 10) once per
-    iteration, since each application adds its rounding to an iterate that
-    the contractive map carries forward."""
+def test_fixed_point_forced_and_affine_forms(case, form, restart):
+    """In 2D and 3D the fixed-point iteration runs as S v + b (the affine
+    form, b = W_h(0) once) or as one forced application per iteration
+    (Algorithm 1 as printed), chosen by opts.fpi_form; "auto" takes the
+    affine form when the workspace has room (restart >= 1).  Both match the
+    oracle's Algorithm 1 iterates and residuals.  Bar: the single-application
+    bar (1e-12, scaled by cond(B) / 10) once per iteration, since each
+    application adds its rounding to an iterate that the contractive map
+    carries forward."""
+    L = _L()
+    fm = {"auto": L.MFWH_FPI_AUTO, "forced": L.MFWH_FPI_FORCED, "affine": L.MFWH_FPI_AFFINE}
+    affine = form == "affine" or (form == "auto" and restart >= 1)
     w = inputs.small(**case)
     gp = _gp(w, restart=restart)
     prob, pl = workload.setup(w)
     k = 6
-    v, info = gp.fixed_point(max_iter=k)
+    v, info = gp.fixed_point(max_iter=k, form=fm[form])
     Vref, rref = omf.fixed_point(prob, pl, w["f"], k)
-    assert info["iterations"] == k and info["applies"] == k + restart
+    assert info["iterations"] == k and info["applies"] == k + (1 if affine else 0)
     assert rel(v.cpu().numpy(), Vref) < k * 1e-12 * max(1.0, np.linalg.cond(pl.B) / 10)
     assert np.allclose(info["history"], rref, rtol=1e-10)
+
+
+def test_fixed_point_form_errors():
+    L = _L()
+    w = inputs.small(seed=3, shape=(37, 29), nf=2, order=4)
+    gp = _gp(w, restart=0)                   # no room for b
+    with pytest.raises(L.MfwhError, match="EWORKSPACE"):
+        gp.fixed_point(max_iter=2, form=L.MFWH_FPI_AFFINE)
+    w1 = inputs.config1(0)
+    gp1 = _gp(w1, restart=1)
+    with pytest.raises(L.MfwhError, match="EINVAL"):
+        gp1.fixed_point(max_iter=2, form=L.MFWH_FPI_AFFINE)   # 1D: forced only
+    with pytest.raises(L.MfwhError, match="EINVAL"):
+        gp1.fixed_point(max_iter=2, form=7)
 
 
 def test_fixed_point_config1_100_iterations():
@@ -329,6 +349,67 @@ def test_gmres_matches_oracle_gmres_history():
     k = min(8, len(ho))
     assert np.allclose(info["history"][:k], ho[:k], rtol=1e-6)
     assert rel(v.cpu().numpy(), Vo) < 1e-9
+
+
+@pytest.mark.parametrize("case", GMRES_CASES, ids=_id)
+def test_gmres_deflated_matches_direct(case):
+    """GMRES-DR(8, 4) (short cycles, so deflated restarts happen) in float64
+    to 1e-13: equal to the sparse direct solve of the discrete Helmholtz
+    problems (eq. discreteHelmholtz), relative L2 and largest pointwise."""
+    w = inputs.small(**case)
+    gp = _gp(w, restart=8)
+    prob, _ = workload.setup(w)
+    v, info = gp.gmres(tol=1e-13, max_iter=400, deflate=4)
+    assert info["converged"], info
+    assert info["rel_residual"] <= 1e-13
+    U = np.stack([fd.helmholtz_direct(w["f"][m], w["omega"][m], prob.h, prob.order, w["c"])
+                  for m in range(case["nf"])])
+    out = v.cpu().numpy()
+    assert rel(out, U) < 1e-10 and rel_max(out, U) < 1e-10
+    if info["iterations"] > 8:
+        assert info["deflated_restarts"] >= 1
+
+
+def test_gmres_deflated_matches_oracle_history():
+    """The same deflated-restart method as the oracle's (oracle/krylov.py):
+    the residual estimates of the first three cycles (two deflated restarts)
+    agree, and so do the solutions."""
+    w = inputs.small(seed=11, shape=(21, 23), nf=2, order=4)
+    gp = _gp(w, restart=10)
+    prob, pl = workload.setup(w)
+    v, info = gp.gmres(tol=1e-12, max_iter=80, deflate=5)
+    Vo, ho, _ = omf.gmres_deflated(prob, pl, w["f"], restart=10, deflate=5, tol=1e-12,
+                                   max_iter=80)
+    h = info["history"]
+    print(f"deflated GMRES: {len(h)} / oracle {len(ho)} iterations, "
+          f"restarts {info['deflated_restarts']}")
+    k = min(20, len(ho), len(h))
+    assert np.allclose(h[:k], ho[:k], rtol=1e-6, atol=1e-13)
+    assert abs(len(h) - len(ho)) <= 2
+    assert rel(v.cpu().numpy(), Vo) < 1e-9
+
+
+def test_gmres_deflated_fp32_refinement_matches_direct():
+    """Float32 stencil with float64 refinement, the inner solves deflated and
+    capped: 1e-5 per frequency against the direct solve."""
+    w = inputs.small(seed=3, shape=(19, 17), nf=3, order=2, varc=True)
+    gp = _gp(w, precision=1, restart=10)
+    prob, _ = workload.setup(w)
+    v, info = gp.gmres(tol=1e-10, max_iter=600, inner_tol=1e-4, deflate=5, inner_max_iter=60)
+    assert info["converged"], info
+    U = np.stack([fd.helmholtz_direct(w["f"][m], w["omega"][m], prob.h, prob.order, w["c"])
+                  for m in range(3)])
+    for m in range(3):
+        assert rel(v.cpu().numpy()[m], U[m]) < 1e-5
+
+
+def test_gmres_deflation_argument_checks():
+    L = _L()
+    w = inputs.small(seed=11, shape=(21, 23), nf=2, order=4)
+    gp = _gp(w, restart=10)
+    for bad in (-1, 9, 63):
+        with pytest.raises(L.MfwhError):
+            gp.gmres(tol=1e-10, deflate=bad)
 
 
 def test_graph_replay_matches_eager_launches():
@@ -519,6 +600,24 @@ def test_config2_full_size_gmres_matches_dst():
     U = np.stack([fd.helmholtz_dst(w["f"][m], w["omega"][m], prob.h, 4) for m in range(4)])
     e = rel(v.cpu().numpy(), U)
     print(f"config2 GMRES: its={info['iterations']} applies={info['applies']} err={e:.2e}")
+    assert e < 1e-7
+
+
+def test_config2_full_size_deflated_gmres30_matches_dst():
+    """The 2D workload with the restart length its configuration names,
+    GMRES(30), deflating 15 harmonic Ritz vectors per restart, to a true
+    relative residual of 1e-11: equal to the DST-I solution to 1e-7 (the
+    error is at most cond(A_h) times the residual, with eigenvalues
+    1 - mu_d of A_h down to ~5e-7; measured 9.9e-8 at 1e-10)."""
+    w = inputs.config2(0)
+    gp = _gp(w, restart=30)
+    v, info = gp.gmres(tol=1e-11, max_iter=600, deflate=15)
+    assert info["converged"], info
+    prob, _ = workload.setup(dict(w, f=None), filt="traditional")
+    U = np.stack([fd.helmholtz_dst(w["f"][m], w["omega"][m], prob.h, 4) for m in range(4)])
+    e = rel(v.cpu().numpy(), U)
+    print(f"config2 GMRES-DR(30,15): its={info['iterations']} applies={info['applies']} "
+          f"deflated restarts={info['deflated_restarts']} err={e:.2e}")
     assert e < 1e-7
 
 
