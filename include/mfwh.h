@@ -272,6 +272,21 @@ size_t mfwh_workspace_bytes(const mfwh_grid* g, const mfwh_time* t, int restart)
 int mfwh_apply(const mfwh_grid* g, const mfwh_time* t, const double* f, const double* v_in,
                double* v_out, int with_forcing, void* ws, size_t ws_bytes, void* stream);
 
+/* mfwh_apply for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same application, arguments as mfwh_apply without the workspace.  Its
+ * scratch is a static device array of MFWH_STATIC_SCRATCH_BYTES held by every
+ * GPU the library runs on until the process ends; the call allocates nothing
+ * (no hipMalloc, no allocating library routine).  A problem whose
+ * mfwh_workspace_bytes(g, t, 0) exceeds that size fails with MFWH_EWORKSPACE.
+ * The array is cleared at the start of every call (fill kernel on the
+ * stream).  All calls on one GPU share its array: calls that overlap in time
+ * on one GPU (different host threads, or different streams without ordering)
+ * race and give undefined results. */
+#define MFWH_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+int mfwh_apply_static(const mfwh_grid* g, const mfwh_time* t, const double* f,
+                      const double* v_in, double* v_out, int with_forcing, void* stream);
+
 /* Fixed-point iteration v <- W_h(v) (Algorithm 1) starting from the given v
  * (device [nf][grid], updated in place).  res_hist (host, may be NULL) gets
  * r^(k) of eq. residual for k = 1..iterations.  Stops when r^(k) <= tol *

@@ -95,6 +95,8 @@ def _load():
                                             ctypes.POINTER(mfwh_time), c_int]),
         "mfwh_apply": (c_int, [ctypes.POINTER(mfwh_grid), ctypes.POINTER(mfwh_time), c_void_p,
                                c_void_p, c_void_p, c_int, c_void_p, c_size_t, c_void_p]),
+        "mfwh_apply_static": (c_int, [ctypes.POINTER(mfwh_grid), ctypes.POINTER(mfwh_time),
+                                      c_void_p, c_void_p, c_void_p, c_int, c_void_p]),
         "mfwh_solve_fixed_point": (c_int, [ctypes.POINTER(mfwh_grid), ctypes.POINTER(mfwh_time),
                                            c_void_p, c_void_p, ctypes.POINTER(mfwh_solve_opts),
                                            P_double, ctypes.POINTER(mfwh_solve_info), c_void_p,
@@ -329,6 +331,15 @@ def mfwh_apply(grid, time, f, v_in, v_out, with_forcing, ws, stream=None):
                           _tptr(v_in, "v_in"), _tptr(v_out, "v_out"), int(with_forcing),
                           ctypes.c_void_p(ws.data_ptr()), ws.numel() * ws.element_size(),
                           _stream(stream)))
+
+
+MFWH_STATIC_SCRATCH_BYTES = 64 << 20
+
+
+def mfwh_apply_static(grid, time, f, v_in, v_out, with_forcing, stream=None):
+    _check(LIB.mfwh_apply_static(ctypes.byref(grid), ctypes.byref(time), _tptr(f, "f"),
+                                 _tptr(v_in, "v_in"), _tptr(v_out, "v_out"), int(with_forcing),
+                                 _stream(stream)))
 
 
 def _solve(fn, grid, time, f, v, opts, ws, stream, hist_len):

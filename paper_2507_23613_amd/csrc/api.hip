@@ -23,6 +23,11 @@
 #include "krylov.h"
 #include "plan.h"
 
+// Scratch of mfwh_apply_static (callers that cannot allocate): one copy per
+// GPU, at an address that host code obtains with hipGetSymbolAddress.  In host
+// code the name below is only a host-side stand-in, never a device address.
+static __device__ __align__(256) unsigned char scratch[MFWH_STATIC_SCRATCH_BYTES];
+
 namespace mfwh {
 namespace {
 
@@ -1515,6 +1520,52 @@ int mfwh_apply(const mfwh_grid* g, const mfwh_time* t, const double* f, const do
   HIPCHK(launch_boundary_fill(g->dim, g->n, t->nf, dirichlet_faces(g),
                               with_forcing ? g->g : nullptr, v_out, pr.s));
   return MFWH_OK;
+}
+
+}  // extern "C"
+
+namespace {
+// Device address of `scratch` per device, looked up once per device with that
+// device current.
+std::mutex g_scratch_mu;
+constexpr int kMaxDevices = 64;
+void* g_scratch_addr[kMaxDevices] = {};
+
+int static_scratch(void** out) {
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(MFWH_EINVAL, "device index out of range");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_addr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(MFWH_EHIP, std::string("hipGetSymbolAddress(scratch): ") +
+                                 hipGetErrorString(e));
+    g_scratch_addr[dev] = p;
+  }
+  *out = g_scratch_addr[dev];
+  return MFWH_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int mfwh_apply_static(const mfwh_grid* g, const mfwh_time* t, const double* f,
+                      const double* v_in, double* v_out, int with_forcing, void* stream) {
+  if (!g || !t) return fail(MFWH_EINVAL, "null grid or time");
+  const size_t need = mfwh_workspace_bytes(g, t, 0);
+  if (need == 0) return fail(MFWH_EINVAL, "invalid problem description");
+  if (need > MFWH_STATIC_SCRATCH_BYTES)
+    return fail(MFWH_EWORKSPACE, "the problem needs " + std::to_string(need) +
+                                     " bytes of scratch; the static scratch holds " +
+                                     std::to_string((size_t)MFWH_STATIC_SCRATCH_BYTES) +
+                                     " (use mfwh_apply with a workspace)");
+  void* ws = nullptr;
+  CHK(static_scratch(&ws));
+  // the array keeps the previous call's contents: clear the part this call uses
+  HIPCHK(launch_fill((double*)ws, (long long)((need + 7) / 8), 0.0, (hipStream_t)stream));
+  return mfwh_apply(g, t, f, v_in, v_out, with_forcing, ws, need, stream);
 }
 
 int mfwh_solve_fixed_point(const mfwh_grid* g, const mfwh_time* t, const double* f, double* v,
