@@ -192,6 +192,23 @@ def paper_square128(n=129):
                 filter="adjusted")
 
 
+def paper_square256_seven(n=257):
+    """The paper's seven-frequency case (Section 8, Fig.
+    multiFreq7SquareNp4Imp): unit square with 256 cells, order 4,
+    omega = {15, 21, 26, 32, 41, 49, 58}, N_p = 4, least-squares filter,
+    Gaussian sources with a_m = omega_m^2, b_m = omega_m and centres
+    {(.6,.45), (.4,.55), (.55,.5), (.5,.5), (.44,.54), (.53,.45), (.44,.47)}
+    given as (x, y); the paper runs it with implicit time stepping."""
+    shape, lengths = (n, n), (1.0, 1.0)
+    omega = np.array([15.0, 21.0, 26.0, 32.0, 41.0, 49.0, 58.0])
+    centers_xy = ((0.6, 0.45), (0.4, 0.55), (0.55, 0.5), (0.5, 0.5), (0.44, 0.54),
+                  (0.53, 0.45), (0.44, 0.47))
+    f = np.stack([_zero_boundary(gaussian(shape, lengths, (cy, cx), om * om, om))
+                  for om, (cx, cy) in zip(omega, centers_xy)])
+    return dict(name="paper-square256-nf7", shape=shape, lengths=lengths, order=4,
+                omega=omega, f=f, c=None, np=4, cfl=0.5, filter="optimised")
+
+
 def small(seed, shape, nf, order, lo=4.0, hi=20.0, varc=False, lengths=None,
           filter="optimised", cfl=0.5):
     """Small random workload for parity tests at sizes the oracle finishes in
