@@ -2,12 +2,13 @@
 
 One step = one complete MFWH solve of the 2D workload (1025^2 grid, order-4
 Laplacian, CFL 0.5, N_f = 4 frequencies drawn U(20, 60), Gaussian-sum
-forcings, least-squares filter): plan, b = W_h(0), restarted GMRES(128) in
-float64 to a true relative residual of 1e-8.  (GMRES(30) stalls near 1e-4 on
-this problem: several discrete eigenvalues sit close to the target
-frequencies, where 1 - mu_d ~ 0, and 30-vector restarts forget them; the
-128-vector basis takes 4.3 GB of the 288 GB HBM.)  Every step runs the fused
-leapfrog + filter kernel for every wave solve of the Krylov iteration.
+forcings, least-squares filter): plan, b = W_h(0), GMRES(30) in float64 to a
+true relative residual of 1e-8, restarted with deflation (15 harmonic Ritz
+vectors of the eigenvalues of A_h nearest zero are kept at every restart;
+plain GMRES(30) stalls near 1e-4 on this problem because several discrete
+eigenvalues sit next to the target frequencies, where 1 - mu_d ~ 0).  Every
+step runs the fused leapfrog + filter kernel for every wave solve of the
+Krylov iteration.
 
 value = interior grid points x time steps x N_f summed over all wave solves
 of the timed steps, divided by the wall time (inputs already in HBM).
@@ -15,15 +16,17 @@ of the timed steps, divided by the wall time (inputs already in HBM).
 Extra fields:
   roofline       the fused step kernel: algorithmic bytes per launch / the
                  launch duration measured with HIP events on its stream during
-                 the timed steps, against the 8 TB/s HBM peak
-  roofline_3d    the same measurement for the three-step kernel on the 3D 256^3
-                 workload (float32 stencil, 8 filters; its 1.8 GB working set
-                 streams from HBM, while the 2D workload's fits the 256 MB
-                 Infinity Cache): two forcing-free applications
+                 the timed steps, against the 8 TB/s HBM peak.  Its hbm3d_*
+                 keys give the same measurement on the 3D 256^3 workload
+                 (float64 and float32 stencil, variable c, 8 filters, two
+                 forcing-free applications each, three-step kernel), whose
+                 1.8 GB working set streams from HBM, while the 2D workload's
+                 fits the 256 MB Infinity Cache
+  roofline_3d    the full 3D measurement, both precisions
   cpu_baseline   the float64 oracle (NumPy, one core) stepping the same
                  workload for a bounded number of time steps
-  time_to_1e8    wall time of one float64 GMRES solve and of one float32-
-                 stencil solve with float64 iterative refinement
+  time_to_1e8    wall time of the float64 solve and of one float32-stencil
+                 solve with float64 iterative refinement (bounded)
 
     python bench.py [--gpus 1] [--steps 3] [--warmup 1]
     python bench.py --mode copy      # plain copy kernel of known size (counter calibration)
@@ -32,6 +35,7 @@ Extra fields:
     python bench.py --mode implicit  # implicit scheme + multigrid: O(N) grid study
     python bench.py --mode bc        # Dirichlet data / Neumann faces at 1025^2
     python bench.py --mode fpi       # 100 fixed-point iterations of the 1D workload
+    python bench.py --mode solve3d   # one full solve of the 3D 256^3 workload
     python bench.py --mode apply --applies 3   # a few forcing-free float64
                                      # applications of the same workload (for
                                      # rocprofv3: the step kernel as the solver runs it)
@@ -256,27 +260,28 @@ def implicit_bench(args):
 
 
 # HBM traffic per launch of the three-step 3D kernel on the 256^3 workload
-# (its 8-accumulator launches; FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0,
-# profiles/k_leap3d_x3_fp32_3d-n256-nf8.md), valid only for
-# the leap3d.hip source it was measured on.
-TRAFFIC3 = {"leap3d_sha256_16": "633db7e588afc68c",
-            "bytes": 982943.3 * 1024 * 2.0 + 1212496.8 * 1024 * 1.0}
+# (its 8-accumulator launches; FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, from the
+# rocprofv3 summaries in profiles/), keyed by precision (1: float32 stencil)
+# and valid only for the leap3d.hip source it was measured on.
+TRAFFIC3 = {1: {"leap3d_sha256_16": "633db7e588afc68c",
+                "bytes": 982943.3 * 1024 * 2.0 + 1212496.8 * 1024 * 1.0}}
 
 
-def roofline_3d():
-    """The 3D 256^3 workload (float32 stencil, variable c, 8 filters): two
-    forcing-free applications with the three-step kernel; its algorithmic bytes
-    per launch over the event-timed launch duration against the 8 TB/s peak
-    (this is the workload whose kernel streams from HBM: 1.8 GB working set)."""
+def roofline_3d(precision):
+    """The 3D 256^3 workload (variable c, 8 filters) in one precision: two
+    forcing-free applications with the three-step kernel after a warm-up; its
+    algorithmic bytes per launch over the event-timed launch duration against
+    the 8 TB/s peak (this is the workload whose kernel streams from HBM: its
+    working set is 1.8 GB in float32 and 2.3 GB in float64)."""
     import hashlib
     import torch
     from paper_2507_23613_amd import _lib as L
     from paper_2507_23613_amd import inputs
     from paper_2507_23613_amd.problem import GpuProblem
-    w = inputs.config3(0)
+    w = _config3()
     L.mfwh_set_option(L.MFWH_OPT_STEPS_PER_PASS, L.MFWH_STEPS_AUTO)
     L.mfwh_set_launch_shape(0)
-    gp = GpuProblem(w, precision=L.MFWH_FP32_STENCIL, restart=0)
+    gp = GpuProblem(w, precision=precision, restart=0)
     nf = len(w["omega"])
     v = torch.randn((nf,) + tuple(w["shape"]), dtype=torch.float64, device="cuda")
     out = torch.empty_like(v)
@@ -285,29 +290,102 @@ def roofline_3d():
     L.mfwh_stats_read()
     L.mfwh_stats_enable(1, 1)
     t0 = time.perf_counter()
-    L.mfwh_apply(gp.grid, gp.time, None, v, out, 0, gp.ws)
+    for _ in range(2):
+        L.mfwh_apply(gp.grid, gp.time, None, v, out, 0, gp.ws)
     torch.cuda.synchronize()
-    el = time.perf_counter() - t0
+    el = (time.perf_counter() - t0) / 2
     L.mfwh_stats_enable(0, 8)
     launches, kms, kbytes = L.mfwh_stats_read()
     achieved = kbytes / (kms * 1e6)
     src = os.path.join(ROOT, "paper_2507_23613_amd", "csrc", "leap3d.hip")
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
-    traffic = round(TRAFFIC3["bytes"]) if sha == TRAFFIC3["leap3d_sha256_16"] else None
+    tr = TRAFFIC3.get(precision)
+    traffic = round(tr["bytes"]) if tr and sha == tr["leap3d_sha256_16"] else None
     ps = gp.interior_points * gp.nt
-    return {"workload": w["name"] + "-fp32-stencil", "nt": gp.nt,
-            "kernel": "k_leap3d_x3<float, order 2, 64x16, chunk 16 (default shape)>: 3 fused "
-                      "leapfrog steps + 8 filter updates per launch (forcing-free)",
+    nt = gp.nt
+    sw = 8 if precision == L.MFWH_FP64 else 4
+    per_pass = 4 * sw + sw + 2 * nf * 8          # W^n, W^{n-1}, 2 outputs, c^2, accumulators
+    per_step = 3 * sw + sw + 2 * nf * 8          # a kernel streaming every step
+    tname = "double" if precision == L.MFWH_FP64 else "float"
+    del gp, v, out
+    torch.cuda.empty_cache()
+    return {"workload": w["name"] + ("-fp64" if precision == L.MFWH_FP64 else "-fp32-stencil"),
+            "nt": nt,
+            "kernel": f"k_leap3d_x3<{tname}, order 2, 64x16, chunk 16>: 3 fused leapfrog steps "
+                      "+ 8 filter updates per launch (forcing-free)",
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "bytes_per_point_per_launch": per_pass,
             "avg_launch_us": round(1e3 * kms / max(1, launches), 2),
             "bytes_per_launch": round(kbytes / max(1, launches)), "timed_launches": launches,
             "ms_per_apply": round(1e3 * el, 1),
             "point_steps_x_nf_per_s": ps * nf / el,
-            "one_step_equivalent": {"bytes_per_point_step": 144,
-                                    "achieved": round(144 * ps / (kms / 1e3) / 1e9, 1),
-                                    "frac": round(144 * ps / (kms / 1e3) / 1e9 / HBM_PEAK_GBS,
-                                                  4)}}
+            "one_step_equivalent": {"bytes_per_point_step": per_step,
+                                    "achieved": round(per_step * ps * 2 / (kms / 1e3) / 1e9, 1),
+                                    "frac": round(per_step * ps * 2 / (kms / 1e3) / 1e9 /
+                                                  HBM_PEAK_GBS, 4)}}
+
+
+_C3 = {}
+
+
+def _config3():
+    """The 3D workload's inputs (drawn once per process)."""
+    from paper_2507_23613_amd import inputs
+    if "w" not in _C3:
+        _C3["w"] = inputs.config3(0)
+    return _C3["w"]
+
+
+def solve3d_bench(args):
+    """One full solve of the 3D workload (256^3, order 2, variable c, N_f = 8):
+    b = W_h(0), GMRES(restart) with deflated restarting to a true relative
+    residual of ``--tol``, float64 or float32 stencil with float64
+    refinement.  The library prints one progress line per Krylov cycle.
+    Reports iterations, wave solves, wall time and the per-frequency relative
+    Helmholtz residual max|f - (L_h + omega^2) V| / max|f| (eq. errorAndResid)
+    evaluated on the GPU with a second-order stencil written here for the
+    check only (it is the residual of the returned field, not part of the
+    solver)."""
+    import torch
+    from paper_2507_23613_amd import _lib as L
+    from paper_2507_23613_amd.problem import GpuProblem
+    w = _config3()
+    prec = L.MFWH_FP32_STENCIL if args.fp32 else L.MFWH_FP64
+    L.mfwh_set_option(L.MFWH_OPT_PROGRESS, 1)
+    gp = GpuProblem(w, precision=prec, restart=args.restart)
+    log(f"3D solve: N_t={gp.nt} precision={prec} GMRES({args.restart}) deflate {args.deflate} "
+        f"workspace {gp.ws.numel() / 2**30:.1f} GiB")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    v, info = gp.gmres(restart=args.restart, deflate=args.deflate, tol=args.tol,
+                       max_iter=args.max_iter, inner_tol=args.inner_tol,
+                       inner_max_iter=args.inner_max_iter, max_outer=args.max_outer)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    L.mfwh_set_option(L.MFWH_OPT_PROGRESS, 0)
+    # relative Helmholtz residual per frequency (order 2, variable c)
+    h = 1.0 / (w["shape"][0] - 1)
+    c2 = torch.as_tensor(w["c"], device="cuda") ** 2
+    f = gp.f
+    rh = []
+    for m in range(len(w["omega"])):
+        u = v[m]
+        lap = torch.zeros_like(u)
+        lap[1:-1, 1:-1, 1:-1] = (u[2:, 1:-1, 1:-1] + u[:-2, 1:-1, 1:-1] + u[1:-1, 2:, 1:-1] +
+                                 u[1:-1, :-2, 1:-1] + u[1:-1, 1:-1, 2:] + u[1:-1, 1:-1, :-2] -
+                                 6.0 * u[1:-1, 1:-1, 1:-1]) / (h * h)
+        r = (f[m] - c2 * lap - float(w["omega"][m]) ** 2 * u)[1:-1, 1:-1, 1:-1]
+        rh.append(float(r.abs().max() / f[m].abs().max()))
+    out = {"mode": "solve3d", "workload": w["name"], "precision": "fp64" if prec == 0 else
+           "fp32-stencil+fp64-refinement", "nt": gp.nt, "restart": args.restart,
+           "deflate": args.deflate, "tol": args.tol, "converged": info["converged"],
+           "rel_residual": info["rel_residual"], "iterations": info["iterations"],
+           "wave_solves": info["applies"], "outer": info["outer"],
+           "deflated_restarts": info["deflated_restarts"], "wall_s": round(el, 1),
+           "s_per_wave_solve": round(el / max(1, info["applies"]), 3),
+           "helmholtz_rel_residual_per_frequency": rh}
+    print(json.dumps(out), flush=True)
 
 
 def fpi_bench(args):
@@ -393,7 +471,18 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--mode", default="solve",
                     choices=["solve", "copy", "apply", "batch", "warmstart", "implicit", "bc",
-                             "fpi"])
+                             "fpi", "solve3d"])
+    ap.add_argument("--restart", type=int, default=30, help="solve3d: GMRES restart length")
+    ap.add_argument("--deflate", type=int, default=15, help="solve3d: harmonic Ritz vectors kept")
+    ap.add_argument("--tol", type=float, default=1e-8, help="solve3d: relative residual")
+    ap.add_argument("--max-iter", type=int, default=1500, help="solve3d: Arnoldi steps")
+    ap.add_argument("--fp32", action="store_true", help="solve3d: float32 stencil + refinement")
+    ap.add_argument("--fp64", action="store_true",
+                    help="apply mode, 3D workload: float64 stencil (default float32)")
+    ap.add_argument("--inner-tol", type=float, default=1e-3, help="solve3d: refinement inner tol")
+    ap.add_argument("--inner-max-iter", type=int, default=0,
+                    help="solve3d: Arnoldi steps per inner solve (0: no cap)")
+    ap.add_argument("--max-outer", type=int, default=20, help="solve3d: refinement steps")
     ap.add_argument("--train", type=int, default=2000)
     ap.add_argument("--test", type=int, default=200)
     ap.add_argument("--epochs", type=int, default=20)
@@ -443,16 +532,19 @@ def main():
     if args.mode == "fpi":
         fpi_bench(args)
         return
+    if args.mode == "solve3d":
+        solve3d_bench(args)
+        return
 
     if args.mode == "apply" and args.config == 3:
         w = inputs.config3(0)
-        prec = L.MFWH_FP32_STENCIL
+        prec = L.MFWH_FP64 if args.fp64 else L.MFWH_FP32_STENCIL
     else:
         w = inputs.config2(0, n=args.n)
         prec = L.MFWH_FP64
     nf = len(w["omega"])
     log(f"workload {w['name']}: omega={np.round(w['omega'], 3).tolist()} N_p={w['np']}")
-    RESTART = 128
+    RESTART, DEFLATE = 30, 15
     gp = GpuProblem(w, precision=prec, restart=0 if args.mode == "apply" else RESTART)
     log(f"N_t={gp.nt} dt={gp.dt:.3e} interior={gp.interior_points}")
     # -1: the library's choice (2D: four steps per pass from 10^6 interior
@@ -479,7 +571,7 @@ def main():
         return
 
     def solve():
-        v, info = gp.gmres(restart=RESTART, max_iter=2000, tol=1e-8)
+        v, info = gp.gmres(restart=RESTART, max_iter=2000, tol=1e-8, deflate=DEFLATE)
         if not info["converged"]:
             raise RuntimeError(f"GMRES did not converge: {info['status']} {info['rel_residual']}")
         return info
@@ -528,15 +620,20 @@ def main():
     roof["one_step_equivalent"] = {
         "bytes_per_point_step": 88, "achieved": round(88 * ps_per_s_kernel / 1e9, 1),
         "frac": round(88 * ps_per_s_kernel / 1e9 / HBM_PEAK_GBS, 4)}
+    roof["one_step_equivalent_frac"] = roof["one_step_equivalent"]["frac"]
 
-    t2e = {"fp64_s": round(elapsed / args.steps, 3)}
+    t2e = {"fp64_s": round(elapsed / args.steps, 3), "fp64_iterations": its[-1]}
     if not args.no_fp32:
-        log("float32-stencil solve with float64 iterative refinement (bounded: 3 outer steps)")
+        # one float32-stencil application differs from the float64 one by
+        # ~3e-3 on this order-4 workload (leapfrog carries the rounding of W
+        # over 3939 steps), so the inner tolerance sits above that floor; the
+        # inner solves are deflated and capped, the outer residual is float64
+        log("float32-stencil solve with float64 iterative refinement (bounded)")
         gp32 = GpuProblem(w, precision=L.MFWH_FP32_STENCIL, restart=RESTART)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        _, info32 = gp32.gmres(restart=RESTART, max_iter=200, tol=1e-8, inner_tol=1e-5,
-                               max_outer=3)
+        v32, info32 = gp32.gmres(restart=RESTART, max_iter=600, tol=1e-8, inner_tol=1e-2,
+                                 max_outer=8, deflate=DEFLATE, inner_max_iter=150)
         torch.cuda.synchronize()
         t2e["fp32_stencil_refined_s"] = round(time.perf_counter() - t1, 3)
         t2e["fp32_converged"] = bool(info32["converged"])
@@ -544,12 +641,25 @@ def main():
         t2e["fp32_iterations"] = info32["iterations"]
         t2e["fp32_outer"] = info32["outer"]
         log(f"fp32: {t2e}")
-        del gp32
-    roof3 = None
+        del gp32, v32
+        torch.cuda.empty_cache()
+    roof3 = {}
     if not args.no_3d:
-        log("3D 256^3 workload: three-step kernel rate (two applications)")
-        roof3 = roofline_3d()
-        log(f"3D: {roof3}")
+        for prec3 in (L.MFWH_FP64, L.MFWH_FP32_STENCIL):
+            log(f"3D 256^3 workload, precision {prec3}: three-step kernel rate "
+                "(two applications)")
+            roof3["fp64" if prec3 == L.MFWH_FP64 else "fp32"] = r3 = roofline_3d(prec3)
+            log(f"3D: {r3}")
+    for key, r3 in roof3.items():
+        # flat copies: the 3D workload streams from HBM (working set beyond
+        # the Infinity Cache), so its fraction is the true-HBM figure
+        roof[f"hbm3d_{key}_workload"] = r3["workload"]
+        roof[f"hbm3d_{key}_achieved"] = r3["achieved"]
+        roof[f"hbm3d_{key}_frac"] = r3["frac"]
+        roof[f"hbm3d_{key}_traffic"] = r3["traffic"]
+        roof[f"hbm3d_{key}_avg_launch_us"] = r3["avg_launch_us"]
+        roof[f"hbm3d_{key}_ms_per_apply"] = r3["ms_per_apply"]
+        roof[f"hbm3d_{key}_point_steps_x_nf_per_s"] = r3["point_steps_x_nf_per_s"]
     if not args.no_cpu:
         log("oracle baseline on the host (about 15 s)")
     cpu = None if args.no_cpu else cpu_baseline(w)
@@ -558,14 +668,17 @@ def main():
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": 1e3 * elapsed / args.steps, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"{w['name']}-order4-cfl0.5-gmres{RESTART}-tol1e-8",
+        "config": {"workload": f"{w['name']}-order4-cfl0.5-gmres{RESTART}-deflate{DEFLATE}"
+                               "-tol1e-8",
                    "grid": list(w["shape"]), "nf": nf, "np": int(w["np"]), "nt": gp.nt,
-                   "gmres_iterations": its, "wave_solves": applies,
+                   "gmres_restart": RESTART, "gmres_deflate": DEFLATE,
+                   "gmres_iterations_per_solve": its[-1], "gmres_iterations": its,
+                   "wave_solves": applies,
                    "steps_per_pass": spp,
                    "launch_shape": list(shape) if shape else None,
                    "omega": np.round(w["omega"], 4).tolist()},
         "roofline": roof,
-        "roofline_3d": roof3,
+        "roofline_3d": roof3 or None,
         "cpu_baseline": cpu,
         "time_to_1e8": t2e,
     }

@@ -392,6 +392,22 @@ int mfwh_cnn_normalize(int batch, long long per_sample, float* t, void* stream);
 int mfwh_cnn_forward(int batch, int nf, int H, int W, const float* params, const float* feat,
                      float* out, void* ws, size_t ws_bytes, void* stream);
 
+/* One 3x3 convolution layer of the network (padding 1, stride 1 or 2) run
+ * alone, with the same kernels the network chains (im2col into bf16, the
+ * BF16 MFMA GEMM, bias, col2im, nearest up-sampling); for inspection and
+ * tests.  x: device NHWC [B][Hi][Wi][cin] float32; up = 1 reads x through
+ * its nearest x2 up-sampling cut to the window grid Hs x Ws (Hs <= 2 Hi,
+ * Ws <= 2 Wi); up = 0 needs Hs = Hi, Ws = Wi.  wb: device float32
+ * W[cout][cin][3][3] then b[cout].  Forward (dz == NULL): z (device NHWC
+ * [B][Ho][Wo][cout], Ho = (Hs - 1)/stride + 1) = conv + b, no activation.
+ * Backward (dz != NULL, z ignored): dx (same layout as x) = gradient w.r.t.
+ * x, dwb (same layout as wb) = gradients w.r.t. W and b.  cin, cout <= 256. */
+size_t mfwh_cnn_conv3x3_workspace_bytes(int batch, int Hi, int Wi, int cin, int cout,
+                                        int stride, int up, int Hs, int Ws);
+int mfwh_cnn_conv3x3(int batch, int Hi, int Wi, int cin, int cout, int stride, int up, int Hs,
+                     int Ws, const float* x, const float* wb, float* z, const float* dz,
+                     float* dx, float* dwb, void* ws, size_t ws_bytes, void* stream);
+
 /* Mean-squared-error loss against target (NHWC) and its gradient w.r.t. the
  * flat parameters (device float32, overwritten); *loss (host) may be NULL. */
 int mfwh_cnn_loss_grad(int batch, int nf, int H, int W, const float* params, const float* feat,
@@ -402,7 +418,8 @@ int mfwh_cnn_loss_grad(int batch, int nf, int H, int W, const float* params, con
 int mfwh_cnn_adam(long long n, float* params, const float* grad, float* m, float* v, int step,
                   float lr, void* stream);
 
-/* The BF16 MFMA GEMM the convolutions use: C[M][N] (float32) = A * B with A
+/* The BF16 MFMA GEMM the convolutions use (gfx950 v_mfma_f32_16x16x32_bf16,
+ * float32 accumulation): C[M][N] (float32) = A * B with A
  * bf16 [M][K] (atrans 0) or stored [K][M] (atrans 1), B bf16 [K][N]; part:
  * float32 scratch of 64*M*N for long reductions (K > 8192 with atrans 1). */
 int mfwh_gemm_bf16(int atrans, const void* A, const void* B, float* C, long long M, int N,
@@ -460,8 +477,12 @@ int mfwh_set_launch_shape(int bx, int by, int chunk);
  * general kernel.
  * MFWH_OPT_PREFETCH_DEPTH (2 or 4; default 4): register sets of row operands
  * a wave of the streamlined 2D kernels rotates through, i.e. it requests the
- * operands of row y + depth - 1 before computing row y. */
-enum { MFWH_OPT_GRAPHS = 1, MFWH_OPT_STEPS_PER_PASS = 2, MFWH_OPT_PREFETCH_DEPTH = 3 };
+ * operands of row y + depth - 1 before computing row y.
+ * MFWH_OPT_PROGRESS (default 0): 1 makes mfwh_solve_gmres print one line to
+ * stderr per Krylov cycle (Arnoldi steps so far, residual estimate, restart
+ * kind) and per refinement step, for long solves. */
+enum { MFWH_OPT_GRAPHS = 1, MFWH_OPT_STEPS_PER_PASS = 2, MFWH_OPT_PREFETCH_DEPTH = 3,
+       MFWH_OPT_PROGRESS = 4 };
 int mfwh_set_option(int key, long long value);
 
 #ifdef __cplusplus

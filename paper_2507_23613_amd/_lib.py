@@ -122,6 +122,8 @@ def _load():
                                      c_void_p, c_size_t, c_void_p]),
         "mfwh_cnn_loss_grad": (c_int, [c_int, c_int, c_int, c_int, c_void_p, c_void_p, c_void_p,
                                        c_void_p, P_double, c_void_p, c_size_t, c_void_p]),
+        "mfwh_cnn_conv3x3_workspace_bytes": (c_size_t, [c_int] * 9),
+        "mfwh_cnn_conv3x3": (c_int, [c_int] * 9 + [c_void_p] * 7 + [c_size_t, c_void_p]),
         "mfwh_cnn_adam": (c_int, [c_longlong, c_void_p, c_void_p, c_void_p, c_void_p, c_int,
                                   ctypes.c_float, c_void_p]),
         "mfwh_gemm_bf16": (c_int, [c_int, c_void_p, c_void_p, c_void_p, c_longlong, c_int,
@@ -416,6 +418,7 @@ MFWH_OPT_GRAPHS = 1
 MFWH_OPT_STEPS_PER_PASS = 2
 MFWH_STEPS_AUTO = -1          # MFWH_OPT_STEPS_PER_PASS value: the built-in choice
 MFWH_OPT_PREFETCH_DEPTH = 3
+MFWH_OPT_PROGRESS = 4
 
 
 def mfwh_set_option(key, value):
@@ -498,6 +501,23 @@ def mfwh_cnn_loss_grad(params, feat, target, grad, nf, ws, stream=None):
                                       _ptr(grad, "grad", torch.float32), ctypes.byref(loss),
                                       *_wsargs(ws), _stream(stream)))
     return loss.value
+
+
+def mfwh_cnn_conv3x3_workspace_bytes(B, Hi, Wi, cin, cout, stride, up, Hs, Ws):
+    return int(LIB.mfwh_cnn_conv3x3_workspace_bytes(B, Hi, Wi, cin, cout, stride, up, Hs, Ws))
+
+
+def mfwh_cnn_conv3x3(B, Hi, Wi, cin, cout, stride, up, Hs, Ws, x, wb, z, dz, dx, dwb, ws,
+                     stream=None):
+    import torch
+    f32 = torch.float32
+
+    def opt(t, what):
+        return None if t is None else _ptr(t, what, f32)
+    _cnn_check(LIB.mfwh_cnn_conv3x3(B, Hi, Wi, cin, cout, stride, up, Hs, Ws,
+                                    _ptr(x, "x", f32), _ptr(wb, "wb", f32), opt(z, "z"),
+                                    opt(dz, "dz"), opt(dx, "dx"), opt(dwb, "dwb"),
+                                    *_wsargs(ws), _stream(stream)))
 
 
 def mfwh_cnn_adam(params, grad, m, v, step, lr, stream=None):

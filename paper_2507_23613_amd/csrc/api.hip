@@ -322,6 +322,7 @@ bool g_shape_set = false;
 bool g_graphs = true;           // solvers record step sequences into graphs
 int g_steps_per_pass = -1;      // steps per pass (MFWH_OPT_STEPS_PER_PASS; -1: automatic)
 int g_depth = 4;                // prefetch depth of the streamlined kernels (MFWH_OPT_PREFETCH_DEPTH)
+bool g_progress = false;        // one stderr line per Krylov cycle (MFWH_OPT_PROGRESS)
 
 int setup(Problem& pr, const mfwh_grid* g, const mfwh_time* t, int restart, void* ws,
           size_t ws_bytes, void* stream) {
@@ -1076,6 +1077,11 @@ int gmres_core(Vecs& V, bool use32, const double* rhs, double* x, bool xzero, do
       CHK(norm2(V, v0, &beta));
       if (!std::isfinite(beta)) return fail(MFWH_ENONFINITE, "non-finite residual in GMRES");
       kr->res = beta;
+      if (g_progress) {
+        std::fprintf(stderr, "[mfwh gmres] %d Arnoldi steps: true relative residual %.3e\n",
+                     hist_off + its, beta / bnorm);
+        std::fflush(stderr);
+      }
       if (beta <= tol_abs) { kr->converged = true; break; }
       if (its >= max_its) break;
       {
@@ -1166,6 +1172,12 @@ int gmres_core(Vecs& V, bool use32, const double* rhs, double* x, bool xzero, do
     j0 = kk;
     fresh = false;
     kr->deflated += 1;
+    if (g_progress) {
+      std::fprintf(stderr, "[mfwh gmres] %d Arnoldi steps: estimate %.3e, deflated restart "
+                   "keeping %d vectors (smallest |theta| %.3e)\n", hist_off + its,
+                   std::fabs(ls.g[kk]) / bnorm, kk, theta.empty() ? 0.0 : std::abs(theta[0]));
+      std::fflush(stderr);
+    }
   }
   kr->its += its;
   return MFWH_OK;
@@ -1726,6 +1738,11 @@ int mfwh_solve_gmres(const mfwh_grid* g, const mfwh_time* t, const double* f, do
       CHK(norm2(V, R, &rn));
       if (!std::isfinite(rn)) return fail(MFWH_ENONFINITE, "non-finite outer residual");
       relres = rn / bnorm;
+      if (g_progress) {
+        std::fprintf(stderr, "[mfwh refinement] step %d: float64 relative residual %.3e\n",
+                     outer, relres);
+        std::fflush(stderr);
+      }
       if (relres <= o.tol) { status = MFWH_OK; break; }
       if (kr.its >= o.max_iter) break;
       HIPCHK(launch_fill(D, V.N, 0.0, pr.s));
@@ -2057,6 +2074,9 @@ int mfwh_set_option(int key, long long value) {
     case MFWH_OPT_PREFETCH_DEPTH:
       if (value != 2 && value != 4) return fail(MFWH_EINVAL, "prefetch depth must be 2 or 4");
       g_depth = (int)value;
+      return MFWH_OK;
+    case MFWH_OPT_PROGRESS:
+      g_progress = value != 0;
       return MFWH_OK;
     default:
       return fail(MFWH_EINVAL, "unknown option");

@@ -5,7 +5,7 @@
 //
 // Compute: every 3x3 convolution (forward, backward w.r.t. input and weights)
 // is an implicit GEMM on the matrix cores: im2col into bfloat16, then one
-// BF16 MFMA GEMM kernel (v_mfma_f32_16x16x16_bf16, float32 accumulation),
+// BF16 MFMA GEMM kernel (v_mfma_f32_16x16x32_bf16, float32 accumulation),
 // col2im for the input gradient.  Activations, gradients and master weights
 // are float32 in NHWC layout [B][H][W][C]; the K index of a convolution is
 // k = (ky*3 + kx)*Cin + ci so each im2col row reads contiguous channels.
@@ -46,16 +46,29 @@ __device__ __forceinline__ bf16raw f2bf(float f) {
 //   A: [M][K] row-major (ATRANS = 0) or stored as [K][M] (ATRANS = 1)
 //   B: [K][N] row-major
 // Block 256 threads = 4 waves, block tile 64 x 64, each wave 32 x 32 as
-// 2 x 2 MFMA 16x16x16 tiles; K advances by 16 through LDS.
+// 2 x 2 tiles of gfx950's v_mfma_f32_16x16x32_bf16; K advances by 32.
+// Staging: every thread moves one 16-byte group of 8 bf16 per operand per K
+// step (global dwordx4 loads when the group is in range and 16-byte
+// aligned, element loads otherwise).  In LDS both operands are stored
+// k-contiguous (As[m][k], Bt[n][k]) so that each lane reads its 8 MFMA
+// operand values as one 16-byte LDS load; rows are padded by 8 bf16 so the
+// 16 rows a wave reads start in different banks.  The lanes of an MFMA
+// operand hold rows (A) / columns (B) lane % 16 and the k-group lane / 16;
+// A and B use the same k-group assignment, so any k order the instruction
+// pairs them in gives the same sum.
 // ---------------------------------------------------------------------------
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef short s16x8 __attribute__((ext_vector_type(8)));
+
 template <int ATRANS>
 __global__ void __launch_bounds__(256) k_gemm_bf16(const bf16raw* __restrict__ A,
                                                    const bf16raw* __restrict__ B,
                                                    float* __restrict__ C, int M, int N, int K,
                                                    int lda, int ldb, int ldc, int kchunk,
                                                    long long zstride) {
-  __shared__ bf16raw As[64][16 + 2];
-  __shared__ bf16raw Bs[16][64 + 2];
+  constexpr int KT = 32, PAD = 8;
+  __shared__ __align__(16) bf16raw As[64][KT + PAD];
+  __shared__ __align__(16) bf16raw Bt[64][KT + PAD];
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
   const int m0 = blockIdx.x * 64, n0 = blockIdx.y * 64;
@@ -67,40 +80,59 @@ __global__ void __launch_bounds__(256) k_gemm_bf16(const bf16raw* __restrict__ A
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
-  for (int k0 = kbeg; k0 < kend; k0 += 16) {
-    // A tile 64 x 16: 4 elements per thread
+  for (int k0 = kbeg; k0 < kend; k0 += KT) {
+    s16x8 va, vb;
+    if (!ATRANS) {
+      // A [M][K]: thread -> row r, k group g (8 consecutive k)
+      const int r = tid >> 2, g = (tid & 3) * 8;
+      const int gm = m0 + r, gk = k0 + g;
+      const bf16raw* src = A + (long long)gm * lda + gk;
+      if (gm < M && gk + 8 <= kend && (((uintptr_t)src) & 15) == 0) {
+        va = *(const s16x8*)src;
+      } else {
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int idx = tid * 4 + e;
-      int r, c;
-      if (ATRANS) { c = idx / 64; r = idx % 64; }   // coalesced along M for [K][M]
-      else { r = idx / 16; c = idx % 16; }
-      const int gm = m0 + r, gk = k0 + c;
-      bf16raw v = 0;
-      if (gm < M && gk < kend)
-        v = ATRANS ? A[(long long)gk * lda + gm] : A[(long long)gm * lda + gk];
-      As[r][c] = v;
+        for (int j = 0; j < 8; ++j) va[j] = (gm < M && gk + j < kend) ? src[j] : (bf16raw)0;
+      }
+      *(s16x8*)&As[r][g] = va;
+    } else {
+      // A stored [K][M]: thread -> k row kk, m group g (8 consecutive m)
+      const int kk = tid >> 3, g = (tid & 7) * 8;
+      const int gk = k0 + kk, gm = m0 + g;
+      const bf16raw* src = A + (long long)gk * lda + gm;
+      if (gk < kend && gm + 8 <= M && (((uintptr_t)src) & 15) == 0) {
+        va = *(const s16x8*)src;
+      } else {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) va[j] = (gk < kend && gm + j < M) ? src[j] : (bf16raw)0;
+      }
+#pragma unroll
+      for (int j = 0; j < 8; ++j) As[g + j][kk] = va[j];
     }
+    {
+      // B [K][N]: thread -> k row kk, n group g
+      const int kk = tid >> 3, g = (tid & 7) * 8;
+      const int gk = k0 + kk, gn = n0 + g;
+      const bf16raw* src = B + (long long)gk * ldb + gn;
+      if (gk < kend && gn + 8 <= N && (((uintptr_t)src) & 15) == 0) {
+        vb = *(const s16x8*)src;
+      } else {
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int idx = tid * 4 + e;
-      const int r = idx / 64, c = idx % 64;
-      const int gk = k0 + r, gn = n0 + c;
-      Bs[r][c] = (gk < kend && gn < N) ? B[(long long)gk * ldb + gn] : (bf16raw)0;
+        for (int j = 0; j < 8; ++j) vb[j] = (gk < kend && gn + j < N) ? src[j] : (bf16raw)0;
+      }
+#pragma unroll
+      for (int j = 0; j < 8; ++j) Bt[g + j][kk] = vb[j];
     }
     __syncthreads();
-    const int li = lane & 15, lk = (lane >> 4) * 4;
+    const int li = lane & 15, lk = (lane >> 4) * 8;
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
-      bf16x4 av;
-#pragma unroll
-      for (int j = 0; j < 4; ++j) av[j] = As[wm + a * 16 + li][lk + j];
+      const s16x8 ar = *(const s16x8*)&As[wm + a * 16 + li][lk];
+      const bf16x8 av = __builtin_bit_cast(bf16x8, ar);
 #pragma unroll
       for (int b = 0; b < 2; ++b) {
-        bf16x4 bv;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) bv[j] = Bs[lk + j][wn + b * 16 + li];
-        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc[a][b], 0, 0, 0);
+        const s16x8 br = *(const s16x8*)&Bt[wn + b * 16 + li][lk];
+        const bf16x8 bv = __builtin_bit_cast(bf16x8, br);
+        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[a][b], 0, 0, 0);
       }
     }
     __syncthreads();
@@ -570,10 +602,10 @@ inline unsigned grid_for(long long n) {
 int gemm(bool atrans, const bf16raw* A, const bf16raw* B, float* C, long long M, int N,
          long long K, int lda, int ldb, int ldc, float* part, hipStream_t s) {
   int nz = 1;
-  long long kc = (K + 15) / 16 * 16;
+  long long kc = (K + 31) / 32 * 32;
   if (atrans && K > 8192) {                  // long reductions: deterministic split-K
     nz = (int)std::min<long long>(kSplit, (K + 4095) / 4096);
-    kc = ((K + nz - 1) / nz + 15) / 16 * 16;
+    kc = ((K + nz - 1) / nz + 31) / 32 * 32;
     nz = (int)((K + kc - 1) / kc);
   }
   dim3 grid((unsigned)((M + 63) / 64), (unsigned)((N + 63) / 64), (unsigned)nz);
@@ -666,9 +698,109 @@ int relu_bwd(const Buf& b, const float* da, const float* z, long long P, int C, 
 
 using namespace mfwh::cnn;
 
+namespace mfwh {
+namespace cnn {
+namespace {
+// One layer as its own net (layer 0) with the buffers the layer helpers use.
+struct ConvOne {
+  Net n;
+  Buf b{};
+  size_t bytes = 0;
+};
+
+int conv_one(int B, int Hi, int Wi, int cin, int cout, int stride, int up, int Hs, int Ws,
+             char* base, ConvOne* c) {
+  if (B < 1 || Hi < 1 || Wi < 1 || cin < 1 || cout < 1 || cin > 256 || cout > 256 ||
+      (stride != 1 && stride != 2) || (up != 0 && up != 1))
+    return cfail(MFWH_EINVAL, "bad convolution dimensions");
+  if (!up && (Hs != Hi || Ws != Wi)) return cfail(MFWH_EINVAL, "Hs, Ws must equal Hi, Wi");
+  if (up && (Hs < 1 || Ws < 1 || Hs > 2 * Hi || Ws > 2 * Wi))
+    return cfail(MFWH_EINVAL, "up-sampled window must fit 2 Hi x 2 Wi");
+  if ((long long)B * Hs * Ws > (1LL << 26)) return cfail(MFWH_EINVAL, "layer too large");
+  Net& n = c->n;
+  n = Net{};
+  n.B = B;
+  Layer& l = n.L[0];
+  l.cin = cin; l.cout = cout; l.stride = stride; l.up = up;
+  l.Hi = Hi; l.Wi = Wi; l.Hs = Hs; l.Ws = Ws;
+  l.Ho = (Hs - 1) / stride + 1; l.Wo = (Ws - 1) / stride + 1;
+  l.K = 9 * cin;
+  l.P = (long long)B * l.Ho * l.Wo;
+  l.woff = 0;
+  l.boff = (size_t)cout * cin * 9;
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> char* {
+    off = (off + 255) / 256 * 256;
+    char* p = base ? base + off : nullptr;
+    off += bytes;
+    return p;
+  };
+  Buf& b = c->b;
+  b.wt[0] = (bf16raw*)take((size_t)l.K * cout * 2);
+  b.wtT[0] = (bf16raw*)take((size_t)l.K * cout * 2);
+  b.col = (bf16raw*)take((size_t)l.P * l.K * 2);
+  b.dcol = (float*)take((size_t)l.P * l.K * 4);
+  b.C = (float*)take((size_t)l.P * cout * 4);
+  b.part = (float*)take((size_t)kSplit * l.K * cout * 4);
+  b.dWt = (float*)take((size_t)l.K * cout * 4);
+  b.dz = (float*)take((size_t)l.P * cout * 4);
+  b.dzb = (bf16raw*)take((size_t)l.P * cout * 2);
+  b.gU = (float*)take((size_t)B * Hs * Ws * cin * 4);
+  c->bytes = (off + 255) / 256 * 256;
+  return MFWH_OK;
+}
+}  // namespace
+}  // namespace cnn
+}  // namespace mfwh
+
 extern "C" {
 
 const char* mfwh_cnn_last_error(void) { return g_cnn_err.c_str(); }
+
+size_t mfwh_cnn_conv3x3_workspace_bytes(int batch, int Hi, int Wi, int cin, int cout, int stride,
+                                        int up, int Hs, int Ws) {
+  ConvOne c;
+  if (conv_one(batch, Hi, Wi, cin, cout, stride, up, Hs, Ws, nullptr, &c) != MFWH_OK) return 0;
+  return c.bytes;
+}
+
+int mfwh_cnn_conv3x3(int batch, int Hi, int Wi, int cin, int cout, int stride, int up, int Hs,
+                     int Ws, const float* x, const float* wb, float* z, const float* dz,
+                     float* dx, float* dwb, void* ws, size_t ws_bytes, void* stream) {
+  ConvOne c;
+  CCHK(conv_one(batch, Hi, Wi, cin, cout, stride, up, Hs, Ws, nullptr, &c));
+  if (!ws || ((uintptr_t)ws) % 256) return cfail(MFWH_EWORKSPACE, "workspace null or misaligned");
+  if (c.bytes > ws_bytes) return cfail(MFWH_EWORKSPACE, "workspace too small");
+  CCHK(conv_one(batch, Hi, Wi, cin, cout, stride, up, Hs, Ws, (char*)ws, &c));
+  if (!x || !wb) return cfail(MFWH_EINVAL, "null array");
+  if (dz ? (!dx || !dwb) : !z) return cfail(MFWH_EINVAL, "null output array");
+  const Net& n = c.n;
+  const Buf& b = c.b;
+  const Layer& l = n.L[0];
+  hipStream_t s = (hipStream_t)stream;
+  k_pack_w<<<grid_for((long long)l.K * l.cout), 256, 0, s>>>(wb, l.cout, l.cin, l.K, l.cout,
+                                                             b.wt[0], b.wtT[0]);
+  CHIP(hipGetLastError());
+  if (!dz) {
+    CCHK(im2col(n, l, x, b.col, s));
+    CCHK(gemm(false, b.col, b.wt[0], b.C, l.P, l.cout, l.K, l.K, l.cout, l.cout, b.part, s));
+    k_bias_act<<<grid_for(l.P * l.cout), 256, 0, s>>>(b.C, wb + l.boff, l.P, l.cout, 0, nullptr,
+                                                      nullptr, z);
+    CHIP(hipGetLastError());
+    return MFWH_OK;
+  }
+  CCHK(relu_bwd(b, dz, nullptr, l.P, l.cout, 0, s));          // dz -> float32 and bf16 copies
+  CCHK(layer_wgrad(n, b, 0, x, dwb, s));
+  if (!up) {
+    CCHK(layer_dgrad(n, b, 0, dx, s));
+  } else {
+    CCHK(layer_dgrad(n, b, 0, b.gU, s));                        // d up2(x) on the window grid
+    k_up2_bwd<<<grid_for((long long)batch * Hi * Wi * cin), 256, 0, s>>>(b.gU, batch, Hs, Ws,
+                                                                          cin, Hi, Wi, dx);
+    CHIP(hipGetLastError());
+  }
+  return MFWH_OK;
+}
 
 size_t mfwh_cnn_param_count(int nf) {
   if (nf < 1 || nf > MFWH_MAX_NF) return 0;
