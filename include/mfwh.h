@@ -337,11 +337,14 @@ typedef struct mfwh_problem {
 /* Workspace bytes for mfwh_solve_gmres_batched (0 if the batch is invalid). */
 size_t mfwh_workspace_bytes_batched(int nprob, const mfwh_problem* probs, int restart);
 
-/* GMRES(m) (as mfwh_solve_gmres, float64 only) on nprob independent problems
- * in lockstep.  Every MFWH application of the batch is ONE sequence of step
- * launches in which each launch advances every active problem by one time
- * step (problems with fewer steps drop out of later launches); the sequence is
- * recorded once per solve into a HIP graph and replayed.  Problems of
+/* GMRES(m) (as mfwh_solve_gmres, float64 only, opts->deflate for deflated
+ * restarting) on nprob independent problems.  Every round advances each
+ * unfinished problem by one operator application (its true residual or one
+ * Arnoldi step, each problem in its own cycle), and every round is ONE
+ * sequence of step launches in which each launch advances every active
+ * problem by one time step (problems with fewer steps drop out of later
+ * launches); the sequence is recorded once per solve into a HIP graph and
+ * replayed.  Problems of
  * different grid size, N_f, frequencies and N_t may be mixed; they must share
  * dim (2 or 3) and order.  A problem leaves the batch when its true residual
  * meets tol.  infos: host [nprob] (may be NULL); latency_ms: host [nprob]

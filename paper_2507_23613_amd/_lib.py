@@ -400,7 +400,8 @@ def mfwh_solve_gmres_batched(problems, opts, ws, stream=None):
                  point_steps=infos[k].point_steps, latency_ms=float(lat[k]),
                  fell_back=bool(infos[k].fell_back),
                  initial_rel_residual=infos[k].initial_rel_residual,
-                 initial_scale=infos[k].initial_scale)
+                 initial_scale=infos[k].initial_scale,
+                 deflated_restarts=infos[k].deflated_restarts)
             for k in range(n)], STATUS[rc]
 
 

@@ -1792,21 +1792,28 @@ int mfwh_solve_gmres_batched(int nprob, const mfwh_problem* probs, const mfwh_so
   mfwh_solve_opts o;
   fill_opts(opts, &o);
   if (o.restart > MFWH_MAX_RESTART) return fail(MFWH_EINVAL, "restart too large");
-  if (o.deflate != 0)
-    return fail(MFWH_EINVAL, "batched solves restart plainly (deflate must be 0)");
+  if (o.deflate < 0 || o.deflate > MFWH_MAX_DEFLATE || (o.deflate > 0 && o.deflate > o.restart - 2))
+    return fail(MFWH_EINVAL, "deflate must be in 0..min(MFWH_MAX_DEFLATE, restart - 2)");
   const auto t0 = std::chrono::steady_clock::now();
   auto ms_since = [&]() {
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   };
   Batch B;
   CHK(batch_setup(B, nprob, probs, o.restart, ws, ws_bytes, stream));
-  const int np = nprob, m = o.restart;
+  const int np = nprob, m = o.restart, kdef = o.deflate;
+  // Per-problem GMRES state.  Every round advances each unfinished problem by
+  // one operator application: the true residual b - A x when its cycle starts
+  // fresh, else one Arnoldi step of its current cycle; all of them share one
+  // replay of the batched step sequence.  With deflation, a cycle that ends
+  // without convergence keeps its harmonic Ritz vectors (as in the single
+  // solver) and the problem continues without a fresh start.
   struct St {
     Vecs V;
-    std::vector<double> H, cs, sn, g, y, hh;
+    GivensLS ls;
+    std::vector<double> Hb, c, y, hh;
     double bnorm = 0, res = 0;
-    int its = 0, k = 0;
-    bool xzero = true, done = false, conv = false, live = false, first = true;
+    int its = 0, j = 0, deflated = 0;
+    bool xzero = true, done = false, conv = false, first = true, fresh = true;
     int fell_back = 0;
     double lat = 0, init_rel = 1.0, scale = 1.0;
   };
@@ -1817,11 +1824,8 @@ int mfwh_solve_gmres_batched(int nprob, const mfwh_problem* probs, const mfwh_so
     Problem& pr = *B.pr[i];
     S[i].V = Vecs{&pr, (long long)pr.P.nf * pr.G.fs, 0};
     S[i].V.nb = blas_blocks(S[i].V.N);
-    S[i].H.assign((size_t)(m + 1) * m, 0.0);
-    S[i].cs.assign(m, 0.0);
-    S[i].sn.assign(m, 0.0);
-    S[i].g.assign(m + 1, 0.0);
-    S[i].y.assign(m, 0.0);
+    S[i].Hb.assign((size_t)(m + 1) * m, 0.0);
+    S[i].c.assign(m + 1, 0.0);
     S[i].hh.assign(2 * (m + 1) + 1, 0.0);
     HIPCHK(launch_fill(pr.W.vec, (long long)pr.W.nvec * S[i].V.N, 0.0, B.s));
   }
@@ -1844,23 +1848,47 @@ int mfwh_solve_gmres_batched(int nprob, const mfwh_problem* probs, const mfwh_so
     CHK(norm2(S[i].V, X(i), &xn));
     S[i].xzero = xn == 0.0;
   }
+  // x += V_k y for the k columns of problem i's current cycle
+  auto update_x = [&](int i, int k) -> int {
+    St& st = S[i];
+    Problem& pr = *B.pr[i];
+    st.ls.solve(k, &st.y);
+    if (k > 0) {
+      double* dy = pr.W.scal + 3 * (m + 2);
+      HIPCHK(hipMemcpyAsync(dy, st.y.data(), k * sizeof(double), hipMemcpyHostToDevice, B.s));
+      HIPCHK(launch_multiaxpy(st.V.vec(0), st.V.N, k, dy, 1.0, X(i), st.V.N, nullptr, st.V.nb,
+                              B.s));
+      HIPCHK(hipStreamSynchronize(B.s));
+      st.xzero = false;
+    }
+    return MFWH_OK;
+  };
   while (true) {
-    std::vector<int> cyc;
-    for (int i = 0; i < np; ++i)
-      if (!S[i].done) cyc.push_back(i);
-    if (cyc.empty()) break;
-    // true residuals r = b - A x at the start of the cycle
-    std::vector<int> nz;
+    std::vector<int> fresh, arn, act;
     std::vector<const double*> v(np, nullptr);
     std::vector<Out> out(np);
-    for (int i : cyc) {
+    for (int i = 0; i < np; ++i) {
+      St& st = S[i];
+      if (st.done) continue;
       const ExtLayout il = int_layout(B.pr[i]->G);
-      out[i] = Out{S[i].V.vec(0), il, X(i), il, 1.0, -1.0, nullptr};
-      if (!S[i].xzero) { nz.push_back(i); v[i] = X(i); }
+      if (st.fresh) {
+        fresh.push_back(i);
+        if (!st.xzero) {     // v0 = A x
+          act.push_back(i);
+          v[i] = X(i);
+          out[i] = Out{st.V.vec(0), il, X(i), il, 1.0, -1.0, nullptr};
+        }
+      } else {               // work = A v_j
+        arn.push_back(i);
+        act.push_back(i);
+        v[i] = st.V.vec(st.j);
+        out[i] = Out{st.V.vec(m + 1), il, st.V.vec(st.j), il, 1.0, -1.0, nullptr};
+      }
     }
-    if (!nz.empty()) CHK(batch_apply(B, nz, v, out, false));
-    std::vector<int> live;
-    for (int i : cyc) {
+    if (fresh.empty() && arn.empty()) break;
+    if (!act.empty()) CHK(batch_apply(B, act, v, out, false));
+    // fresh starts: residual, scaling / fallback of an initial guess, stop test
+    for (int i : fresh) {
       St& st = S[i];
       double* v0 = st.V.vec(0);
       if (st.first && !st.xzero && o.scale_initial) {
@@ -1907,98 +1935,89 @@ int mfwh_solve_gmres_batched(int nprob, const mfwh_problem* probs, const mfwh_so
       HIPCHK(hipMemcpyAsync(dnr, &b2, sizeof(double), hipMemcpyHostToDevice, B.s));
       HIPCHK(launch_scale_by_rnorm(v0, dnr, v0, st.V.N, B.s));
       HIPCHK(hipStreamSynchronize(B.s));
-      std::fill(st.H.begin(), st.H.end(), 0.0);
-      std::fill(st.g.begin(), st.g.end(), 0.0);
-      st.g[0] = beta;
-      st.k = 0;
-      live.push_back(i);
+      std::fill(st.Hb.begin(), st.Hb.end(), 0.0);
+      std::fill(st.c.begin(), st.c.end(), 0.0);
+      st.c[0] = beta;
+      st.ls.reset(m, st.c);
+      st.j = 0;
+      st.fresh = false;
     }
-    std::vector<int> act = live;
-    for (int j = 0; j < m && !act.empty(); ++j) {
-      std::vector<int> a2;
-      for (int i : act)
-        if (S[i].its < o.max_iter) a2.push_back(i);
-      act = a2;
-      if (act.empty()) break;
-      std::vector<const double*> vj(np, nullptr);
-      std::vector<Out> ow(np);
-      for (int i : act) {
-        const ExtLayout il = int_layout(B.pr[i]->G);
-        vj[i] = S[i].V.vec(j);
-        ow[i] = Out{S[i].V.vec(m + 1), il, S[i].V.vec(j), il, 1.0, -1.0, nullptr};
-      }
-      CHK(batch_apply(B, act, vj, ow, false));
-      for (int i : act) {
-        St& st = S[i];
-        Problem& pr = *B.pr[i];
-        const int rs = m + 2;
-        double *dh1 = pr.W.scal, *dh2 = pr.W.scal + rs, *dnr = pr.W.scal + 2 * rs;
-        double* work = st.V.vec(m + 1);
-        Vecs& V = st.V;
-        HIPCHK(launch_multidot(V.vec(0), V.N, j + 1, work, V.N, pr.W.partial, V.nb, B.s));
-        HIPCHK(launch_reduce(pr.W.partial, V.nb, j + 1, dh1, B.s));
-        HIPCHK(launch_multiaxpy(V.vec(0), V.N, j + 1, dh1, -1.0, work, V.N, nullptr, V.nb, B.s));
-        HIPCHK(launch_multidot(V.vec(0), V.N, j + 1, work, V.N, pr.W.partial, V.nb, B.s));
-        HIPCHK(launch_reduce(pr.W.partial, V.nb, j + 1, dh2, B.s));
-        HIPCHK(launch_multiaxpy(V.vec(0), V.N, j + 1, dh2, -1.0, work, V.N, pr.W.partial, V.nb,
-                                B.s));
-        HIPCHK(launch_reduce(pr.W.partial, V.nb, 1, dnr, B.s));
-        HIPCHK(hipMemcpyAsync(st.hh.data(), dh1, (j + 1) * sizeof(double),
-                              hipMemcpyDeviceToHost, B.s));
-        HIPCHK(hipMemcpyAsync(st.hh.data() + (m + 1), dh2, (j + 1) * sizeof(double),
-                              hipMemcpyDeviceToHost, B.s));
-        HIPCHK(hipMemcpyAsync(st.hh.data() + 2 * (m + 1), dnr, sizeof(double),
-                              hipMemcpyDeviceToHost, B.s));
-      }
-      HIPCHK(hipStreamSynchronize(B.s));
-      std::vector<int> keep;
-      for (int i : act) {
-        St& st = S[i];
-        Problem& pr = *B.pr[i];
-        const double hnext = std::sqrt(st.hh[2 * (m + 1)]);
-        if (!std::isfinite(hnext)) return fail(MFWH_ENONFINITE, "non-finite Arnoldi vector");
-        for (int r = 0; r <= j; ++r) st.H[(size_t)r * m + j] = st.hh[r] + st.hh[(m + 1) + r];
-        st.H[(size_t)(j + 1) * m + j] = hnext;
-        if (hnext > 0.0)
-          HIPCHK(launch_scale_by_rnorm(st.V.vec(m + 1), pr.W.scal + 2 * (m + 2), st.V.vec(j + 1),
-                                       st.V.N, B.s));
-        for (int r = 0; r < j; ++r) {
-          const double a0 = st.H[(size_t)r * m + j], a1 = st.H[(size_t)(r + 1) * m + j];
-          st.H[(size_t)r * m + j] = st.cs[r] * a0 + st.sn[r] * a1;
-          st.H[(size_t)(r + 1) * m + j] = -st.sn[r] * a0 + st.cs[r] * a1;
-        }
-        const double a0 = st.H[(size_t)j * m + j], a1 = st.H[(size_t)(j + 1) * m + j];
-        const double den = std::hypot(a0, a1);
-        st.cs[j] = den > 0 ? a0 / den : 1.0;
-        st.sn[j] = den > 0 ? a1 / den : 0.0;
-        st.H[(size_t)j * m + j] = den;
-        st.H[(size_t)(j + 1) * m + j] = 0.0;
-        st.g[j + 1] = -st.sn[j] * st.g[j];
-        st.g[j] = st.cs[j] * st.g[j];
-        ++st.its;
-        st.k = j + 1;
-        const double est = std::fabs(st.g[j + 1]);
-        if (!(est <= o.tol * st.bnorm || hnext == 0.0)) keep.push_back(i);
-      }
-      act = keep;
-    }
-    for (int i : live) {
+    // one Arnoldi step per problem in a cycle: classical Gram-Schmidt twice
+    for (int i : arn) {
       St& st = S[i];
       Problem& pr = *B.pr[i];
-      const int k = st.k;
-      for (int r = k - 1; r >= 0; --r) {
-        double sum = st.g[r];
-        for (int c = r + 1; c < k; ++c) sum -= st.H[(size_t)r * m + c] * st.y[c];
-        st.y[r] = st.H[(size_t)r * m + r] != 0.0 ? sum / st.H[(size_t)r * m + r] : 0.0;
+      const int rs = m + 2, j = st.j;
+      double *dh1 = pr.W.scal, *dh2 = pr.W.scal + rs, *dnr = pr.W.scal + 2 * rs;
+      double* work = st.V.vec(m + 1);
+      Vecs& V = st.V;
+      HIPCHK(launch_multidot(V.vec(0), V.N, j + 1, work, V.N, pr.W.partial, V.nb, B.s));
+      HIPCHK(launch_reduce(pr.W.partial, V.nb, j + 1, dh1, B.s));
+      HIPCHK(launch_multiaxpy(V.vec(0), V.N, j + 1, dh1, -1.0, work, V.N, nullptr, V.nb, B.s));
+      HIPCHK(launch_multidot(V.vec(0), V.N, j + 1, work, V.N, pr.W.partial, V.nb, B.s));
+      HIPCHK(launch_reduce(pr.W.partial, V.nb, j + 1, dh2, B.s));
+      HIPCHK(launch_multiaxpy(V.vec(0), V.N, j + 1, dh2, -1.0, work, V.N, pr.W.partial, V.nb,
+                              B.s));
+      HIPCHK(launch_reduce(pr.W.partial, V.nb, 1, dnr, B.s));
+      HIPCHK(hipMemcpyAsync(st.hh.data(), dh1, (j + 1) * sizeof(double), hipMemcpyDeviceToHost,
+                            B.s));
+      HIPCHK(hipMemcpyAsync(st.hh.data() + (m + 1), dh2, (j + 1) * sizeof(double),
+                            hipMemcpyDeviceToHost, B.s));
+      HIPCHK(hipMemcpyAsync(st.hh.data() + 2 * (m + 1), dnr, sizeof(double),
+                            hipMemcpyDeviceToHost, B.s));
+    }
+    if (!arn.empty()) HIPCHK(hipStreamSynchronize(B.s));
+    for (int i : arn) {
+      St& st = S[i];
+      Problem& pr = *B.pr[i];
+      const int j = st.j;
+      const double hnext = std::sqrt(st.hh[2 * (m + 1)]);
+      if (!std::isfinite(hnext)) return fail(MFWH_ENONFINITE, "non-finite Arnoldi vector");
+      for (int r = 0; r <= j; ++r) st.Hb[(size_t)r * m + j] = st.hh[r] + st.hh[(m + 1) + r];
+      st.Hb[(size_t)(j + 1) * m + j] = hnext;
+      if (hnext > 0.0)
+        HIPCHK(launch_scale_by_rnorm(st.V.vec(m + 1), pr.W.scal + 2 * (m + 2), st.V.vec(j + 1),
+                                     st.V.N, B.s));
+      st.ls.add_column(st.Hb, j, j + 1);
+      ++st.its;
+      st.j = j + 1;
+      const double est = std::fabs(st.ls.g[j + 1]);
+      const bool stop = est <= o.tol * st.bnorm || hnext == 0.0 || st.its >= o.max_iter;
+      if (!stop && st.j < m) continue;
+      CHK(update_x(i, st.j));
+      if (stop || kdef <= 0) {
+        st.fresh = true;                 // true residual next round
+        continue;
       }
-      if (k > 0) {
-        double* dy = pr.W.scal + 3 * (m + 2);
-        HIPCHK(hipMemcpyAsync(dy, st.y.data(), k * sizeof(double), hipMemcpyHostToDevice, B.s));
-        HIPCHK(launch_multiaxpy(st.V.vec(0), st.V.N, k, dy, 1.0, X(i), st.V.N, nullptr, st.V.nb,
-                                B.s));
-        HIPCHK(hipStreamSynchronize(B.s));
-        st.xzero = false;
+      // deflated restart (same step as the single-problem solver)
+      std::vector<double> rho(m + 1);
+      for (int r = 0; r <= m; ++r) {
+        double acc = st.c[r];
+        for (int q = 0; q < m; ++q) acc -= st.Hb[(size_t)r * m + q] * st.y[q];
+        rho[r] = acc;
       }
+      std::vector<std::complex<double>> theta;
+      std::vector<double> P, hnew, cnew;
+      int kk = 0;
+      std::string err;
+      if (deflation_step(m, st.Hb.data(), rho.data(), kdef, &theta, &P, &hnew, &cnew, &kk,
+                         &err) != 0) {
+        st.fresh = true;
+        continue;
+      }
+      HIPCHK(hipMemcpyAsync(pr.W.defl, P.data(), P.size() * sizeof(double),
+                            hipMemcpyHostToDevice, B.s));
+      HIPCHK(launch_basis_combine(st.V.vec(0), st.V.N, m + 1, kk + 1, pr.W.defl, st.V.N, B.s));
+      HIPCHK(hipStreamSynchronize(B.s));
+      std::fill(st.Hb.begin(), st.Hb.end(), 0.0);
+      std::fill(st.c.begin(), st.c.end(), 0.0);
+      for (int r = 0; r <= kk; ++r) {
+        st.c[r] = cnew[r];
+        for (int q = 0; q < kk; ++q) st.Hb[(size_t)r * m + q] = hnew[(size_t)r * kk + q];
+      }
+      st.ls.reset(m, st.c);
+      for (int q = 0; q < kk; ++q) st.ls.add_column(st.Hb, q, kk);
+      st.j = kk;
+      st.deflated += 1;
     }
   }
   int status = MFWH_OK;
@@ -2017,7 +2036,7 @@ int mfwh_solve_gmres_batched(int nprob, const mfwh_problem* probs, const mfwh_so
       infos[i].fell_back = S[i].fell_back;
       infos[i].implicit_solves = 0;
       infos[i].mg_cycles = 0;
-      infos[i].deflated_restarts = 0;
+      infos[i].deflated_restarts = S[i].deflated;
       infos[i].initial_rel_residual = S[i].init_rel;
       infos[i].initial_scale = S[i].scale;
     }

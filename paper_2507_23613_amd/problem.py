@@ -120,14 +120,16 @@ class GpuBatch:
             raise L.MfwhError(-1, "invalid batch")
         self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
 
-    def gmres(self, max_iter=1000, tol=1e-8, initial=None, zero_fallback=0, scale_initial=0):
-        """initial: optional list of device tensors (initial guesses)."""
+    def gmres(self, max_iter=1000, tol=1e-8, initial=None, zero_fallback=0, scale_initial=0,
+              deflate=0):
+        """initial: optional list of device tensors (initial guesses);
+        deflate > 0: GMRES-DR(restart, deflate) per problem."""
         for k, v in enumerate(self.v):
             if initial is None:
                 v.zero_()
             else:
                 v.copy_(initial[k])
         opts = L.make_opts(self.restart, max_iter, tol, zero_fallback=zero_fallback,
-                           scale_initial=scale_initial)
+                           scale_initial=scale_initial, deflate=deflate)
         infos, status = L.mfwh_solve_gmres_batched(self.problems, opts, self.ws)
         return self.v, infos, status

@@ -725,6 +725,24 @@ def test_batched_gmres_equals_single_solves(dim):
         assert infos[k]["latency_ms"] > 0
 
 
+@pytest.mark.parametrize("dim", [2, 3])
+def test_batched_deflated_gmres_equals_single_solves(dim):
+    """Deflated restarts per problem inside the batch: the same iterations
+    and solutions as the single-problem solver with the same options."""
+    from paper_2507_23613_amd.problem import GpuBatch
+    ws = _batch_workloads(dim)
+    gb = GpuBatch(ws, restart=8)
+    vs, infos, status = gb.gmres(max_iter=300, tol=1e-11, deflate=4)
+    for k, w in enumerate(ws):
+        gp = _gp(w, restart=8)
+        v1, info1 = gp.gmres(max_iter=300, tol=1e-11, deflate=4)
+        assert info1["converged"], info1
+        assert abs(infos[k]["iterations"] - info1["iterations"]) <= 1, (k, infos[k], info1)
+        assert rel(vs[k].cpu().numpy(), v1.cpu().numpy()) < 1e-10, k
+        if info1["iterations"] > 8:
+            assert infos[k]["deflated_restarts"] >= 1
+
+
 def test_batched_gmres_matches_direct():
     from paper_2507_23613_amd.problem import GpuBatch
     ws = _batch_workloads(2)
