@@ -36,6 +36,7 @@ Extra fields:
     python bench.py --mode bc        # Dirichlet data / Neumann faces at 1025^2
     python bench.py --mode fpi       # 100 fixed-point iterations of the 1D workload
     python bench.py --mode solve3d   # one full solve of the 3D 256^3 workload
+    python bench.py --mode gemm      # the warm-start network's BF16 MFMA GEMM shapes
     python bench.py --mode apply --applies 3   # a few forcing-free float64
                                      # applications of the same workload (for
                                      # rocprofv3: the step kernel as the solver runs it)
@@ -127,11 +128,11 @@ def batch_bench(args):
     from paper_2507_23613_amd.problem import GpuBatch, GpuProblem
     ws = inputs.config4(0)
     log(f"batch of {len(ws)} problems")
-    gb = GpuBatch(ws, restart=30)
+    gb = GpuBatch(ws, restart=args.restart)
     log(f"workspace {gb.ws.numel() / 2**30:.1f} GiB")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    _, infos, status = gb.gmres(max_iter=1500, tol=1e-8, deflate=15)
+    _, infos, status = gb.gmres(max_iter=args.max_iter, tol=args.tol, deflate=args.deflate)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     ps = sum(i["point_steps"] * len(w["omega"]) for i, w in zip(infos, ws))
@@ -142,15 +143,22 @@ def batch_bench(args):
            "latency_ms_p50": float(np.percentile(lat, 50)),
            "latency_ms_p99": float(np.percentile(lat, 99)),
            "iterations_max": max(i["iterations"] for i in infos),
-           "iterations_median": float(np.median([i["iterations"] for i in infos]))}
+           "iterations_median": float(np.median([i["iterations"] for i in infos])),
+           "gmres_restart": args.restart, "gmres_deflate": args.deflate,
+           "max_iter": args.max_iter}
+    for k, (i, w) in enumerate(zip(infos, ws)):
+        if not i["converged"]:
+            log(f"problem {k} ({w['shape'][0]}^2, N_f = {len(w['omega'])}): not converged, "
+                f"relative residual {i['rel_residual']:.2e} after {i['iterations']} iterations")
     log(json.dumps(out))
     del gb
     if args.sequential:
         t0 = time.perf_counter()
         ps1 = 0
         for k, w in enumerate(ws):
-            gp = GpuProblem(w, restart=30)
-            _, info = gp.gmres(restart=30, max_iter=1500, tol=1e-8, deflate=15)
+            gp = GpuProblem(w, restart=args.restart)
+            _, info = gp.gmres(restart=args.restart, max_iter=args.max_iter, tol=args.tol,
+                               deflate=args.deflate)
             ps1 += info["point_steps"] * len(w["omega"])
             if k % 8 == 7:
                 log(f"sequential: {k + 1} problems done")
@@ -164,24 +172,24 @@ def batch_bench(args):
 
 def warmstart_bench(args):
     """Config-5 study: 2D n^2 (default 256^2), N_f = 4, omega ~ U(20, 50),
-    Gaussian-sum forcings.  Train on float64 MFWH-GMRES solutions (1e-10) of
+    Gaussian-sum forcings.  Train on float64 MFWH-GMRES solutions (1e-9) of
     ``--train`` problems, test on ``--test`` held-out problems from a
-    disjoint seed stream: GMRES iterations (batched solver) and wall time to
-    1e-8 (single-problem solver, inference included) from the network's guess
-    with zero fallback against a zero start."""
+    disjoint seed stream: GMRES iterations and wall time to 1e-8 (single-
+    problem solver, deflated GMRES(30), inference included) from the
+    network's guess with zero fallback against a zero start."""
     import torch
     from paper_2507_23613_amd import _lib as L
     from paper_2507_23613_amd import inputs, warmstart
-    from paper_2507_23613_amd.problem import GpuBatch
     n = 256 if args.n == 1025 else args.n
     t0 = time.perf_counter()
     tr = inputs.config5(seed=1000, count=args.train, n=n)
     te = inputs.config5(seed=2000, count=args.test, n=n)
     log(f"drew {len(tr)} + {len(te)} problems ({time.perf_counter() - t0:.0f} s)")
-    F, OM, U, infos = warmstart.solve_set(tr, restart=64, tol=1e-10, max_iter=400, log=log)
+    F, OM, U, infos = warmstart.solve_set(tr, log=log)
     keep = torch.as_tensor([i for i, x in enumerate(infos) if x["converged"]], device=F.device)
     F, OM, U = F[keep], OM[keep], U[keep]
-    log(f"training set: {len(keep)} converged solutions ({time.perf_counter() - t0:.0f} s)")
+    gen_s = time.perf_counter() - t0
+    log(f"training set: {len(keep)} converged solutions ({gen_s:.0f} s)")
     model = warmstart.WarmStart(nf=4, H=n, W=n, batch=16)
     feats, targets = model.features(F, OM), model.targets(F, OM, U)
     del U
@@ -189,39 +197,24 @@ def warmstart_bench(args):
     hist = model.train(feats, targets, epochs=args.epochs, lr=1e-3, log=log)
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t1
-    del feats, targets
-    zero_its, warm_its, fell, init_res = [], [], 0, []
-    for s in range(0, len(te), 64):
-        part = te[s:s + 64]
-        gb = GpuBatch(part, restart=64)
-        _, i0, _ = gb.gmres(max_iter=800, tol=1e-8)
-        Fb = torch.stack([gp.f for gp in gb.items])
-        OMb = torch.stack([torch.as_tensor(gp.omega, device=gp.device) for gp in gb.items])
-        v0 = model.predict(Fb, OMb)
-        _, i1, _ = gb.gmres(max_iter=800, tol=1e-8, initial=[v0[k] for k in range(len(part))],
-                            zero_fallback=1, scale_initial=1)
-        zero_its += [x["iterations"] for x in i0]
-        warm_its += [x["iterations"] for x in i1]
-        fell += sum(x["fell_back"] for x in i1)
-        init_res += [x["initial_rel_residual"] for x in i1]
-        log(f"evaluated {min(s + 64, len(te))}/{len(te)}")
-        del gb
-    rows = warmstart.compare_solves(te[:args.compare], model, restart=64)
-    rows32 = warmstart.compare_solves(te[:min(4, args.compare)], model, restart=64,
-                                      precision=L.MFWH_FP32_STENCIL)
+    del feats, targets, F, OM
+    torch.cuda.empty_cache()
+    rows = warmstart.compare_solves(te, model, log=log)
+    zero_its = [r["zero_its"] for r in rows]
+    warm_its = [r["warm_its"] for r in rows]
     out = {"mode": "warmstart", "grid": [n, n], "train": int(len(keep)), "test": len(te),
-           "epochs": args.epochs, "train_s": round(train_s, 1),
-           "loss_first_last": [hist[0], hist[-1]],
+           "epochs": args.epochs, "data_generation_s": round(gen_s, 1),
+           "train_s": round(train_s, 1), "loss_first_last": [hist[0], hist[-1]],
            "iterations_zero_mean": float(np.mean(zero_its)),
            "iterations_warm_mean": float(np.mean(warm_its)),
            "iterations_zero_median": float(np.median(zero_its)),
            "iterations_warm_median": float(np.median(warm_its)),
-           "fallbacks": int(fell), "initial_rel_residual_median": float(np.median(init_res)),
-           "single_fp64_zero_s_mean": float(np.mean([r["zero_s"] for r in rows])),
-           "single_fp64_warm_s_mean": float(np.mean([r["warm_s"] for r in rows])),
-           "single_fp32_warm_s_mean": float(np.mean([r["warm_s"] for r in rows32])),
-           "single_fp32_warm_converged": int(sum(r["warm_conv"] for r in rows32)),
-           "single_compared": len(rows)}
+           "time_zero_s_mean": float(np.mean([r["zero_s"] for r in rows])),
+           "time_warm_s_mean": float(np.mean([r["warm_s"] for r in rows])),
+           "converged_zero": int(sum(r["zero_conv"] for r in rows)),
+           "converged_warm": int(sum(r["warm_conv"] for r in rows)),
+           "fallbacks": int(sum(r["fell_back"] for r in rows)),
+           "initial_rel_residual_median": float(np.median([r["warm_init_res"] for r in rows]))}
     print(json.dumps(out), flush=True)
 
 
@@ -389,6 +382,47 @@ def solve3d_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def gemm_bench(args):
+    """The warm-start network's BF16 MFMA GEMM on the forward shapes of its six
+    layers for a batch of 16 256^2 inputs (M = pixels, N = output channels,
+    K = 9 x input channels): event-timed TFLOP/s (2 M N K per call) against
+    the 2.5 PFLOP/s dense bf16 peak, and the bytes the call must move
+    (A, B read once, C written once) against the 8 TB/s HBM peak."""
+    import torch
+    from paper_2507_23613_amd import _lib as L
+    B, H, nf = 16, 256, 4
+    shapes = [(B * H * H, 32, 9 * 6 * nf), (B * 128 * 128, 64, 9 * 32), (B * 64 * 64, 64, 9 * 64),
+              (B * 128 * 128, 64, 9 * 64), (B * H * H, 32, 9 * 64), (B * H * H, nf, 9 * 32)]
+    rows = []
+    for M, N, K in shapes:
+        A = torch.randn(M, K, device="cuda").to(torch.bfloat16)
+        Bm = torch.randn(K, N, device="cuda").to(torch.bfloat16)
+        C = torch.empty(M, N, dtype=torch.float32, device="cuda")
+        part = torch.empty(1, dtype=torch.float32, device="cuda")
+        for _ in range(2):
+            L.mfwh_gemm_bf16(A.view(torch.int16), Bm.view(torch.int16), C, 0, M, N, K, K, N, N,
+                             part)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 10
+        e0.record()
+        for _ in range(reps):
+            L.mfwh_gemm_bf16(A.view(torch.int16), Bm.view(torch.int16), C, 0, M, N, K, K, N, N,
+                             part)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        tf = 2.0 * M * N * K / (ms * 1e-3) / 1e12
+        gbs = (2.0 * (M * K + K * N) + 4.0 * M * N) / (ms * 1e-3) / 1e9
+        rows.append({"M": M, "N": N, "K": K, "us": round(1e3 * ms, 1), "tflops": round(tf, 2),
+                     "mfma_frac": round(tf / 2500.0, 4), "GBps": round(gbs, 1),
+                     "hbm_frac": round(gbs / HBM_PEAK_GBS, 3)})
+        log(json.dumps(rows[-1]))
+        del A, Bm, C
+    print(json.dumps({"mode": "gemm", "kernel": "k_gemm_bf16 (v_mfma_f32_16x16x32_bf16)",
+                      "rows": rows}), flush=True)
+
+
 def fpi_bench(args):
     """The 1D workload (N = 201, order 2, omega = (5.3, 11.7), traditional
     filter, N_p = 1): 100 plain fixed-point iterations (Algorithm 1) from
@@ -472,14 +506,20 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--mode", default="solve",
                     choices=["solve", "copy", "apply", "batch", "warmstart", "implicit", "bc",
-                             "fpi", "solve3d"])
-    ap.add_argument("--restart", type=int, default=30, help="solve3d: GMRES restart length")
-    ap.add_argument("--deflate", type=int, default=15, help="solve3d: harmonic Ritz vectors kept")
-    ap.add_argument("--tol", type=float, default=1e-8, help="solve3d: relative residual")
-    ap.add_argument("--max-iter", type=int, default=1500, help="solve3d: Arnoldi steps")
+                             "fpi", "solve3d", "gemm"])
+    ap.add_argument("--restart", type=int, default=30,
+                    help="solve3d and batch modes: GMRES restart length")
+    ap.add_argument("--deflate", type=int, default=15,
+                    help="solve3d and batch modes: harmonic Ritz vectors kept")
+    ap.add_argument("--tol", type=float, default=1e-8,
+                    help="solve3d and batch modes: relative residual")
+    ap.add_argument("--max-iter", type=int, default=1500,
+                    help="solve3d and batch modes: Arnoldi steps")
     ap.add_argument("--fp32", action="store_true", help="solve3d: float32 stencil + refinement")
     ap.add_argument("--fp64", action="store_true",
                     help="apply mode, 3D workload: float64 stencil (default float32)")
+    ap.add_argument("--shape", default="",
+                    help="apply mode: launch shape override bx,by,chunk (mfwh_set_launch_shape)")
     ap.add_argument("--inner-tol", type=float, default=1e-3, help="solve3d: refinement inner tol")
     ap.add_argument("--inner-max-iter", type=int, default=0,
                     help="solve3d: Arnoldi steps per inner solve (0: no cap)")
@@ -536,6 +576,9 @@ def main():
     if args.mode == "solve3d":
         solve3d_bench(args)
         return
+    if args.mode == "gemm":
+        gemm_bench(args)
+        return
 
     if args.mode == "apply" and args.config == 3:
         w = inputs.config3(0)
@@ -558,6 +601,10 @@ def main():
         log(f"autotuned: {spp} steps per pass, launch shape {shape}")
 
     if args.mode == "apply":
+        if args.shape:
+            bx, by, ch = (int(x) for x in args.shape.split(","))
+            L.mfwh_set_launch_shape(bx, by, ch)
+            gp = GpuProblem(w, precision=prec, restart=0)      # set up with the shape
         v = torch.randn((nf,) + tuple(w["shape"]), dtype=torch.float64, device="cuda")
         out = torch.empty_like(v)
         for k in range(args.applies):

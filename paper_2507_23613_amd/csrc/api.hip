@@ -1186,6 +1186,22 @@ int gmres_core(Vecs& V, bool use32, const double* rhs, double* x, bool xzero, do
 // ---------------------------------------------------------------------------
 // batched problems: one step launch advances every active problem
 // ---------------------------------------------------------------------------
+struct BatchTables {
+  size_t ntab = 0;     // coefficient table doubles
+  size_t nargs = 0;    // bound on the multi-step path's argument records
+  size_t nstart = 0;   // bound on its prefix-sum entries
+};
+
+// One launch of the forcing-free multi-step path: the problems of one group
+// (same steps per pass and accumulator bound) at one global pass index.
+struct FastLaunch {
+  int steps = 0;
+  bool q4 = false;
+  int count = 0;               // problems in the launch
+  int total = 0;               // blocks over all of them
+  size_t args = 0, start = 0;  // offsets into the argument and prefix tables
+};
+
 struct Batch {
   int np = 0;
   std::vector<Problem*> pr;
@@ -1197,6 +1213,18 @@ struct Batch {
   LaunchShape ls;
   StepGraph sg[2];
   hipStream_t s = nullptr;
+  // forcing-free applications of 2D batches on the streamlined multi-step
+  // kernels: after the first step (one general batched launch), launch L
+  // runs every problem's L-th pass, grouped by kind
+  bool fast = false;
+  int fast_spp = 0;
+  LaunchShape fast_ls;
+  LeapArgs<double>* dfargs = nullptr;     // device
+  int* dfstart = nullptr;                 // device prefix sums
+  int* dfmap = nullptr;                   // device record -> problem
+  std::vector<std::vector<FastLaunch>> fl;
+  std::vector<int> fast_set;              // problems the recorded sequence covers
+  BatchTables tables;
   ~Batch() {
     for (auto& b : sg) {
       if (b.x) (void)hipGraphExecDestroy(b.x);
@@ -1206,20 +1234,27 @@ struct Batch {
   }
 };
 
-size_t batch_shared_bytes(int np, const size_t* ntab) {
+
+
+size_t batch_shared_bytes(int np, const BatchTables& t) {
   size_t b = 0;
   auto take = [&](size_t x) { b = (b + 255) / 256 * 256 + x; };
   take((size_t)np * sizeof(BatchProb<double>));
   take((size_t)np * sizeof(int));
-  take(*ntab * sizeof(double));
+  take(t.ntab * sizeof(double));
+  take(t.nargs * sizeof(LeapArgs<double>));
+  take(t.nstart * sizeof(int));
+  take(t.nargs * sizeof(int));
   return (b + 255) / 256 * 256;
 }
 
 // Per-problem workspace sizes and table size; validates the batch.
 int batch_sizes(int np, const mfwh_problem* P, int restart, std::vector<size_t>* sizes,
-                size_t* ntab) {
+                BatchTables* tb) {
   if (np < 1 || !P) return fail(MFWH_EINVAL, "empty batch");
-  *ntab = 0;
+  *tb = BatchTables{};
+  size_t* ntab = &tb->ntab;
+  long long maxpass = 0;
   sizes->clear();
   for (int i = 0; i < np; ++i) {
     Geom G;
@@ -1237,21 +1272,168 @@ int batch_sizes(int np, const mfwh_problem* P, int restart, std::vector<size_t>*
       return fail(MFWH_EINVAL, "bad frequency list");
     const long long nt = std::llround(P[i].time.T / P[i].time.dt);
     *ntab += (size_t)2 * (nt + 1) * P[i].time.nf;
+    // passes after the first step with at least two steps per pass, and at
+    // most two tail passes
+    const long long passes = (nt - 1) / 2 + 2;
+    tb->nargs += (size_t)passes;
+    maxpass = std::max(maxpass, passes);
     sizes->push_back(carve(G, P[i].time.nf, false, P[i].grid.c != nullptr, restart, nullptr).bytes);
   }
+  // one prefix entry per record plus one closing entry per launch group (at
+  // most six groups per pass index: three pass kinds, two accumulator bounds)
+  tb->nstart = tb->nargs + (size_t)6 * (size_t)maxpass;
+  return MFWH_OK;
+}
+
+// The forcing-free launch sequence of every problem on the streamlined 2D
+// kernels, the same passes (buffers, coefficients, tiling) as a single
+// problem's forcing-free application, grouped per global pass index.
+int batch_fast_setup(Batch& B, const BatchTables& tb, const std::vector<int>* only = nullptr) {
+  B.fast = false;
+  B.fl.clear();
+  B.tables = tb;
+  B.fast_set.assign(B.np, only ? 0 : 1);
+  if (only)
+    for (int i : *only) B.fast_set[i] = 1;
+  if (B.dim != 2) return MFWH_OK;
+  const int spp = g_steps_per_pass >= 0 ? g_steps_per_pass : 3;
+  if (spp < 2) return MFWH_OK;                     // general / one-step kernels chosen
+  LaunchShape ls{128, 1, 8};
+  if (g_shape_set) ls = g_shape_override;
+  if (spp >= 3 && ls.bx < 128) return MFWH_OK;
+  if (ls.bx != 64 && ls.bx != 128 && ls.bx != 256) return MFWH_OK;
+  // per problem: its passes after the first step
+  struct Pass { int kind; LeapArgs<double> a; };
+  std::vector<std::vector<Pass>> passes(B.np);
+  size_t maxl = 0;
+  for (int i = 0; i < B.np; ++i) {
+    if (!B.fast_set[i]) continue;                  // not in the recorded sequence
+    Problem& pr = *B.pr[i];
+    const Plan& P = pr.P;
+    const int nf = P.nf;
+    double* wa = pr.W.w64a;
+    double* wb = pr.W.w64b;
+    double* spare[2] = {pr.W.w64c, pr.W.w64d};
+    double* prev = wa;              // after the first step: W^1 in wb, W^0 in wa
+    double* cur = wb;
+    LeapArgs<double> la{};
+    la.c2 = pr.varc ? pr.W.c64 : nullptr;
+    la.f = nullptr;
+    la.q = pr.W.q;
+    la.g = pr.G;
+    double wx[3], wy[3], wz[3];
+    stencil_weights<double>(pr.grid, wx, wy, wz);
+    for (int k = 0; k < 3; ++k) {
+      la.wx[k] = wx[k];
+      la.wy[k] = wy[k];
+      la.wz[k] = wz[k];
+    }
+    la.force = 0;
+    la.nf = nf;
+    la.cA = 2.0;
+    la.cB = -1.0;
+    la.cC = P.dt * P.dt;
+    auto active = [&](int k, int m) { return P.kappa[(size_t)(k + 1) * nf + m] != 0.0; };
+    int n = 1;
+    while (n < P.nt) {
+      const int kind = (spp >= 3 && n + spp <= P.nt) ? spp : (n + 1 < P.nt) ? 2 : 1;
+      LeapArgs<double> a = la;
+      if (kind >= 2) {
+        a.wc = cur;
+        a.wp = prev;
+        a.w1 = spare[0];
+        a.w2 = spare[1];
+        spare[0] = prev;
+        spare[1] = cur;
+        prev = a.w1;
+        cur = a.w2;
+      } else {
+        a.wc = cur;
+        a.wp = prev;
+        a.w1 = prev;
+        a.w2 = nullptr;
+        prev = cur;
+        cur = a.w1;
+      }
+      int nq = 0;
+      for (int m = 0; m < MFWH_MAX_NF; ++m) {
+        a.phi1[m] = a.phi2[m] = 0.0;
+        for (int k = 0; k < 4; ++k) a.kk[k][m] = 0.0;
+        a.qm[m] = 0;
+      }
+      for (int m = 0; m < nf; ++m) {
+        bool on = false;
+        for (int k = 0; k < kind; ++k) on = on || active(n + k, m);
+        if (!on) continue;
+        a.qm[nq] = m;
+        for (int k = 0; k < kind; ++k) a.kk[k][nq] = P.kappa[(size_t)(n + 1 + k) * nf + m];
+        ++nq;
+      }
+      a.nq = nq;
+      for (int j = nq; j < MFWH_MAX_NF; ++j) a.qm[j] = nq > 0 ? a.qm[nq - 1] : 0;
+      leap2d_tiling(a, pr.grid->order, kind, ls);
+      passes[i].push_back(Pass{kind, a});
+      n += kind;
+    }
+    maxl = std::max(maxl, passes[i].size());
+  }
+  // group per pass index: (kind, accumulator bound)
+  std::vector<LeapArgs<double>> hargs;
+  std::vector<int> hstart, hmap;
+  B.fl.assign(maxl, {});
+  for (size_t L = 0; L < maxl; ++L) {
+    for (int kind = 1; kind <= 4; ++kind)
+      for (int q = 0; q < 2; ++q) {
+        FastLaunch f;
+        f.steps = kind;
+        f.q4 = q == 0;
+        f.args = hargs.size();
+        f.start = hstart.size();
+        int tot = 0;
+        for (int i = 0; i < B.np; ++i) {
+          if (L >= passes[i].size() || passes[i][L].kind != kind) continue;
+          const LeapArgs<double>& a = passes[i][L].a;
+          if ((a.nq <= 4) != f.q4) continue;
+          hargs.push_back(a);
+          hmap.push_back(i);
+          hstart.push_back(tot);
+          tot += a.nblocks;
+          ++f.count;
+        }
+        if (f.count == 0) {
+          hstart.resize(f.start);
+          continue;
+        }
+        hstart.push_back(tot);
+        f.total = tot;
+        B.fl[L].push_back(f);
+      }
+  }
+  if (hargs.size() > tb.nargs || hstart.size() > tb.nstart) return MFWH_OK;   // not sized for it
+  HIPCHK(hipMemcpyAsync(B.dfargs, hargs.data(), hargs.size() * sizeof(LeapArgs<double>),
+                        hipMemcpyHostToDevice, B.s));
+  HIPCHK(hipMemcpyAsync(B.dfstart, hstart.data(), hstart.size() * sizeof(int),
+                        hipMemcpyHostToDevice, B.s));
+  HIPCHK(hipMemcpyAsync(B.dfmap, hmap.data(), hmap.size() * sizeof(int), hipMemcpyHostToDevice,
+                        B.s));
+  HIPCHK(hipStreamSynchronize(B.s));               // the host tables go out of scope
+  B.fast = true;
+  B.fast_spp = spp;
+  B.fast_ls = ls;
   return MFWH_OK;
 }
 
 int batch_setup(Batch& B, int np, const mfwh_problem* P, int restart, void* ws, size_t ws_bytes,
                 void* stream) {
   std::vector<size_t> sizes;
-  size_t ntab;
-  CHK(batch_sizes(np, P, restart, &sizes, &ntab));
+  BatchTables tb;
+  CHK(batch_sizes(np, P, restart, &sizes, &tb));
+  const size_t ntab = tb.ntab;
   if (!ws) return fail(MFWH_EWORKSPACE, "null workspace");
   if (((uintptr_t)ws) % 256) return fail(MFWH_EWORKSPACE, "workspace must be 256-byte aligned");
   size_t total = 0;
   for (size_t b : sizes) total += b;
-  const size_t shared = batch_shared_bytes(np, &ntab);
+  const size_t shared = batch_shared_bytes(np, tb);
   if (total + shared > ws_bytes)
     return fail(MFWH_EWORKSPACE, "workspace too small: need " + std::to_string(total + shared));
   B.np = np;
@@ -1279,6 +1461,9 @@ int batch_setup(Batch& B, int np, const mfwh_problem* P, int restart, void* ws, 
   B.dprobs = (BatchProb<double>*)take((size_t)np * sizeof(BatchProb<double>));
   B.dactive = (int*)take((size_t)np * sizeof(int));
   B.dtab = (double*)take(ntab * sizeof(double));
+  B.dfargs = (LeapArgs<double>*)take(tb.nargs * sizeof(LeapArgs<double>));
+  B.dfstart = (int*)take(tb.nstart * sizeof(int));
+  B.dfmap = (int*)take(tb.nargs * sizeof(int));
   // launch shape shared by the batch: the override if set, else 64 lanes x 8 rows
   if (g_shape_set) B.ls = g_shape_override;
   else {
@@ -1320,6 +1505,7 @@ int batch_setup(Batch& B, int np, const mfwh_problem* P, int restart, void* ws, 
   HIPCHK(hipMemcpyAsync(B.dprobs, hp.data(), np * sizeof(BatchProb<double>),
                         hipMemcpyHostToDevice, B.s));
   HIPCHK(hipMemcpyAsync(B.dtab, tab.data(), ntab * sizeof(double), hipMemcpyHostToDevice, B.s));
+  CHK(batch_fast_setup(B, tb));
   HIPCHK(hipStreamSynchronize(B.s));
   B.hactive.assign(np, 0);
   return MFWH_OK;
@@ -1340,13 +1526,44 @@ int batch_apply(Batch& B, const std::vector<int>& act, const std::vector<const d
   HIPCHK(hipMemcpyAsync(B.dactive, B.hactive.data(), B.np * sizeof(int), hipMemcpyHostToDevice,
                         B.s));
   StepGraph& sg = B.sg[forcing ? 1 : 0];
+  if (!forcing && B.fast) {
+    // the recorded forcing-free sequence launches the passes of the problems
+    // it was built for; once fewer than half of them are still active, it is
+    // rebuilt for the active ones so that late rounds launch only their
+    // blocks and passes
+    int built = 0;
+    for (int f : B.fast_set) built += f;
+    bool covered = true;
+    for (int i : act) covered = covered && B.fast_set[i];
+    if (!covered || 2 * (int)act.size() < built) {
+      if (sg.x) (void)hipGraphExecDestroy(sg.x);
+      if (sg.g) (void)hipGraphDestroy(sg.g);
+      sg.x = nullptr;
+      sg.g = nullptr;
+      CHK(batch_fast_setup(B, B.tables, &act));
+      HIPCHK(hipStreamSynchronize(B.s));
+    }
+  }
   if (!sg.x) {
     hipStream_t cs;
     HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
     hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed);
-    for (int n = 0; n < B.maxnt && e == hipSuccess; ++n) {
-      BatchArgs<double> ba{B.dprobs, B.dactive, B.np, B.ntiles, n, forcing ? 1 : 0};
+    if (!forcing && B.fast) {
+      // the first step of every problem, then its streamlined passes
+      BatchArgs<double> ba{B.dprobs, B.dactive, B.np, B.ntiles, 0, 0};
       e = launch_step_batched<double>(ba, B.dim, B.order, B.ls, cs);
+      for (size_t L = 0; L < B.fl.size() && e == hipSuccess; ++L)
+        for (const FastLaunch& f : B.fl[L]) {
+          if (e != hipSuccess) break;
+          e = launch_leap2d_batched(B.dfargs + f.args, B.dfstart + f.start, B.dfmap + f.args,
+                                    B.dactive, f.count, f.total, B.order, f.steps, f.q4,
+                                    B.fast_ls, cs);
+        }
+    } else {
+      for (int n = 0; n < B.maxnt && e == hipSuccess; ++n) {
+        BatchArgs<double> ba{B.dprobs, B.dactive, B.np, B.ntiles, n, forcing ? 1 : 0};
+        e = launch_step_batched<double>(ba, B.dim, B.order, B.ls, cs);
+      }
     }
     hipError_t e2 = hipStreamEndCapture(cs, &sg.g);
     (void)hipStreamDestroy(cs);
@@ -1778,12 +1995,12 @@ int mfwh_solve_gmres(const mfwh_grid* g, const mfwh_time* t, const double* f, do
 
 size_t mfwh_workspace_bytes_batched(int nprob, const mfwh_problem* probs, int restart) {
   std::vector<size_t> sizes;
-  size_t ntab;
+  BatchTables tb;
   restart = std::max(0, std::min(restart, MFWH_MAX_RESTART));
-  if (batch_sizes(nprob, probs, restart, &sizes, &ntab) != MFWH_OK) return 0;
+  if (batch_sizes(nprob, probs, restart, &sizes, &tb) != MFWH_OK) return 0;
   size_t total = 0;
   for (size_t b : sizes) total += b;
-  return total + batch_shared_bytes(nprob, &ntab);
+  return total + batch_shared_bytes(nprob, tb);
 }
 
 int mfwh_solve_gmres_batched(int nprob, const mfwh_problem* probs, const mfwh_solve_opts* opts,

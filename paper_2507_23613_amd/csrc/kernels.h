@@ -119,6 +119,19 @@ struct LeapArgs {
 template <typename T>
 hipError_t launch_leap2d(LeapArgs<T>& a, int order, int steps, int depth, const LaunchShape& ls,
                          hipStream_t s);
+// Tiling fields (chunk, ntx, nchunk, nblocks) of one streamlined 2D pass of
+// `steps` steps with shape ls, as launch_leap2d sets them.
+void leap2d_tiling(LeapArgs<double>& a, int order, int steps, const LaunchShape& ls);
+// Forcing-free streamlined 2D passes of many problems in one launch: block b
+// runs record p's block b - start[p] with args[p] (device arrays: np
+// LeapArgs records, np + 1 prefix sums of their nblocks, np problem indices
+// map[p] into the activity flags `active`; a record whose problem's flag is
+// 0 is skipped).  steps 1..4 (3 and 4 need bx >= 128); every record's
+// nq <= 4 when q4; depth 4.
+hipError_t launch_leap2d_batched(const LeapArgs<double>* args, const int* start,
+                                 const int* map, const int* active, int np, int total_blocks,
+                                 int order, int steps, bool q4, const LaunchShape& ls,
+                                 hipStream_t s);
 // Default launch shapes of the streamlined kernels.
 LaunchShape default_leap_shape(const Geom& g, int steps);
 // leap3d.hip: one streamlined 3D step (z-march; shape 64 x 4 or 64 x 8) or

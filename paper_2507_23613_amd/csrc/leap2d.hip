@@ -79,10 +79,8 @@ struct Row2 {
 // one step
 // -------------------------------------------------------------------------
 template <typename T, int R, int BX, int QM, bool FORCE, int PD>
-__global__ void __launch_bounds__(BX) k_leap2d(LeapArgs<T> a) {
+__device__ __forceinline__ void leap1_body(const LeapArgs<T>& a, const int lb) {
   __shared__ T row[2][BX + 2 * R];
-  const int lb = xcd_tile(blockIdx.x, gridDim.x);
-  if (lb >= a.nblocks) return;
   const int bx = lb / a.nchunk;
   const int by = lb - bx * a.nchunk;
   const int tid = threadIdx.x;
@@ -185,11 +183,39 @@ __global__ void __launch_bounds__(BX) k_leap2d(LeapArgs<T> a) {
   }
 }
 
+template <typename T, int R, int BX, int QM, bool FORCE, int PD>
+__global__ void __launch_bounds__(BX) k_leap2d(LeapArgs<T> a) {
+  const int lb = xcd_tile(blockIdx.x, gridDim.x);
+  if (lb >= a.nblocks) return;
+  leap1_body<T, R, BX, QM, FORCE, PD>(a, lb);
+}
+
+// The same pass over many problems in one launch: block b runs record p's
+// block b - start[p] with record p's arguments (start: np + 1 prefix sums of
+// the records' block counts; record p belongs to problem map[p], skipped
+// when active[map[p]] == 0).
+template <typename T, int R, int BX, int QM, bool FORCE, int PD>
+__global__ void __launch_bounds__(BX) k_leap2d_batched(const LeapArgs<T>* __restrict__ args,
+                                                     const int* __restrict__ start,
+                                                     const int* __restrict__ map,
+                                                     const int* __restrict__ active, int np) {
+  const int gb = xcd_tile(blockIdx.x, gridDim.x);
+  if (gb >= start[np]) return;
+  int lo = 0, hi = np;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (start[mid] <= gb) lo = mid;
+    else hi = mid;
+  }
+  if (!active[map[lo]]) return;
+  leap1_body<T, R, BX, QM, FORCE, PD>(args[lo], gb - start[lo]);
+}
+
 // -------------------------------------------------------------------------
 // two steps per pass
 // -------------------------------------------------------------------------
 template <typename T, int R, int BX, int QM, bool FORCE, int PD, int CH>
-__global__ void __launch_bounds__(BX) k_leap2d_x2(LeapArgs<T> a) {
+__device__ __forceinline__ void x2_body(const LeapArgs<T>& a, const int lb) {
   constexpr int OW = BX - 4 * R;          // owned columns per block
   __shared__ T rn[2][BX];                 // W^n row of the first step
   __shared__ T r1[2][BX];                 // W^{n+1} row of the second step
@@ -217,8 +243,6 @@ __global__ void __launch_bounds__(BX) k_leap2d_x2(LeapArgs<T> a) {
     if constexpr (FORCE) return a.kk[st][j];
     else return kks[st][j];
   };
-  const int lb = xcd_tile(blockIdx.x, gridDim.x);
-  if (lb >= a.nblocks) return;
   const int bx = lb / a.nchunk;
   const int by = lb - bx * a.nchunk;
   const int l = threadIdx.x;
@@ -383,6 +407,34 @@ __global__ void __launch_bounds__(BX) k_leap2d_x2(LeapArgs<T> a) {
   }
 }
 
+template <typename T, int R, int BX, int QM, bool FORCE, int PD, int CH>
+__global__ void __launch_bounds__(BX) k_leap2d_x2(LeapArgs<T> a) {
+  const int lb = xcd_tile(blockIdx.x, gridDim.x);
+  if (lb >= a.nblocks) return;
+  x2_body<T, R, BX, QM, FORCE, PD, CH>(a, lb);
+}
+
+// The same pass over many problems in one launch: block b runs record p's
+// block b - start[p] with record p's arguments (start: np + 1 prefix sums of
+// the records' block counts; record p belongs to problem map[p], skipped
+// when active[map[p]] == 0).
+template <typename T, int R, int BX, int QM, bool FORCE, int PD, int CH>
+__global__ void __launch_bounds__(BX) k_leap2d_x2_batched(const LeapArgs<T>* __restrict__ args,
+                                                     const int* __restrict__ start,
+                                                     const int* __restrict__ map,
+                                                     const int* __restrict__ active, int np) {
+  const int gb = xcd_tile(blockIdx.x, gridDim.x);
+  if (gb >= start[np]) return;
+  int lo = 0, hi = np;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (start[mid] <= gb) lo = mid;
+    else hi = mid;
+  }
+  if (!active[map[lo]]) return;
+  x2_body<T, R, BX, QM, FORCE, PD, CH>(args[lo], gb - start[lo]);
+}
+
 // -------------------------------------------------------------------------
 // KS steps per pass, forcing-free (GMRES matvecs)
 // -------------------------------------------------------------------------
@@ -418,7 +470,7 @@ struct RowK {
 };
 
 template <typename T, int R, int BX, int QM, int KS, int PD, int CH>
-__global__ void __launch_bounds__(BX) k_leap2d_xk(LeapArgs<T> a) {
+__device__ __forceinline__ void xk_body(const LeapArgs<T>& a, const int lb) {
   using S = XkShape<R, KS>;
   constexpr int OW = BX - 2 * KS * R;
   __shared__ T lds[2][KS][BX];            // x-neighbour rows of levels 0 .. KS-1
@@ -429,8 +481,6 @@ __global__ void __launch_bounds__(BX) k_leap2d_xk(LeapArgs<T> a) {
   // cs[k] = wx_k, cs[R + k] = wy_k, then cA, cB, cC)
   __shared__ double kks[KS][QM];
   __shared__ T cs[2 * R + 4];
-  const int lb = xcd_tile(blockIdx.x, gridDim.x);
-  if (lb >= a.nblocks) return;
   const int bx = lb / a.nchunk;
   const int by = lb - bx * a.nchunk;
   const int l = threadIdx.x;
@@ -585,6 +635,34 @@ __global__ void __launch_bounds__(BX) k_leap2d_xk(LeapArgs<T> a) {
   }
 }
 
+template <typename T, int R, int BX, int QM, int KS, int PD, int CH>
+__global__ void __launch_bounds__(BX) k_leap2d_xk(LeapArgs<T> a) {
+  const int lb = xcd_tile(blockIdx.x, gridDim.x);
+  if (lb >= a.nblocks) return;
+  xk_body<T, R, BX, QM, KS, PD, CH>(a, lb);
+}
+
+// The same pass over many problems in one launch: block b runs record p's
+// block b - start[p] with record p's arguments (start: np + 1 prefix sums of
+// the records' block counts; record p belongs to problem map[p], skipped
+// when active[map[p]] == 0).
+template <typename T, int R, int BX, int QM, int KS, int PD, int CH>
+__global__ void __launch_bounds__(BX) k_leap2d_xk_batched(const LeapArgs<T>* __restrict__ args,
+                                                     const int* __restrict__ start,
+                                                     const int* __restrict__ map,
+                                                     const int* __restrict__ active, int np) {
+  const int gb = xcd_tile(blockIdx.x, gridDim.x);
+  if (gb >= start[np]) return;
+  int lo = 0, hi = np;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (start[mid] <= gb) lo = mid;
+    else hi = mid;
+  }
+  if (!active[map[lo]]) return;
+  xk_body<T, R, BX, QM, KS, PD, CH>(args[lo], gb - start[lo]);
+}
+
 template <typename T, int R, int BX, int PD>
 hipError_t launch_pd(LeapArgs<T>& a, int steps, int grid, hipStream_t s) {
   const bool fo = a.force != 0;
@@ -681,7 +759,80 @@ hipError_t launch_r(LeapArgs<T>& a, int steps, int depth, const LaunchShape& ls,
   }
 }
 
+template <int R, int BX, int QM>
+hipError_t launch_batched_bx(const LeapArgs<double>* args, const int* start, const int* map,
+                             const int* active, int np, int grid, int steps, int chunk,
+                             hipStream_t s) {
+  if (steps >= 3) {
+    if constexpr (BX >= 128) {
+      const bool ch8 = BX == 128 && chunk == 8;
+      if (steps == 3) {
+        if (ch8) k_leap2d_xk_batched<double, R, BX, QM, 3, 4, 8><<<grid, BX, 0, s>>>(args, start, map, active, np);
+        else k_leap2d_xk_batched<double, R, BX, QM, 3, 4, 0><<<grid, BX, 0, s>>>(args, start, map, active, np);
+      } else {
+        if (ch8) k_leap2d_xk_batched<double, R, BX, QM, 4, 4, 8><<<grid, BX, 0, s>>>(args, start, map, active, np);
+        else k_leap2d_xk_batched<double, R, BX, QM, 4, 4, 0><<<grid, BX, 0, s>>>(args, start, map, active, np);
+      }
+      return hipGetLastError();
+    }
+    return hipErrorInvalidValue;
+  }
+  if (steps == 2) {
+    if constexpr (BX <= 128) {
+      if (chunk == 4) k_leap2d_x2_batched<double, R, BX, QM, false, 4, 4><<<grid, BX, 0, s>>>(args, start, map, active, np);
+      else if (chunk == 8) k_leap2d_x2_batched<double, R, BX, QM, false, 4, 8><<<grid, BX, 0, s>>>(args, start, map, active, np);
+      else if (chunk == 16) k_leap2d_x2_batched<double, R, BX, QM, false, 4, 16><<<grid, BX, 0, s>>>(args, start, map, active, np);
+      else k_leap2d_x2_batched<double, R, BX, QM, false, 4, 0><<<grid, BX, 0, s>>>(args, start, map, active, np);
+    } else {
+      k_leap2d_x2_batched<double, R, BX, QM, false, 4, 0><<<grid, BX, 0, s>>>(args, start, map, active, np);
+    }
+    return hipGetLastError();
+  }
+  k_leap2d_batched<double, R, BX, QM, false, 4><<<grid, BX, 0, s>>>(args, start, map, active, np);
+  return hipGetLastError();
+}
+
+template <int R, int BX>
+hipError_t launch_batched_q(const LeapArgs<double>* args, const int* start, const int* map,
+                            const int* active, int np, int grid, int steps, int chunk, bool q4,
+                            hipStream_t s) {
+  return q4 ? launch_batched_bx<R, BX, 4>(args, start, map, active, np, grid, steps, chunk, s)
+            : launch_batched_bx<R, BX, 8>(args, start, map, active, np, grid, steps, chunk, s);
+}
+
 }  // namespace
+
+void leap2d_tiling(LeapArgs<double>& a, int order, int steps, const LaunchShape& ls) {
+  const int R = order == 2 ? 1 : 2;
+  a.chunk = std::max(1, ls.chunk);
+  const int ow = steps >= 2 ? ls.bx - 2 * steps * R : ls.bx;
+  a.ntx = (a.g.nxi + ow - 1) / ow;
+  a.nchunk = (a.g.nyi + a.chunk - 1) / a.chunk;
+  a.nblocks = a.ntx * a.nchunk;
+}
+
+hipError_t launch_leap2d_batched(const LeapArgs<double>* args, const int* start,
+                                 const int* map, const int* active, int np, int total_blocks,
+                                 int order, int steps, bool q4, const LaunchShape& ls,
+                                 hipStream_t s) {
+  if (total_blocks <= 0) return hipSuccess;
+  const int grid = pad8(total_blocks);
+  const int chunk = std::max(1, ls.chunk);
+  const int R = order == 2 ? 1 : 2;
+  switch (ls.bx) {
+    case 64:
+      return R == 1 ? launch_batched_q<1, 64>(args, start, map, active, np, grid, steps, chunk, q4, s)
+                    : launch_batched_q<2, 64>(args, start, map, active, np, grid, steps, chunk, q4, s);
+    case 128:
+      return R == 1 ? launch_batched_q<1, 128>(args, start, map, active, np, grid, steps, chunk, q4, s)
+                    : launch_batched_q<2, 128>(args, start, map, active, np, grid, steps, chunk, q4, s);
+    case 256:
+      return R == 1 ? launch_batched_q<1, 256>(args, start, map, active, np, grid, steps, chunk, q4, s)
+                    : launch_batched_q<2, 256>(args, start, map, active, np, grid, steps, chunk, q4, s);
+    default:
+      return hipErrorInvalidValue;
+  }
+}
 
 template <typename T>
 hipError_t launch_leap2d(LeapArgs<T>& a, int order, int steps, int depth, const LaunchShape& ls,

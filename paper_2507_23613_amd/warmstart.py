@@ -30,22 +30,37 @@ def he_init(nf, seed=0):
     return p
 
 
-def solve_set(workloads, restart=64, tol=1e-10, max_iter=800, chunk=64, log=None):
-    """Solve every workload with batched float64 GMRES.  Returns device
-    tensors F [N][nf][H][W], OM [N][nf], U [N][nf][H][W] and the infos."""
+def solve_set(workloads, restart=30, deflate=15, tol=1e-9, max_iter=1500, batched=False,
+              chunk=64, log=None, every=100):
+    """Solve every workload with float64 GMRES (deflated restarts), one problem
+    at a time on the multi-step kernels, or with the batched solver.  Returns
+    device tensors F [N][nf][H][W], OM [N][nf], U [N][nf][H][W] and the
+    infos."""
     F, OM, U, infos = [], [], [], []
-    for s in range(0, len(workloads), chunk):
-        part = workloads[s:s + chunk]
-        gb = GpuBatch(part, restart=restart)
-        vs, inf, _ = gb.gmres(max_iter=max_iter, tol=tol)
-        for gp, v, i in zip(gb.items, vs, inf):
+    if batched:
+        for s in range(0, len(workloads), chunk):
+            part = workloads[s:s + chunk]
+            gb = GpuBatch(part, restart=restart)
+            vs, inf, _ = gb.gmres(max_iter=max_iter, tol=tol, deflate=deflate)
+            for gp, v, i in zip(gb.items, vs, inf):
+                F.append(gp.f)
+                OM.append(torch.as_tensor(gp.omega, device=gp.device))
+                U.append(v.clone())
+                infos.append(i)
+            del gb
+            if log:
+                log(f"solved {min(s + chunk, len(workloads))}/{len(workloads)}")
+    else:
+        for k, w in enumerate(workloads):
+            gp = GpuProblem(w, restart=restart)
+            v, i = gp.gmres(max_iter=max_iter, tol=tol, deflate=deflate)
             F.append(gp.f)
             OM.append(torch.as_tensor(gp.omega, device=gp.device))
-            U.append(v.clone())
+            U.append(v)
             infos.append(i)
-        del gb
-        if log:
-            log(f"solved {min(s + chunk, len(workloads))}/{len(workloads)}")
+            del gp
+            if log and (k + 1) % every == 0:
+                log(f"solved {k + 1}/{len(workloads)}")
     return torch.stack(F), torch.stack(OM), torch.stack(U), infos
 
 
@@ -118,25 +133,30 @@ class WarmStart:
         return v
 
 
-def compare_solves(ws, model, restart=64, tol=1e-8, max_iter=800, precision=L.MFWH_FP64):
+def compare_solves(ws, model, restart=30, deflate=15, tol=1e-8, max_iter=1500,
+                   precision=L.MFWH_FP64, log=None, every=50):
     """Solve each workload from zero and from the network's guess (single-problem
-    solver, zero fallback on); wall times include the network inference."""
+    solver, deflated restarts, zero fallback on); wall times include the
+    network inference."""
     rows = []
-    for w in ws:
+    for k, w in enumerate(ws):
         gp = GpuProblem(w, precision=precision, restart=restart)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        _, i0 = gp.gmres(max_iter=max_iter, tol=tol)
+        _, i0 = gp.gmres(max_iter=max_iter, tol=tol, deflate=deflate)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         F = gp.f.unsqueeze(0)
         OM = torch.as_tensor(gp.omega, device=gp.device).unsqueeze(0)
         v0 = model.predict(F, OM)[0].contiguous()
-        _, i1 = gp.gmres(v=v0, max_iter=max_iter, tol=tol, zero_fallback=1, scale_initial=1)
+        _, i1 = gp.gmres(v=v0, max_iter=max_iter, tol=tol, zero_fallback=1, scale_initial=1,
+                         deflate=deflate)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         rows.append(dict(zero_its=i0["iterations"], zero_s=t1 - t0, zero_conv=i0["converged"],
                          warm_its=i1["iterations"], warm_s=t2 - t1, warm_conv=i1["converged"],
                          fell_back=i1["fell_back"], warm_init_res=i1["initial_rel_residual"]))
         del gp
+        if log and (k + 1) % every == 0:
+            log(f"compared {k + 1}/{len(ws)}")
     return rows

@@ -107,13 +107,25 @@ def test_apply_fp64(case, forcing):
 
 @pytest.mark.parametrize("case", APPLY_CASES, ids=_id)
 def test_apply_fp32_stencil(case):
+    """Float32-stencil application against the float64 oracle.  Two measures:
+    the output V' = B^{-1} q (bar tol32, which scales with cond(B)), and the
+    filtered fields q = B V' themselves, before B^{-1} amplifies their
+    rounding (bar 8 eps32 N_t: the float32 rounding of W accumulated over the
+    N_t steps, with no cond(B) factor)."""
     w = inputs.small(**case)
     gp = _gp(w, precision=1)
     prob, pl = workload.setup(w)
     V = rand_v(w["shape"], case["nf"], 101)
     out = gp.apply(torch.as_tensor(V, device="cuda"), forcing=True).cpu().numpy()
     ref = omf.apply(prob, pl, w["f"], V, True)
-    assert rel(out, ref) < tol32(pl)
+    qo = np.tensordot(pl.B, out, axes=(1, 0))
+    qr = np.tensordot(pl.B, ref, axes=(1, 0))
+    e_v, e_q = rel(out, ref), rel(qo, qr)
+    bar_q = max(1e-5, 8 * EPS32 * pl.nt)
+    print(f"fp32 {_id(case)}: N_t={pl.nt} cond(B)={np.linalg.cond(pl.B):.1f} "
+          f"V' {e_v:.2e} (bar {tol32(pl):.1e})  q {e_q:.2e} (bar {bar_q:.1e})")
+    assert e_v < tol32(pl)
+    assert e_q < bar_q
 
 
 SHAPES_2D = [(64, 1, 1), (64, 1, 5), (128, 1, 3), (256, 1, 8), (128, 1, 64)]
