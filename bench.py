@@ -60,8 +60,8 @@ HBM_PEAK_GBS = 8000.0
 # profiles/k_leap2d_xk4_fp64_2d-n1025-nf4.md).  Keyed by (steps per pass, bx,
 # chunk) and valid only for the kernel source it was measured on: reported
 # as null for another configuration or once leap2d.hip changes.
-TRAFFIC = {"leap2d_sha256_16": "b0c3f37fc386cd5e",
-           "bytes": {(4, 128, 8): 32904.5 * 1024 * 2.0 + 48688.1 * 1024 * 1.0}}
+TRAFFIC = {"leap2d_sha256_16": "b3614863954f88b3",
+           "bytes": {(4, 128, 8): 32908.4 * 1024 * 2.0 + 48688.2 * 1024 * 1.0}}
 
 
 def measured_traffic(cfg):
@@ -176,7 +176,9 @@ def warmstart_bench(args):
     ``--train`` problems, test on ``--test`` held-out problems from a
     disjoint seed stream: GMRES iterations and wall time to 1e-8 (single-
     problem solver, deflated GMRES(30), inference included) from the
-    network's guess with zero fallback against a zero start."""
+    network's guess with zero fallback against a zero start.  ``--batched``
+    solves the training set (to 1e-8) and both test runs 64 problems at a time
+    with the batched solver."""
     import torch
     from paper_2507_23613_amd import _lib as L
     from paper_2507_23613_amd import inputs, warmstart
@@ -185,7 +187,8 @@ def warmstart_bench(args):
     tr = inputs.config5(seed=1000, count=args.train, n=n)
     te = inputs.config5(seed=2000, count=args.test, n=n)
     log(f"drew {len(tr)} + {len(te)} problems ({time.perf_counter() - t0:.0f} s)")
-    F, OM, U, infos = warmstart.solve_set(tr, log=log)
+    F, OM, U, infos = warmstart.solve_set(tr, batched=args.batched,
+                                          tol=1e-8 if args.batched else 1e-9, log=log)
     keep = torch.as_tensor([i for i, x in enumerate(infos) if x["converged"]], device=F.device)
     F, OM, U = F[keep], OM[keep], U[keep]
     gen_s = time.perf_counter() - t0
@@ -199,10 +202,12 @@ def warmstart_bench(args):
     train_s = time.perf_counter() - t1
     del feats, targets, F, OM
     torch.cuda.empty_cache()
-    rows = warmstart.compare_solves(te, model, log=log)
+    rows = (warmstart.compare_batched(te, model, log=log) if args.batched
+            else warmstart.compare_solves(te, model, log=log))
     zero_its = [r["zero_its"] for r in rows]
     warm_its = [r["warm_its"] for r in rows]
     out = {"mode": "warmstart", "grid": [n, n], "train": int(len(keep)), "test": len(te),
+           "train_solved": len(tr), "batched_data": bool(args.batched),
            "epochs": args.epochs, "data_generation_s": round(gen_s, 1),
            "train_s": round(train_s, 1), "loss_first_last": [hist[0], hist[-1]],
            "iterations_zero_mean": float(np.mean(zero_its)),
@@ -305,8 +310,9 @@ def roofline_3d(precision):
     torch.cuda.empty_cache()
     return {"workload": w["name"] + ("-fp64" if precision == L.MFWH_FP64 else "-fp32-stencil"),
             "nt": nt,
-            "kernel": f"k_leap3d_x3<{tname}, order 2, 64x16, chunk 16>: 3 fused leapfrog steps "
-                      "+ 8 filter updates per launch (forcing-free)",
+            "kernel": f"k_leap3d_x3r<{tname}, order 2, 48x10 tiles aligned to 128 B on 64x16 "
+                      "lanes, 32-plane chunks>: 3 fused leapfrog steps + 8 filter updates per "
+                      "launch (forcing-free)",
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "bytes_per_point_per_launch": per_pass,
@@ -530,13 +536,16 @@ def main():
     ap.add_argument("--compare", type=int, default=16,
                     help="warmstart mode: test problems timed one at a time")
     ap.add_argument("--no-tune", action="store_true", help="skip the launch-shape autotuner")
+    ap.add_argument("--batched", action="store_true",
+                    help="warmstart mode: solve the training set with the batched solver")
     ap.add_argument("--sequential", action="store_true",
                     help="batch mode: also solve the problems one at a time")
     ap.add_argument("--applies", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-fp32", action="store_true", help="skip the float32-stencil solve")
     ap.add_argument("--no-3d", action="store_true", help="skip the 3D 256^3 kernel rate")
-    ap.add_argument("--n", type=int, default=1025, help="grid points per axis")
+    ap.add_argument("--n", type=int, default=1025,
+                    help="grid points per axis (apply mode with --config 3: 3D grid, default 256)")
     ap.add_argument("--config", type=int, default=2, choices=[2, 3],
                     help="apply mode: the 2D 1025^2 workload (float64) or the 3D 256^3 "
                          "workload (float32 stencil, variable c, 8 frequencies)")
@@ -581,7 +590,7 @@ def main():
         return
 
     if args.mode == "apply" and args.config == 3:
-        w = inputs.config3(0)
+        w = inputs.config3(0, n=256 if args.n == 1025 else args.n)
         prec = L.MFWH_FP64 if args.fp64 else L.MFWH_FP32_STENCIL
     else:
         w = inputs.config2(0, n=args.n)

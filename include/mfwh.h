@@ -447,7 +447,10 @@ int mfwh_stats_read(long long* launches, double* total_ms, double* total_bytes);
  * streamlined 2D kernels take 64, 128 or 256), by threads along y (3D: 4, 8
  * or 2 with bx 64/64/128; 8 with bx 32), chunk rows (2D) or planes (3D)
  * marched per block.  In 3D a shape with by = 16 (bx 64 or 32) sets only the
- * multi-step kernels (two and three steps per launch); 64 x 8 sets every
+ * multi-step kernels (two and three steps per launch); 48 x 16 selects the
+ * three-step kernel over 128-byte-aligned 48 x 10 column tiles (64 x 16
+ * lanes; its two-step passes take 64 x 16) and is ignored by every other
+ * kernel and by 2D problems; 64 x 8 sets every
  * kernel with order 2 except the three-step one (the two-step kernel then
  * owns 60 x 4 columns per block, and three steps per pass fall back to two);
  * any other shape sets the one-step kernels (and the multi-step kernels keep

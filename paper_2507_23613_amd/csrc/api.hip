@@ -318,6 +318,12 @@ struct Problem {
 };
 
 LaunchShape g_shape_override;   // bx == 0: use defaults
+// shapes of the three-step 3D kernels: 64 x 16 and 32 x 16 lanes with
+// 58- and 26-column tiles, and 48 x 16, which names 64 x 16 lanes over
+// 128-byte-aligned 48-column tiles (three-step 3D passes only)
+bool x3_shape(const LaunchShape& o) {
+  return o.by == 16 && (o.bx == 64 || o.bx == 32 || o.bx == 48);
+}
 bool g_shape_set = false;
 bool g_graphs = true;           // solvers record step sequences into graphs
 int g_steps_per_pass = -1;      // steps per pass (MFWH_OPT_STEPS_PER_PASS; -1: automatic)
@@ -370,14 +376,14 @@ int setup(Problem& pr, const mfwh_grid* g, const mfwh_time* t, int restart, void
   pr.spp = pr.G.dim == 2 ? want : pr.G.dim == 3 ? std::min(want, spp_max3) : 0;
   if (pr.refl) pr.spp = 0;   // Neumann / Robin faces: general step kernels
   pr.depth = g_depth;
-  pr.leap = pr.G.dim == 3 ? default_leap3d_shape(pr.G, pr.spp, g->order)
+  pr.leap = pr.G.dim == 3 ? default_leap3d_shape(pr.G, pr.spp, g->order, pr.fp32)
                           : default_leap_shape(pr.G, pr.spp);
-  pr.leap1 = default_leap3d_shape(pr.G, 1, g->order);
+  pr.leap1 = default_leap3d_shape(pr.G, 1, g->order, pr.fp32);
   if (g_shape_set) {
     const LaunchShape& o = g_shape_override;
-    if (pr.G.dim == 3 && o.by == 16) {
+    if (pr.G.dim == 3 && x3_shape(o)) {
       pr.leap = o;             // multi-step 3D shape: the other kernels keep theirs
-    } else {
+    } else if (o.bx != 48) {   // (48 names a three-step 3D tile only)
       pr.shape64 = pr.shape32 = pr.leap1 = o;
       // 64 x 8 also suits the two-step 3D kernel with order 2
       if (!(pr.G.dim == 3 && pr.spp >= 2) || (o.bx == 64 && o.by == 8 && g->order == 2))
@@ -388,7 +394,7 @@ int setup(Problem& pr, const mfwh_grid* g, const mfwh_time* t, int restart, void
   // three- and four-step 2D kernels need bx >= 128, the three-step 3D kernel
   // by = 16
   if (pr.G.dim == 2 && pr.spp >= 3 && pr.leap.bx < 128) pr.spp = 2;
-  if (pr.G.dim == 3 && pr.spp == 3 && pr.leap.by != 16) pr.spp = 2;
+  if (pr.G.dim == 3 && pr.spp == 3 && !x3_shape(pr.leap)) pr.spp = 2;
   if (pr.implicit) {
     pr.W.lev[0].c2 = pr.varc ? pr.W.c64 : nullptr;
     pr.W.mx[0] = nullptr;   // level 0 solves in place in the W buffers
@@ -2324,7 +2330,8 @@ int mfwh_set_launch_shape(int bx, int by, int chunk) {
     g_shape_set = false;
     return MFWH_OK;
   }
-  if (!((bx == 64 || bx == 128 || bx == 256 || bx == 32) && by >= 1 && chunk >= 1))
+  if (!((bx == 64 || bx == 128 || bx == 256 || bx == 32 || (bx == 48 && by == 16)) && by >= 1 &&
+        chunk >= 1))
     return fail(MFWH_EINVAL, "bad launch shape");
   g_shape_override.bx = bx;
   g_shape_override.by = by;

@@ -139,7 +139,7 @@ LaunchShape default_leap_shape(const Geom& g, int steps);
 template <typename T>
 hipError_t launch_leap3d(LeapArgs<T>& a, int order, int steps, const LaunchShape& ls,
                          hipStream_t s);
-LaunchShape default_leap3d_shape(const Geom& g, int steps, int order);
+LaunchShape default_leap3d_shape(const Geom& g, int steps, int order, bool fp32);
 
 // mg2d.hip: implicit trapezoid steps and their multigrid solver (2D, float64)
 // One multigrid level: interior nx x ny points at row pitch py; the operator

@@ -557,6 +557,259 @@ __global__ void __launch_bounds__(BX * BY) k_leap3d_x3(LeapArgs<T> a) {
   }
 }
 
+// Three steps per pass with RY rows per lane (order 2, forcing-free): the
+// scheme of k_leap3d_x3 on a taller tile.  A 64 x BYT block covers 64 x
+// (BYT * RY) columns; lane (lx, ly) holds rows ly + BYT * r (r < RY), so a
+// block owns OX x (BYT * RY - 6) columns and its W^n, W^{n-1}, c^2
+// footprint shrinks towards the owned tile as the tile grows.  With
+// OX = 48 the owned x-range of every tile starts on a 128-byte boundary of
+// the float64 accumulator rows (row pitches are multiples of 64 elements),
+// so no accumulator line is shared by two tiles; lanes past OX + 6 mirror
+// the last live column and never store.  The four planes a chunk computes
+// before its first owned plane read no accumulators.  Every access is a
+// wave-uniform plane base plus a per-lane 32-bit byte offset fixed for the
+// whole march (an in-plane offset: planes hold fewer than 2^29 points), so
+// addresses cost one register per row.  Accumulators are fetched with the
+// other operands of the next plane when QPF, else at the start of their
+// own plane (fewer registers).
+template <typename U>
+__device__ __forceinline__ U ld_off(const U* base, uint32_t off) {
+  return *reinterpret_cast<const U*>(reinterpret_cast<const char*>(base) + off);
+}
+template <typename U>
+__device__ __forceinline__ void st_off(U* base, uint32_t off, U v) {
+  *reinterpret_cast<U*>(reinterpret_cast<char*>(base) + off) = v;
+}
+
+template <typename T, int RY, int QM, bool QPF>
+struct Plane3R {
+  T w[RY], sw[RY];           // new W^n values (plane z + 3) and factors
+  T p[RY], c[RY];            // W^{n-1}, c^2 on plane z + 2
+  double q[QPF ? RY : 1][QPF ? QM : 1];   // accumulators on plane z (QPF)
+};
+
+template <typename T, int BYT, int RY, int OX, int QM, bool QPF, int MINW>
+__global__ void __attribute__((amdgpu_flat_work_group_size(64 * BYT, 64 * BYT),
+                               amdgpu_waves_per_eu(MINW)))
+k_leap3d_x3r(LeapArgs<T> a) {
+  constexpr int BX = 64, H = 3;
+  constexpr int BY = BYT * RY;
+  constexpr int LW = OX + 2 * H;          // live lanes per row
+  constexpr int OY = BY - 2 * H;
+  static_assert(LW <= BX && OY > 0, "tile");
+  __shared__ T p0[2][BY][BX];             // W^n on plane z + 2
+  __shared__ T p1[2][BY][BX];             // W^{n+1} on plane z + 1
+  __shared__ T p2[2][BY][BX];             // W^{n+2} on plane z
+  __shared__ double kks[3][QM];
+  __shared__ T cs[7];
+  const int lb = xcd_tile3(blockIdx.x, gridDim.x);
+  if (lb >= a.nblocks) return;
+  const int cz = lb % a.nchunk;
+  const int t2 = lb / a.nchunk;
+  const int tx = t2 % a.ntx;
+  const int ty = t2 / a.ntx;
+  const int lx = threadIdx.x, ly = threadIdx.y;
+  {
+    const int t = ly * BX + lx;
+    if (t < 3 * QM) kks[t / QM][t % QM] = a.kk[t / QM][t % QM];
+    if (t < 7)
+      cs[t] = t == 0 ? a.wx[0] + a.wy[0] + a.wz[0]
+            : t == 1 ? a.wx[1]
+            : t == 2 ? a.wy[1]
+            : t == 3 ? a.wz[1]
+            : t == 4 ? a.cA
+            : t == 5 ? a.cB
+                     : a.cC;
+  }
+  const int nxi = a.g.nxi, nyi = a.g.nyi, nzi = a.g.nzi;
+  const long long py = a.g.py, pz = a.g.pz, fs = a.g.fs;
+  const int x0 = tx * OX, y0 = ty * OY;
+  const int ex = x0 - H + min(lx, LW - 1);
+  T sx;
+  const int ix = ext_src3(ex, nxi, sx);
+  const bool xin = ex >= 0 && ex < nxi;
+  const int qx = min(max(ex, x0), min(x0 + OX, nxi) - 1);
+  auto inx = [&](int m) { return lx >= m && lx < LW - m; };
+  int yl[RY];
+  T sxy[RY];
+  uint32_t co[RY];     // byte offset of the lane's column in a T plane
+  uint32_t qo[RY];     // byte offset of its owned column in a float64 plane
+  uint32_t oo[RY];     // byte offset of its (owned) column in a T plane
+  bool m1[RY], m2[RY], own[RY], qrow[RY];
+#pragma unroll
+  for (int r = 0; r < RY; ++r) {
+    yl[r] = ly + BYT * r;
+    const int ey = y0 - H + yl[r];
+    T sy;
+    const int iy = ext_src3(ey, nyi, sy);
+    sxy[r] = sx * sy;
+    const bool in = xin && ey >= 0 && ey < nyi;
+    auto iny = [&](int m) { return yl[r] >= m && yl[r] < BY - m; };
+    m1[r] = in && inx(1) && iny(1);
+    m2[r] = in && inx(2) && iny(2);
+    own[r] = in && inx(3) && iny(3);
+    qrow[r] = iny(H);
+    co[r] = (uint32_t)((iy * py + ix) * (long long)sizeof(T));
+    const int qy = min(max(ey, y0), min(y0 + OY, nyi) - 1);
+    const long long qc = qy * py + qx;          // = the lane's own column when own[r]
+    qo[r] = (uint32_t)(qc * 8);
+    oo[r] = (uint32_t)(qc * (long long)sizeof(T));
+  }
+  const T* __restrict__ c2p = a.c2 ? a.c2 : a.wp;       // read and ignored when c = 1
+  const int z0 = cz * a.chunk;
+  const int z1 = min(z0 + a.chunk, nzi);
+  const T* __restrict__ wc = a.wc;
+  auto step = [&](T ce, const T (*pl)[BX], int y, T zm, T zp, T pv, T cc) {
+    const int cx = min(max(lx, 1), BX - 2), cy = min(max(y, 1), BY - 2);
+    const T lap = cs[0] * ce + cs[1] * (pl[cy][cx - 1] + pl[cy][cx + 1]) +
+                  cs[2] * (pl[cy - 1][cx] + pl[cy + 1][cx]) + cs[3] * (zm + zp);
+    return cs[4] * ce + cs[5] * pv + cs[6] * (cc * lap);
+  };
+
+  T wn[RY][3];         // W^n on planes z+1 .. z+3 at iteration z
+  T w1[RY][3];         // W^{n+1} on planes z .. z+2
+  T w2[RY][3];         // W^{n+2} on planes z-1 .. z+1
+  T cw[RY][3];         // c^2 on planes z .. z+2
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    T sz;
+    const int iz = ext_src3(z0 - 3 + k, nzi, sz);
+    const T* pl = wc + iz * pz;
+#pragma unroll
+    for (int r = 0; r < RY; ++r) wn[r][k + 1] = sxy[r] * sz * ld_off(pl, co[r]);
+  }
+#pragma unroll
+  for (int r = 0; r < RY; ++r)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      w1[r][k] = T(0);
+      w2[r][k] = T(0);
+      cw[r][k] = T(1);
+    }
+
+  using P = Plane3R<T, RY, QM, QPF>;
+  auto loadq = [&](double (*qv)[QM], int z) {
+#pragma unroll
+    for (int q = 0; q < QM; ++q) {
+      const double* qp = a.q + a.qm[q] * fs + z * pz;
+#pragma unroll
+      for (int r = 0; r < RY; ++r)
+        if (qrow[r]) qv[r][q] = ld_off(qp, qo[r]);
+    }
+  };
+  auto fetch = [&](P& o, int z, bool withq) {
+    T sz;
+    const int iz = ext_src3(z + 3, nzi, sz);
+    const int e1 = min(max(z + 2, 0), nzi - 1);
+    const T* pw = wc + iz * pz;
+    const T* pp = a.wp + e1 * pz;
+    const T* pc = c2p + e1 * pz;
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+      o.w[r] = ld_off(pw, co[r]);
+      o.sw[r] = sxy[r] * sz;
+      o.p[r] = ld_off(pp, co[r]);
+      o.c[r] = ld_off(pc, co[r]);
+    }
+    if constexpr (QPF) {
+      if (withq) loadq(o.q, z);
+    }
+  };
+  // one plane: levels 1..3; with `store` the plane is owned (z >= z0):
+  // outputs and accumulators are written
+  auto process = [&](int z, const P& o, int buf, bool store) {
+    double qn[QPF ? 1 : RY][QPF ? 1 : QM];
+    if constexpr (!QPF) {
+      if (store) loadq(qn, z);
+    }
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+      wn[r][0] = wn[r][1];
+      wn[r][1] = wn[r][2];
+      wn[r][2] = o.sw[r] * o.w[r];
+      w1[r][0] = w1[r][1];
+      w1[r][1] = w1[r][2];
+      w2[r][0] = w2[r][1];
+      w2[r][1] = w2[r][2];
+      cw[r][0] = cw[r][1];
+      cw[r][1] = cw[r][2];
+      cw[r][2] = a.c2 ? o.c[r] : T(1);
+      p0[buf][yl[r]][lx] = wn[r][1];
+      p1[buf][yl[r]][lx] = w1[r][1];
+      p2[buf][yl[r]][lx] = w2[r][1];
+    }
+    __syncthreads();
+    T* o1 = a.w1 + z * pz;
+    T* o2 = a.w2 + z * pz;
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+      // level 1: W^{n+1} on plane z + 2
+      const T v1 = step(wn[r][1], p0[buf], yl[r], wn[r][0], wn[r][2], o.p[r], cw[r][2]);
+      w1[r][2] = (m1[r] && z + 2 >= 0 && z + 2 < nzi) ? v1 : T(0);
+      // level 2: W^{n+2} on plane z + 1
+      const T v2 = step(w1[r][1], p1[buf], yl[r], w1[r][0], w1[r][2], wn[r][0], cw[r][1]);
+      w2[r][2] = (m2[r] && z + 1 >= 0 && z + 1 < nzi) ? v2 : T(0);
+      // level 3: W^{n+3} on plane z (owned)
+      const T v3 = step(w2[r][1], p2[buf], yl[r], w2[r][0], w2[r][2], w1[r][0], cw[r][0]);
+      if (store && own[r]) {
+        st_off(o1, oo[r], w2[r][1]);
+        st_off(o2, oo[r], v3);
+        const double d1 = (double)w1[r][0], d2 = (double)w2[r][1], d3 = (double)v3;
+#pragma unroll
+        for (int q = 0; q < QM; ++q) {
+          double qv;
+          if constexpr (QPF) qv = o.q[r][q];
+          else qv = qn[r][q];
+          if (q < a.nq)
+            st_off(a.q + a.qm[q] * fs + z * pz, qo[r],
+                   ((qv + kks[0][q] * d1) + kks[1][q] * d2) + kks[2][q] * d3);
+        }
+      }
+    }
+  };
+
+  // the four planes below the chunk (levels only), then the chunk; fetches
+  // past the last plane re-read the last plane (valid, unused)
+  P ra, rb;
+  const int r0 = z0 - 4;
+  fetch(ra, r0, false);
+  fetch(rb, r0 + 1, false);
+  process(r0, ra, 0, false);
+  fetch(ra, r0 + 2, false);
+  process(r0 + 1, rb, 1, false);
+  fetch(rb, r0 + 3, false);
+  process(r0 + 2, ra, 0, false);
+  fetch(ra, z0, true);
+  process(r0 + 3, rb, 1, false);
+  for (int z = z0; z < z1; z += 2) {
+    fetch(rb, min(z + 1, z1 - 1), true);
+    process(z, ra, 0, true);
+    if (z + 1 >= z1) break;
+    fetch(ra, min(z + 2, z1 - 1), true);
+    process(z + 1, rb, 1, true);
+  }
+}
+
+template <typename T, int BYT, int RY, int OX>
+hipError_t launch_x3r(LeapArgs<T>& a, hipStream_t s) {
+  const Geom& g = a.g;
+  constexpr int OY = BYT * RY - 6;
+  // float32 fits two 1024-lane blocks per CU (64 VGPRs); float64 needs 96
+  // and keeps one
+  constexpr int MINW = sizeof(T) == 4 ? 8 : 1;
+  a.ntx = (g.nxi + OX - 1) / OX;
+  a.nty = (g.nyi + OY - 1) / OY;
+  a.nchunk = (g.nzi + a.chunk - 1) / a.chunk;
+  a.nblocks = a.ntx * a.nty * a.nchunk;
+  const int grid = pad8(a.nblocks);
+  const dim3 blk(64, BYT);
+  if (a.force) return hipErrorInvalidValue;   // three steps per pass run forcing-free
+  if (g.pz * 8 >= (1LL << 32)) return hipErrorInvalidValue;   // 32-bit in-plane offsets
+  if (a.nq <= 4) k_leap3d_x3r<T, BYT, RY, OX, 4, false, MINW><<<grid, blk, 0, s>>>(a);
+  else k_leap3d_x3r<T, BYT, RY, OX, 8, false, MINW><<<grid, blk, 0, s>>>(a);
+  return hipGetLastError();
+}
+
 template <typename T, int BX, int BY>
 hipError_t launch_x3_3(LeapArgs<T>& a, hipStream_t s) {
   const Geom& g = a.g;
@@ -576,13 +829,16 @@ template <typename T, int R>
 hipError_t launch_r3(LeapArgs<T>& a, int steps, const LaunchShape& ls, hipStream_t s) {
   if (steps == 3) {
     if constexpr (R == 1) {
+      if (ls.bx == 48 && ls.by == 16) return launch_x3r<T, 16, 1, 48>(a, s);
       if (ls.bx == 64 && ls.by == 16) return launch_x3_3<T, 64, 16>(a, s);
       if (ls.bx == 32 && ls.by == 16) return launch_x3_3<T, 32, 16>(a, s);
     }
     return hipErrorInvalidValue;
   }
   if (steps == 2) {
-    if (ls.bx == 64 && ls.by == 16) return launch_x2_3<T, R, 64, 16>(a, s);
+    // 48 x 16 names the aligned three-step tile; its two-step passes (the
+    // forced passes and the tail) take 64 x 16
+    if ((ls.bx == 64 || ls.bx == 48) && ls.by == 16) return launch_x2_3<T, R, 64, 16>(a, s);
     if (ls.bx == 32 && ls.by == 16) return launch_x2_3<T, R, 32, 16>(a, s);
     // 64 x 8 owns 60 x 4 columns with order 2; order 4 would own no row
     if constexpr (R == 1)
@@ -613,12 +869,11 @@ template hipError_t launch_leap3d<double>(LeapArgs<double>&, int, int, const Lau
 template hipError_t launch_leap3d<float>(LeapArgs<float>&, int, int, const LaunchShape&,
                                          hipStream_t);
 
-LaunchShape default_leap3d_shape(const Geom& g, int steps, int order) {
+LaunchShape default_leap3d_shape(const Geom& g, int steps, int order, bool fp32) {
   LaunchShape ls;
   ls.bx = 64;
   // two steps: 64 x 8 with order 2 (60 x 4 owned columns; two blocks per CU,
-  // measured 4 % faster on 256^3 than 64 x 16), 64 x 16 with order 4;
-  // three steps (order 2): 64 x 16
+  // measured 4 % faster on 256^3 than 64 x 16), 64 x 16 with order 4
   ls.by = steps == 3 ? 16 : steps == 2 ? (order == 2 ? 8 : 16) : 4;
   const int h = steps >= 2 ? steps * order : 0;              // 2 x steps x R halo columns
   const int ox = 64 - h, oy = ls.by - h;
@@ -626,12 +881,20 @@ LaunchShape default_leap3d_shape(const Geom& g, int steps, int order) {
   const long long target_waves = 256LL * 16;
   long long ch = tiles * (ls.bx * ls.by / 64) * g.nzi / target_waves;
   ls.chunk = (int)std::min<long long>(std::max<long long>(ch, steps >= 2 ? 8 : 4), 64);
-  // three steps: 16 planes (256^3: 0.259 ms per step against 0.269 for 32
-  // and 0.282 for 64; the 4 recomputed planes per chunk buy more blocks), or
-  // 8 where 16-plane chunks leave fewer than two blocks per CU (ms per
-  // application with 16 / 8 planes: 97^3 21.2 / 16.5, 129^3 59.5 / 55.5,
-  // 193^3 314 / 329)
-  if (steps == 3) ls.chunk = tiles * ((g.nzi + 15) / 16) >= 512 ? 16 : 8;
+  if (steps == 3) {
+    // three steps (order 2): the aligned 48 x 10 tile (k_leap3d_x3r).  ms
+    // per 256^3 application, float32 / float64: 58 x 10 tile with 16-plane
+    // chunks 1040 / 1340; 48 x 10 with 8-plane chunks - / 1068, 16 910 /
+    // 1076, 24 897 / -, 32 885 / 1044, 48 901 / - (one run).  Float32,
+    // chunks of 8 / 16 / 32 planes: 129^3 46.3 / 49.1 / 52.8 ms, 193^3 278
+    // / 279 / 267 ms.  Chunks of 32 planes while that gives at least 384
+    // blocks (0.75 per slot at two blocks per CU; 192 in float64, one block
+    // per CU), else 16 on the same terms, else 8.
+    ls.bx = 48;
+    const long long t48 = ((g.nxi + 47) / 48) * (long long)((g.nyi + 9) / 10);
+    const long long want = fp32 ? 384 : 192;
+    ls.chunk = t48 * ((g.nzi + 31) / 32) >= want ? 32 : t48 * ((g.nzi + 15) / 16) >= want ? 16 : 8;
+  }
   return ls;
 }
 

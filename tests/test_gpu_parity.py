@@ -137,7 +137,8 @@ SHAPES_3D_X2 = [(64, 16, 1), (64, 16, 7), (32, 16, 3), (64, 16, 200), (64, 16, 1
                 (64, 8, 5), (64, 8, 64)]   # 64 x 8: order 2 only
 # three steps per pass (3): order 2, forcing-free passes (order 4 and forced
 # passes run the two-step kernel with the same shape)
-SHAPES_3D_X3 = [(64, 16, 1), (64, 16, 5), (32, 16, 3), (64, 16, 64), (64, 16, 300)]
+SHAPES_3D_X3 = [(64, 16, 1), (64, 16, 5), (32, 16, 3), (64, 16, 64), (64, 16, 300), (48, 16, 1),
+                (48, 16, 6), (48, 16, 300)]
 
 
 @pytest.mark.parametrize("shape", SHAPES_2D, ids=lambda s: f"bx{s[0]}-c{s[2]}")
@@ -224,6 +225,55 @@ def test_x3_3d_eight_filters(chunk, forcing, precision):
         L.mfwh_set_launch_shape(0)
         L.mfwh_set_option(L.MFWH_OPT_STEPS_PER_PASS, L.MFWH_STEPS_AUTO)
     assert rel(out, ref) < (tol64(pl) if precision == 0 else tol32(pl))
+
+
+# three-step 3D tiles: 58 x 10 and 26 x 10 columns (k_leap3d_x3 on 64 x 16
+# and 32 x 16 lanes) and the 128-byte-aligned 48 x 10 tile (k_leap3d_x3r,
+# named 48 x 16), with whole, partial and one-plane chunks
+X3_TILES = [(64, 16, 16), (32, 16, 7), (48, 16, 16), (48, 16, 5), (48, 16, 1), (48, 16, 32),
+            (48, 16, 64)]
+_X3_REF = {}
+
+
+def _x3_case(forcing):
+    if forcing not in _X3_REF:
+        w = inputs.small(seed=12, shape=(100, 61, 24), nf=8, order=2, varc=True, lo=4.0, hi=30.0)
+        prob, pl = workload.setup(w)
+        V = rand_v(w["shape"], 8, 13)
+        _X3_REF[forcing] = (w, pl, V, omf.apply(prob, pl, w["f"], V, forcing))
+    return _X3_REF[forcing]
+
+
+@pytest.mark.parametrize("shape", X3_TILES, ids=lambda t: f"{t[0]}x{t[1]}-c{t[2]}")
+@pytest.mark.parametrize("forcing", [False, True], ids=["free", "forced"])
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "fp32"])
+def test_x3_3d_tiles(shape, forcing, precision):
+    """Three steps per pass in 3D over several tiles in x and y with ragged
+    edges (98 x 59 x 22 interior points, 8 filters), whole and partial
+    chunks; forced passes run the two-step kernel.  B is ill-conditioned
+    here (cond 571), so besides V' the filtered fields q = B V' are compared
+    before B^{-1} amplifies their rounding, at 16 u N_t with u the unit
+    roundoff of the stencil's precision: leapfrog carries each step's
+    rounding (a few u, the step's coefficients summing to at most 8 in
+    magnitude) undamped through the N_t = 932 steps, on both sides of the
+    comparison (1.7e-12 in float64, 8.9e-4 in float32)."""
+    L = _L()
+    w, pl, V, ref = _x3_case(forcing)
+    try:
+        L.mfwh_set_option(L.MFWH_OPT_STEPS_PER_PASS, 3)
+        L.mfwh_set_launch_shape(*shape)
+        gp = _gp(w, precision=precision)
+        out = gp.apply(torch.as_tensor(V, device="cuda"), forcing=forcing).cpu().numpy()
+    finally:
+        L.mfwh_set_launch_shape(0)
+        L.mfwh_set_option(L.MFWH_OPT_STEPS_PER_PASS, L.MFWH_STEPS_AUTO)
+    e = rel(out, ref)
+    e_q = rel(np.tensordot(pl.B, out, axes=(1, 0)), np.tensordot(pl.B, ref, axes=(1, 0)))
+    bar_q = 16 * (2.0 ** -53 if precision == 0 else EPS32) * pl.nt
+    print(f"x3 tile {shape} forcing={forcing} precision={precision}: V' {e:.2e}, q {e_q:.2e} "
+          f"(bar {bar_q:.1e})")
+    assert e < (tol64(pl) if precision == 0 else tol32(pl))
+    assert e_q < bar_q
 
 
 def test_apply_in_place_and_deterministic():
@@ -654,7 +704,8 @@ def test_config3_full_size_forcing_free_three_step(precision):
     """The 3D workload exactly as the benchmark runs it -- 256^3, order 2,
     variable c, N_f = 8, the real dt, float32 stencil (and float64) --
     forcing-free: three steps per pass (the automatic choice with order 2;
-    64x16 blocks, 16-plane chunks).  An 18-step window runs the first step,
+    128-byte-aligned 48 x 10 tiles on 64 x 16 lanes, 32-plane chunks).  An
+    18-step window runs the first step,
     five three-step passes and a two-step tail: 7 step launches (two steps
     per pass would make 10).  Whole field against the oracle, relative L2
     and largest pointwise error, at 1e-12 (float64) and 1e-5 (float32)."""
