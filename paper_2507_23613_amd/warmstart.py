@@ -82,11 +82,18 @@ class WarmStart:
             self.ws[B] = torch.empty(n, dtype=torch.uint8, device=self.device)
         return self.ws[B]
 
+    # samples per features/targets call (the library takes at most 2^26
+    # pixels per call)
+    CHUNK = 256
+
     def features(self, F, OM):
         B = F.shape[0]
         feat = torch.empty((B, self.H, self.W, 6 * self.nf), dtype=torch.float32,
                            device=self.device)
-        L.mfwh_cnn_features(F.contiguous(), OM.contiguous(), self.lengths, feat, self._ws(B))
+        for s in range(0, B, self.CHUNK):
+            e = min(B, s + self.CHUNK)
+            L.mfwh_cnn_features(F[s:e].contiguous(), OM[s:e].contiguous(), self.lengths,
+                                feat[s:e], self._ws(e - s))
         return feat
 
     def targets(self, F, OM, U):
@@ -96,8 +103,11 @@ class WarmStart:
         amplitude)."""
         B = F.shape[0]
         out = torch.empty((B, self.H, self.W, self.nf), dtype=torch.float32, device=self.device)
-        L.mfwh_cnn_scale(1, out, U.contiguous(), F.contiguous(), OM.contiguous(), self._ws(B))
-        L.mfwh_cnn_normalize(out)
+        for s in range(0, B, self.CHUNK):
+            e = min(B, s + self.CHUNK)
+            L.mfwh_cnn_scale(1, out[s:e], U[s:e].contiguous(), F[s:e].contiguous(),
+                             OM[s:e].contiguous(), self._ws(e - s))
+            L.mfwh_cnn_normalize(out[s:e])
         return out
 
     def train(self, feats, targets, epochs=20, lr=1e-3, seed=0, log=None):
@@ -160,3 +170,40 @@ def compare_solves(ws, model, restart=30, deflate=15, tol=1e-8, max_iter=1500,
         if log and (k + 1) % every == 0:
             log(f"compared {k + 1}/{len(ws)}")
     return rows
+
+
+def compare_batched(ws, model, restart=30, deflate=15, tol=1e-8, max_iter=1500, chunk=64,
+                    log=None):
+    """compare_solves with the batched solver: each chunk of workloads is
+    solved together from zero and then from the network's guesses (zero
+    fallback and residual-optimal scaling per problem).  Iterations are per
+    problem; times are per chunk (guesses' inference included) divided by
+    the chunk's size."""
+    rows = []
+    for s in range(0, len(ws), chunk):
+        part = ws[s:s + chunk]
+        gb = GpuBatch(part, restart=restart)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, i0, _ = gb.gmres(max_iter=max_iter, tol=tol, deflate=deflate)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        F = torch.stack([gp.f for gp in gb.items])
+        OM = torch.stack([torch.as_tensor(gp.omega, device=gp.device) for gp in gb.items])
+        guess = model.predict(F, OM)
+        _, i1, _ = gb.gmres(max_iter=max_iter, tol=tol, deflate=deflate,
+                            initial=[guess[k] for k in range(len(part))], zero_fallback=1,
+                            scale_initial=1)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        n = len(part)
+        for a, b in zip(i0, i1):
+            rows.append(dict(zero_its=a["iterations"], zero_s=(t1 - t0) / n,
+                             zero_conv=a["converged"], warm_its=b["iterations"],
+                             warm_s=(t2 - t1) / n, warm_conv=b["converged"],
+                             fell_back=b["fell_back"], warm_init_res=b["initial_rel_residual"]))
+        del gb, F, OM, guess
+        if log:
+            log(f"compared {min(s + chunk, len(ws))}/{len(ws)} (batched)")
+    return rows
+
