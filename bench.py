@@ -260,10 +260,13 @@ def implicit_bench(args):
 
 # HBM traffic per launch of the three-step 3D kernel on the 256^3 workload
 # (its 8-accumulator launches; FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, from the
-# rocprofv3 summaries in profiles/), keyed by precision (1: float32 stencil)
-# and valid only for the leap3d.hip source it was measured on.
-TRAFFIC3 = {1: {"leap3d_sha256_16": "633db7e588afc68c",
-                "bytes": 982943.3 * 1024 * 2.0 + 1212496.8 * 1024 * 1.0}}
+# rocprofv3 summaries in profiles/), keyed by precision (0: float64, 1:
+# float32 stencil) and valid only for the leap3d.hip source it was measured
+# on.
+TRAFFIC3 = {0: {"leap3d_sha256_16": "7c9216af5dc1b263",
+                "bytes": 980784.5 * 1024 * 2.0 + 1288861.5 * 1024 * 1.0},
+            1: {"leap3d_sha256_16": "7c9216af5dc1b263",
+                "bytes": 775426.2 * 1024 * 2.0 + 1164474.6 * 1024 * 1.0}}
 
 
 def roofline_3d(precision):

@@ -486,7 +486,7 @@ int mfwh_set_launch_shape(int bx, int by, int chunk);
  * operands of row y + depth - 1 before computing row y.
  * MFWH_OPT_PROGRESS (default 0): 1 makes mfwh_solve_gmres print one line to
  * stderr per Krylov cycle (Arnoldi steps so far, residual estimate, restart
- * kind) and per refinement step, for long solves. */
+ * kind), every 25 Arnoldi steps and per refinement step, for long solves. */
 enum { MFWH_OPT_GRAPHS = 1, MFWH_OPT_STEPS_PER_PASS = 2, MFWH_OPT_PREFETCH_DEPTH = 3,
        MFWH_OPT_PROGRESS = 4 };
 int mfwh_set_option(int key, long long value);

@@ -328,7 +328,8 @@ bool g_shape_set = false;
 bool g_graphs = true;           // solvers record step sequences into graphs
 int g_steps_per_pass = -1;      // steps per pass (MFWH_OPT_STEPS_PER_PASS; -1: automatic)
 int g_depth = 4;                // prefetch depth of the streamlined kernels (MFWH_OPT_PREFETCH_DEPTH)
-bool g_progress = false;        // one stderr line per Krylov cycle (MFWH_OPT_PROGRESS)
+bool g_progress = false;        // stderr lines per Krylov cycle and every 25 Arnoldi steps
+                                // (MFWH_OPT_PROGRESS)
 
 int setup(Problem& pr, const mfwh_grid* g, const mfwh_time* t, int restart, void* ws,
           size_t ws_bytes, void* stream) {
@@ -1133,6 +1134,11 @@ int gmres_core(Vecs& V, bool use32, const double* rhs, double* x, bool xzero, do
       k = j + 1;
       const double est = std::fabs(ls.g[j + 1]);
       if (hist) hist[hist_off + its - 1] = est / bnorm;
+      if (g_progress && (hist_off + its) % 25 == 0) {
+        std::fprintf(stderr, "[mfwh gmres] %d Arnoldi steps: estimate %.3e\n", hist_off + its,
+                     est / bnorm);
+        std::fflush(stderr);
+      }
       if (est <= tol_abs || hnext == 0.0) { stop = true; break; }
     }
     if (its >= max_its) stop = true;
