@@ -19,14 +19,15 @@ Extra fields:
                  the timed steps, against the 8 TB/s HBM peak.  Its hbm3d_*
                  keys give the same measurement on the 3D 256^3 workload
                  (float64 and float32 stencil, variable c, 8 filters, two
-                 forcing-free applications each, three-step kernel), whose
+                 forcing-free applications each, four-step kernel), whose
                  1.8 GB working set streams from HBM, while the 2D workload's
                  fits the 256 MB Infinity Cache
   roofline_3d    the full 3D measurement, both precisions
   cpu_baseline   the float64 oracle (NumPy, one core) stepping the same
                  workload for a bounded number of time steps
   time_to_1e8    wall time of the float64 solve and of one float32-stencil
-                 solve with float64 iterative refinement (bounded)
+                 solve with float64 iterative refinement (bounded), with the
+                 latter's relative error per frequency against the former
 
     python bench.py [--gpus 1] [--steps 3] [--warmup 1]
     python bench.py --mode copy      # plain copy kernel of known size (counter calibration)
@@ -258,20 +259,20 @@ def implicit_bench(args):
                       "rows": rows}), flush=True)
 
 
-# HBM traffic per launch of the three-step 3D kernel on the 256^3 workload
+# HBM traffic per launch of the four-step 3D kernel on the 256^3 workload
 # (its 8-accumulator launches; FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, from the
 # rocprofv3 summaries in profiles/), keyed by precision (0: float64, 1:
 # float32 stencil) and valid only for the leap3d.hip source it was measured
 # on.
-TRAFFIC3 = {0: {"leap3d_sha256_16": "7c9216af5dc1b263",
-                "bytes": 980784.5 * 1024 * 2.0 + 1288861.5 * 1024 * 1.0},
-            1: {"leap3d_sha256_16": "7c9216af5dc1b263",
-                "bytes": 775426.2 * 1024 * 2.0 + 1164474.6 * 1024 * 1.0}}
+TRAFFIC3 = {0: {"leap3d_sha256_16": "987920804d485bbe",
+                "bytes": 1104277.0 * 1024 * 2.0 + 1288635.8 * 1024 * 1.0},
+            1: {"leap3d_sha256_16": "987920804d485bbe",
+                "bytes": 975555.6 * 1024 * 2.0 + 1190744.7 * 1024 * 1.0}}
 
 
 def roofline_3d(precision):
     """The 3D 256^3 workload (variable c, 8 filters) in one precision: two
-    forcing-free applications with the three-step kernel after a warm-up; its
+    forcing-free applications with the four-step kernel after a warm-up; its
     algorithmic bytes per launch over the event-timed launch duration against
     the 8 TB/s peak (this is the workload whose kernel streams from HBM: its
     working set is 1.8 GB in float32 and 2.3 GB in float64)."""
@@ -313,9 +314,9 @@ def roofline_3d(precision):
     torch.cuda.empty_cache()
     return {"workload": w["name"] + ("-fp64" if precision == L.MFWH_FP64 else "-fp32-stencil"),
             "nt": nt,
-            "kernel": f"k_leap3d_x3r<{tname}, order 2, 48x10 tiles aligned to 128 B on 64x16 "
-                      "lanes, 32-plane chunks>: 3 fused leapfrog steps + 8 filter updates per "
-                      "launch (forcing-free)",
+            "kernel": f"k_leap3d_xkr<{tname}, 4 steps, order 2, 48x8 tiles aligned to 128 B on "
+                      "64x16 lanes, 32-plane chunks>: 4 fused leapfrog steps + 8 filter updates "
+                      "per launch (forcing-free)",
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "bytes_per_point_per_launch": per_pass,
@@ -553,8 +554,8 @@ def main():
                     help="apply mode: the 2D 1025^2 workload (float64) or the 3D 256^3 "
                          "workload (float32 stencil, variable c, 8 frequencies)")
     ap.add_argument("--spp", type=int, default=-1, choices=[-1, 0, 1, 2, 3, 4],
-                    help="step kernel: -1 the library's choice (2D 3 or 4, 3D 3), 0 general, "
-                         "1..4 streamlined steps per launch (3D: at most 3)")
+                    help="step kernel: -1 the library's choice (2D 3 or 4, 3D 4), 0 general, "
+                         "1..4 streamlined steps per launch (3D: 4 on the aligned tile only)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU slab "
@@ -604,8 +605,8 @@ def main():
     gp = GpuProblem(w, precision=prec, restart=0 if args.mode == "apply" else RESTART)
     log(f"N_t={gp.nt} dt={gp.dt:.3e} interior={gp.interior_points}")
     # -1: the library's choice (2D: four steps per pass from 10^6 interior
-    # points, else three; 3D: three)
-    auto = (4 if gp.interior_points >= 1000000 else 3) if len(w["shape"]) == 2 else 3
+    # points, else three; 3D with order 2: four)
+    auto = (4 if gp.interior_points >= 1000000 else 3) if len(w["shape"]) == 2 else 4
     spp, shape = (args.spp if args.spp >= 0 else auto), None
     if not args.no_tune and args.mode == "solve":
         from paper_2507_23613_amd import autotune
@@ -630,10 +631,13 @@ def main():
                 f"grid-point-steps/s x Nf (steps per pass {args.spp})")
         return
 
+    last = {}
+
     def solve():
         v, info = gp.gmres(restart=RESTART, max_iter=2000, tol=1e-8, deflate=DEFLATE)
         if not info["converged"]:
             raise RuntimeError(f"GMRES did not converge: {info['status']} {info['rel_residual']}")
+        last["v"] = v
         return info
 
     for k in range(args.warmup):
@@ -700,13 +704,19 @@ def main():
         t2e["fp32_rel_residual"] = info32["rel_residual"]
         t2e["fp32_iterations"] = info32["iterations"]
         t2e["fp32_outer"] = info32["outer"]
+        # per frequency: relative L2 distance of the float32-stencil result
+        # from the float64 solve's (converged to 1e-8)
+        v64 = last["v"]
+        t2e["fp32_vs_fp64_rel_error_per_frequency"] = [
+            float(torch.linalg.vector_norm(v32[m] - v64[m]) / torch.linalg.vector_norm(v64[m]))
+            for m in range(nf)]
         log(f"fp32: {t2e}")
         del gp32, v32
         torch.cuda.empty_cache()
     roof3 = {}
     if not args.no_3d:
         for prec3 in (L.MFWH_FP64, L.MFWH_FP32_STENCIL):
-            log(f"3D 256^3 workload, precision {prec3}: three-step kernel rate "
+            log(f"3D 256^3 workload, precision {prec3}: four-step kernel rate "
                 "(two applications)")
             roof3["fp64" if prec3 == L.MFWH_FP64 else "fp32"] = r3 = roofline_3d(prec3)
             log(f"3D: {r3}")

@@ -448,15 +448,16 @@ int mfwh_stats_read(long long* launches, double* total_ms, double* total_bytes);
  * or 2 with bx 64/64/128; 8 with bx 32), chunk rows (2D) or planes (3D)
  * marched per block.  In 3D a shape with by = 16 (bx 64 or 32) sets only the
  * multi-step kernels (two and three steps per launch); 48 x 16 selects the
- * three-step kernel over 128-byte-aligned 48 x 10 column tiles (64 x 16
- * lanes; its two-step passes take 64 x 16) and is ignored by every other
- * kernel and by 2D problems; 64 x 8 sets every
+ * three- and four-step kernel over 128-byte-aligned 48-column tiles (64 x 16
+ * lanes, 10 or 8 owned rows; its two-step passes take 64 x 16; the default)
+ * and is ignored by every other kernel and by 2D problems; 64 x 8 sets every
  * kernel with order 2 except the three-step one (the two-step kernel then
  * owns 60 x 4 columns per block, and three steps per pass fall back to two);
  * any other shape sets the one-step kernels (and the multi-step kernels keep
  * their defaults).  The three- and four-step 2D kernels run an unrolled
- * march when bx = 128 and chunk = 8 (their default).  bx = 0 restores the
- * built-in heuristics. */
+ * march when bx = 128 and chunk = 8 (their default), the four-step one also
+ * with chunk = 16 (its default from 1.6e7 interior points).  bx = 0 restores
+ * the built-in heuristics. */
 int mfwh_set_launch_shape(int bx, int by, int chunk);
 
 /* Process-wide options, read when a call sets up its problem.
@@ -466,7 +467,7 @@ int mfwh_set_launch_shape(int bx, int by, int chunk);
  * While step timing (mfwh_stats_enable) is on, a graph replay is timed as a
  * whole and counted as the number of step launches it holds.
  * MFWH_OPT_STEPS_PER_PASS (default -1 = automatic: four steps per launch on
- * 2D grids of at least 10^6 interior points, three on smaller ones, three on
+ * 2D grids of at least 10^6 interior points, three on smaller ones, four on
  * 3D grids with order 2, two with order 4): 2D grids:
  * after the first step,
  * 0 runs every step with the general step kernel, 1 with the streamlined 2D
@@ -476,9 +477,10 @@ int mfwh_set_launch_shape(int bx, int by, int chunk);
  * steps per launch for applications without forcing (with forcing: two).
  * 3D grids: 0 runs the general kernel, 1 the streamlined 3D kernel (one
  * step per launch, launch shapes 64 x 4 or 64 x 8), 2 two steps per launch
- * (64 x 8 with order 2, 64 x 16 or 32 x 16), 3 or more three steps per
- * launch with order 2 for applications without forcing (64 x 16 or 32 x 16;
- * with forcing, and with order 4: two).  All compute the
+ * (64 x 8 with order 2, 64 x 16 or 32 x 16), 3 three steps per launch with
+ * order 2 for applications without forcing (48 x 16, 64 x 16 or 32 x 16), 4
+ * four steps (48 x 16 only; other shapes run three); with forcing, and with
+ * order 4: two.  All compute the
  * same values up to floating-point contraction; 1D grids always use the
  * general kernel.
  * MFWH_OPT_PREFETCH_DEPTH (2 or 4; default 4): register sets of row operands

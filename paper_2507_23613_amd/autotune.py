@@ -23,9 +23,10 @@ CAND_3D = [(64, 4, ch) for ch in (2, 4, 8, 16, 32)] + \
           [(64, 8, ch) for ch in (4, 8, 16)] + [(128, 2, ch) for ch in (4, 8, 16)] + \
           [(32, 8, ch) for ch in (4, 8)]
 # 3D (steps-per-pass option, shape): 0 = general kernel, 1 = streamlined kernel,
-# 2 and 3 = two and three fused steps per pass (three with order 2 only; the
-# library runs two for order 4)
-CAND_3D_PASS = [(3, (bx, 16, ch)) for bx in (48, 64, 32) for ch in (8, 16, 32)] + \
+# 2, 3 and 4 = two to four fused steps per pass (three and four with order 2
+# only, four on the aligned 48 x 16 tile; the library runs two for order 4)
+CAND_3D_PASS = [(4, (48, 16, ch)) for ch in (8, 16, 32)] + \
+               [(3, (bx, 16, ch)) for bx in (48, 64, 32) for ch in (8, 16, 32)] + \
                [(2, (bx, 16, ch)) for bx in (64, 32) for ch in (8, 16, 32, 64)] + \
                [(2, (64, 8, ch)) for ch in (16, 32, 64)] + \
                [(1, (64, by, ch)) for by in (4, 8) for ch in (4, 8, 16, 32)] + \

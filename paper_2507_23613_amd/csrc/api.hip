@@ -365,15 +365,17 @@ int setup(Problem& pr, const mfwh_grid* g, const mfwh_time* t, int restart, void
                                      " bytes, got " + std::to_string(ws_bytes));
   pr.shape64 = default_shape(pr.G, g->order, 8);
   pr.shape32 = default_shape(pr.G, g->order, 4);
-  // 2D: 0..4 steps per pass; 3D: 0..3 with order 2, 0..2 with order 4;
+  // 2D: 0..4 steps per pass; 3D: 0..4 with order 2 (four on the aligned
+  // tile only), 0..2 with order 4;
   // automatic: four steps per pass on 2D grids of 10^6 interior points and
   // more, three below (ms per application, three / four steps: 513^2
   // 11.9 / 12.4, 1025^2 32.0 / 30.4, 2049^2 213 / 194, 4097^2 2728 / 1844),
-  // and three in 3D with order 2 (256^3: 0.259 ms per step against 0.352
-  // for two)
-  const int spp_max3 = g->order == 2 ? 3 : 2;
+  // and four in 3D with order 2 (ms per application, three / four steps on
+  // the aligned tile, float32: 129^3 46.1 / 39.5, 193^3 266 / 258, 256^3
+  // 898 / 702; float64 256^3 1016 / 834), two with order 4
+  const int spp_max3 = g->order == 2 ? 4 : 2;
   const int auto2 = (long long)pr.G.nxi * pr.G.nyi >= 1000000LL ? 4 : 3;
-  const int want = g_steps_per_pass >= 0 ? g_steps_per_pass : pr.G.dim == 2 ? auto2 : 3;
+  const int want = g_steps_per_pass >= 0 ? g_steps_per_pass : pr.G.dim == 2 ? auto2 : 4;
   pr.spp = pr.G.dim == 2 ? want : pr.G.dim == 3 ? std::min(want, spp_max3) : 0;
   if (pr.refl) pr.spp = 0;   // Neumann / Robin faces: general step kernels
   pr.depth = g_depth;
@@ -395,6 +397,7 @@ int setup(Problem& pr, const mfwh_grid* g, const mfwh_time* t, int restart, void
   // three- and four-step 2D kernels need bx >= 128, the three-step 3D kernel
   // by = 16
   if (pr.G.dim == 2 && pr.spp >= 3 && pr.leap.bx < 128) pr.spp = 2;
+  if (pr.G.dim == 3 && pr.spp == 4 && pr.leap.bx != 48) pr.spp = 3;   // aligned tile only
   if (pr.G.dim == 3 && pr.spp == 3 && !x3_shape(pr.leap)) pr.spp = 2;
   if (pr.implicit) {
     pr.W.lev[0].c2 = pr.varc ? pr.W.c64 : nullptr;

@@ -557,21 +557,22 @@ __global__ void __launch_bounds__(BX * BY) k_leap3d_x3(LeapArgs<T> a) {
   }
 }
 
-// Three steps per pass with RY rows per lane (order 2, forcing-free): the
-// scheme of k_leap3d_x3 on a taller tile.  A 64 x BYT block covers 64 x
-// (BYT * RY) columns; lane (lx, ly) holds rows ly + BYT * r (r < RY), so a
-// block owns OX x (BYT * RY - 6) columns and its W^n, W^{n-1}, c^2
-// footprint shrinks towards the owned tile as the tile grows.  With
-// OX = 48 the owned x-range of every tile starts on a 128-byte boundary of
-// the float64 accumulator rows (row pitches are multiples of 64 elements),
-// so no accumulator line is shared by two tiles; lanes past OX + 6 mirror
-// the last live column and never store.  The four planes a chunk computes
+// KS = 3 or 4 steps per pass on aligned tiles (order 2, forcing-free):
+// the scheme of k_leap3d_x3 with KS levels.  A 64 x 16 block owns OX x
+// (16 - 2 KS) columns; level j = W^{n+j} (j = 1 .. KS) is computed on plane
+// z + KS - j at iteration z, on lanes at least j from the block edge, from
+// level j - 1 on planes z + KS - j - 1 .. z + KS - j + 1 (x/y neighbours
+// from the level's LDS plane, one barrier per iteration).  With OX = 48 the
+// owned x-range of every tile starts on a 128-byte boundary of the float64
+// accumulator rows (row pitches are multiples of 64 elements), so no
+// accumulator line is shared by two tiles; lanes past OX + 2 KS mirror the
+// last live column and never store.  The 2 KS - 2 planes a chunk computes
 // before its first owned plane read no accumulators.  Every access is a
 // wave-uniform plane base plus a per-lane 32-bit byte offset fixed for the
 // whole march (an in-plane offset: planes hold fewer than 2^29 points), so
-// addresses cost one register per row.  Accumulators are fetched with the
-// other operands of the next plane when QPF, else at the start of their
-// own plane (fewer registers).
+// addresses cost one register per stream; accumulators are loaded at the
+// start of their own plane.  Every accumulator is read and written once per
+// KS steps; w1 / w2 receive W^{n+KS-1} and W^{n+KS}.
 template <typename U>
 __device__ __forceinline__ U ld_off(const U* base, uint32_t off) {
   return *reinterpret_cast<const U*>(reinterpret_cast<const char*>(base) + off);
@@ -581,26 +582,29 @@ __device__ __forceinline__ void st_off(U* base, uint32_t off, U v) {
   *reinterpret_cast<U*>(reinterpret_cast<char*>(base) + off) = v;
 }
 
-template <typename T, int RY, int QM, bool QPF>
-struct Plane3R {
-  T w[RY], sw[RY];           // new W^n values (plane z + 3) and factors
-  T p[RY], c[RY];            // W^{n-1}, c^2 on plane z + 2
-  double q[QPF ? RY : 1][QPF ? QM : 1];   // accumulators on plane z (QPF)
+template <typename T>
+struct PlaneR {
+  T w, sw;          // new W^n value (plane z + KS) and its factor
+  T p, c;           // W^{n-1}, c^2 on plane z + KS - 1
 };
 
-template <typename T, int BYT, int RY, int OX, int QM, bool QPF, int MINW>
-__global__ void __attribute__((amdgpu_flat_work_group_size(64 * BYT, 64 * BYT),
+// window length of level j: the three planes its stencil reads, reaching
+// down to plane z where the accumulators take it
+__host__ __device__ constexpr int lev_len(int ks, int j) {
+  return j == 0 ? 3 : (ks - j + 1 > 3 ? ks - j + 1 : 3);
+}
+
+template <typename T, int KS, int OX, int QM, int MINW>
+__global__ void __attribute__((amdgpu_flat_work_group_size(1024, 1024),
                                amdgpu_waves_per_eu(MINW)))
-k_leap3d_x3r(LeapArgs<T> a) {
-  constexpr int BX = 64, H = 3;
-  constexpr int BY = BYT * RY;
+k_leap3d_xkr(LeapArgs<T> a) {
+  constexpr int BX = 64, BY = 16, H = KS;
   constexpr int LW = OX + 2 * H;          // live lanes per row
   constexpr int OY = BY - 2 * H;
-  static_assert(LW <= BX && OY > 0, "tile");
-  __shared__ T p0[2][BY][BX];             // W^n on plane z + 2
-  __shared__ T p1[2][BY][BX];             // W^{n+1} on plane z + 1
-  __shared__ T p2[2][BY][BX];             // W^{n+2} on plane z
-  __shared__ double kks[3][QM];
+  constexpr int LM = lev_len(KS, 1);      // longest window
+  static_assert((KS == 3 || KS == 4) && LW <= BX && OY > 0, "tile");
+  __shared__ T pl[KS][2][BY][BX];         // level j on plane z + KS - 1 - j
+  __shared__ double kks[KS][QM];
   __shared__ T cs[7];
   const int lb = xcd_tile3(blockIdx.x, gridDim.x);
   if (lb >= a.nblocks) return;
@@ -611,7 +615,7 @@ k_leap3d_x3r(LeapArgs<T> a) {
   const int lx = threadIdx.x, ly = threadIdx.y;
   {
     const int t = ly * BX + lx;
-    if (t < 3 * QM) kks[t / QM][t % QM] = a.kk[t / QM][t % QM];
+    if (t < KS * QM) kks[t / QM][t % QM] = a.kk[t / QM][t % QM];
     if (t < 7)
       cs[t] = t == 0 ? a.wx[0] + a.wy[0] + a.wz[0]
             : t == 1 ? a.wx[1]
@@ -625,188 +629,150 @@ k_leap3d_x3r(LeapArgs<T> a) {
   const long long py = a.g.py, pz = a.g.pz, fs = a.g.fs;
   const int x0 = tx * OX, y0 = ty * OY;
   const int ex = x0 - H + min(lx, LW - 1);
-  T sx;
-  const int ix = ext_src3(ex, nxi, sx);
-  const bool xin = ex >= 0 && ex < nxi;
-  const int qx = min(max(ex, x0), min(x0 + OX, nxi) - 1);
-  auto inx = [&](int m) { return lx >= m && lx < LW - m; };
-  int yl[RY];
-  T sxy[RY];
-  uint32_t co[RY];     // byte offset of the lane's column in a T plane
-  uint32_t qo[RY];     // byte offset of its owned column in a float64 plane
-  uint32_t oo[RY];     // byte offset of its (owned) column in a T plane
-  bool m1[RY], m2[RY], own[RY], qrow[RY];
+  const int ey = y0 - H + ly;
+  T sx, sy;
+  const int ix = ext_src3(ex, nxi, sx), iy = ext_src3(ey, nyi, sy);
+  const T sxy = sx * sy;
+  const bool in = ex >= 0 && ex < nxi && ey >= 0 && ey < nyi;
+  bool mk[KS + 1];                        // level j computed here (mk[KS]: owned)
 #pragma unroll
-  for (int r = 0; r < RY; ++r) {
-    yl[r] = ly + BYT * r;
-    const int ey = y0 - H + yl[r];
-    T sy;
-    const int iy = ext_src3(ey, nyi, sy);
-    sxy[r] = sx * sy;
-    const bool in = xin && ey >= 0 && ey < nyi;
-    auto iny = [&](int m) { return yl[r] >= m && yl[r] < BY - m; };
-    m1[r] = in && inx(1) && iny(1);
-    m2[r] = in && inx(2) && iny(2);
-    own[r] = in && inx(3) && iny(3);
-    qrow[r] = iny(H);
-    co[r] = (uint32_t)((iy * py + ix) * (long long)sizeof(T));
-    const int qy = min(max(ey, y0), min(y0 + OY, nyi) - 1);
-    const long long qc = qy * py + qx;          // = the lane's own column when own[r]
-    qo[r] = (uint32_t)(qc * 8);
-    oo[r] = (uint32_t)(qc * (long long)sizeof(T));
-  }
+  for (int m = 1; m <= KS; ++m)
+    mk[m] = in && lx >= m && lx < LW - m && ly >= m && ly < BY - m;
+  const bool qrow = ly >= H && ly < BY - H;
+  const int qx = min(max(ex, x0), min(x0 + OX, nxi) - 1);
+  const int qy = min(max(ey, y0), min(y0 + OY, nyi) - 1);
+  const long long qc = qy * py + qx;      // = the lane's own column when mk[KS]
+  const uint32_t co = (uint32_t)((iy * py + ix) * (long long)sizeof(T));
+  const uint32_t qo = (uint32_t)(qc * 8);
+  const uint32_t oo = (uint32_t)(qc * (long long)sizeof(T));
   const T* __restrict__ c2p = a.c2 ? a.c2 : a.wp;       // read and ignored when c = 1
   const int z0 = cz * a.chunk;
   const int z1 = min(z0 + a.chunk, nzi);
   const T* __restrict__ wc = a.wc;
-  auto step = [&](T ce, const T (*pl)[BX], int y, T zm, T zp, T pv, T cc) {
-    const int cx = min(max(lx, 1), BX - 2), cy = min(max(y, 1), BY - 2);
-    const T lap = cs[0] * ce + cs[1] * (pl[cy][cx - 1] + pl[cy][cx + 1]) +
-                  cs[2] * (pl[cy - 1][cx] + pl[cy + 1][cx]) + cs[3] * (zm + zp);
+  auto step = [&](T ce, const T (*p)[BX], T zm, T zp, T pv, T cc) {
+    const int cx = min(max(lx, 1), BX - 2), cy = min(max(ly, 1), BY - 2);
+    const T lap = cs[0] * ce + cs[1] * (p[cy][cx - 1] + p[cy][cx + 1]) +
+                  cs[2] * (p[cy - 1][cx] + p[cy + 1][cx]) + cs[3] * (zm + zp);
     return cs[4] * ce + cs[5] * pv + cs[6] * (cc * lap);
   };
 
-  T wn[RY][3];         // W^n on planes z+1 .. z+3 at iteration z
-  T w1[RY][3];         // W^{n+1} on planes z .. z+2
-  T w2[RY][3];         // W^{n+2} on planes z-1 .. z+1
-  T cw[RY][3];         // c^2 on planes z .. z+2
+  // lev[j][0 .. L_j - 1]: W^{n+j} on planes z + KS - j - L_j + 1 .. z + KS - j
+  T lev[KS][LM];
+  T cw[KS];                               // c^2 on planes z .. z + KS - 1
 #pragma unroll
-  for (int k = 0; k < 2; ++k) {
+  for (int j = 0; j < KS; ++j)
+#pragma unroll
+    for (int i = 0; i < LM; ++i) lev[j][i] = T(0);
+#pragma unroll
+  for (int i = 0; i < KS; ++i) cw[i] = T(1);
+  const int r0 = z0 - 2 * KS + 2;
+#pragma unroll
+  for (int k = 1; k < 3; ++k) {           // W^n on planes r0 + KS - 3 + k
     T sz;
-    const int iz = ext_src3(z0 - 3 + k, nzi, sz);
-    const T* pl = wc + iz * pz;
-#pragma unroll
-    for (int r = 0; r < RY; ++r) wn[r][k + 1] = sxy[r] * sz * ld_off(pl, co[r]);
+    const int iz = ext_src3(r0 + KS - 3 + k, nzi, sz);
+    lev[0][k] = sxy * sz * ld_off(wc + iz * pz, co);
   }
-#pragma unroll
-  for (int r = 0; r < RY; ++r)
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      w1[r][k] = T(0);
-      w2[r][k] = T(0);
-      cw[r][k] = T(1);
-    }
 
-  using P = Plane3R<T, RY, QM, QPF>;
-  auto loadq = [&](double (*qv)[QM], int z) {
-#pragma unroll
-    for (int q = 0; q < QM; ++q) {
-      const double* qp = a.q + a.qm[q] * fs + z * pz;
-#pragma unroll
-      for (int r = 0; r < RY; ++r)
-        if (qrow[r]) qv[r][q] = ld_off(qp, qo[r]);
-    }
-  };
-  auto fetch = [&](P& o, int z, bool withq) {
+  auto fetch = [&](PlaneR<T>& o, int z) {
     T sz;
-    const int iz = ext_src3(z + 3, nzi, sz);
-    const int e1 = min(max(z + 2, 0), nzi - 1);
-    const T* pw = wc + iz * pz;
-    const T* pp = a.wp + e1 * pz;
-    const T* pc = c2p + e1 * pz;
-#pragma unroll
-    for (int r = 0; r < RY; ++r) {
-      o.w[r] = ld_off(pw, co[r]);
-      o.sw[r] = sxy[r] * sz;
-      o.p[r] = ld_off(pp, co[r]);
-      o.c[r] = ld_off(pc, co[r]);
-    }
-    if constexpr (QPF) {
-      if (withq) loadq(o.q, z);
-    }
+    const int iz = ext_src3(z + KS, nzi, sz);
+    const int e1 = min(max(z + KS - 1, 0), nzi - 1);
+    o.w = ld_off(wc + iz * pz, co);
+    o.sw = sxy * sz;
+    o.p = ld_off(a.wp + e1 * pz, co);
+    o.c = ld_off(c2p + e1 * pz, co);
   };
-  // one plane: levels 1..3; with `store` the plane is owned (z >= z0):
+  // one plane: levels 1 .. KS; with `store` the plane is owned (z >= z0):
   // outputs and accumulators are written
-  auto process = [&](int z, const P& o, int buf, bool store) {
-    double qn[QPF ? 1 : RY][QPF ? 1 : QM];
-    if constexpr (!QPF) {
-      if (store) loadq(qn, z);
+  auto process = [&](int z, const PlaneR<T>& o, int buf, bool store) {
+    double qv[QM];
+    if (store && qrow) {
+#pragma unroll
+      for (int q = 0; q < QM; ++q) qv[q] = ld_off(a.q + a.qm[q] * fs + z * pz, qo);
     }
 #pragma unroll
-    for (int r = 0; r < RY; ++r) {
-      wn[r][0] = wn[r][1];
-      wn[r][1] = wn[r][2];
-      wn[r][2] = o.sw[r] * o.w[r];
-      w1[r][0] = w1[r][1];
-      w1[r][1] = w1[r][2];
-      w2[r][0] = w2[r][1];
-      w2[r][1] = w2[r][2];
-      cw[r][0] = cw[r][1];
-      cw[r][1] = cw[r][2];
-      cw[r][2] = a.c2 ? o.c[r] : T(1);
-      p0[buf][yl[r]][lx] = wn[r][1];
-      p1[buf][yl[r]][lx] = w1[r][1];
-      p2[buf][yl[r]][lx] = w2[r][1];
+    for (int j = 0; j < KS; ++j) {
+      const int L = lev_len(KS, j);
+#pragma unroll
+      for (int i = 0; i + 1 < LM; ++i)
+        if (i + 1 < L) lev[j][i] = lev[j][i + 1];
     }
+    lev[0][2] = o.sw * o.w;
+#pragma unroll
+    for (int i = 0; i + 1 < KS; ++i) cw[i] = cw[i + 1];
+    cw[KS - 1] = a.c2 ? o.c : T(1);
+#pragma unroll
+    for (int j = 0; j < KS; ++j) pl[j][buf][ly][lx] = lev[j][lev_len(KS, j) - 2];
     __syncthreads();
-    T* o1 = a.w1 + z * pz;
-    T* o2 = a.w2 + z * pz;
+    T vlast = T(0);
 #pragma unroll
-    for (int r = 0; r < RY; ++r) {
-      // level 1: W^{n+1} on plane z + 2
-      const T v1 = step(wn[r][1], p0[buf], yl[r], wn[r][0], wn[r][2], o.p[r], cw[r][2]);
-      w1[r][2] = (m1[r] && z + 2 >= 0 && z + 2 < nzi) ? v1 : T(0);
-      // level 2: W^{n+2} on plane z + 1
-      const T v2 = step(w1[r][1], p1[buf], yl[r], w1[r][0], w1[r][2], wn[r][0], cw[r][1]);
-      w2[r][2] = (m2[r] && z + 1 >= 0 && z + 1 < nzi) ? v2 : T(0);
-      // level 3: W^{n+3} on plane z (owned)
-      const T v3 = step(w2[r][1], p2[buf], yl[r], w2[r][0], w2[r][2], w1[r][0], cw[r][0]);
-      if (store && own[r]) {
-        st_off(o1, oo[r], w2[r][1]);
-        st_off(o2, oo[r], v3);
-        const double d1 = (double)w1[r][0], d2 = (double)w2[r][1], d3 = (double)v3;
+    for (int j = 0; j < KS; ++j) {
+      // level j + 1 on plane z + KS - 1 - j
+      const int L = lev_len(KS, j);
+      const T prev = j == 0 ? o.p : lev[j - 1][lev_len(KS, j - 1) - 3];
+      const T v = step(lev[j][L - 2], pl[j][buf], lev[j][L - 3], lev[j][L - 1], prev,
+                       cw[KS - 1 - j]);
+      if (j + 1 < KS) {
+        const int pz1 = z + KS - 1 - j;
+        lev[j + 1][lev_len(KS, j + 1) - 1] = (mk[j + 1] && pz1 >= 0 && pz1 < nzi) ? v : T(0);
+      } else {
+        vlast = v;
+      }
+    }
+    if (store && mk[KS]) {
+      st_off(a.w1 + z * pz, oo, lev[KS - 1][lev_len(KS, KS - 1) - 2]);
+      st_off(a.w2 + z * pz, oo, vlast);
+      double d[KS];                       // W^{n+1} .. W^{n+KS} on plane z
 #pragma unroll
-        for (int q = 0; q < QM; ++q) {
-          double qv;
-          if constexpr (QPF) qv = o.q[r][q];
-          else qv = qn[r][q];
-          if (q < a.nq)
-            st_off(a.q + a.qm[q] * fs + z * pz, qo[r],
-                   ((qv + kks[0][q] * d1) + kks[1][q] * d2) + kks[2][q] * d3);
-        }
+      for (int k = 1; k < KS; ++k) d[k - 1] = (double)lev[k][lev_len(KS, k) - 1 - (KS - k)];
+      d[KS - 1] = (double)vlast;
+#pragma unroll
+      for (int q = 0; q < QM; ++q) {
+        double acc = qv[q];
+#pragma unroll
+        for (int k = 0; k < KS; ++k) acc += kks[k][q] * d[k];
+        if (q < a.nq) st_off(a.q + a.qm[q] * fs + z * pz, qo, acc);
       }
     }
   };
 
-  // the four planes below the chunk (levels only), then the chunk; fetches
-  // past the last plane re-read the last plane (valid, unused)
-  P ra, rb;
-  const int r0 = z0 - 4;
-  fetch(ra, r0, false);
-  fetch(rb, r0 + 1, false);
-  process(r0, ra, 0, false);
-  fetch(ra, r0 + 2, false);
-  process(r0 + 1, rb, 1, false);
-  fetch(rb, r0 + 3, false);
-  process(r0 + 2, ra, 0, false);
-  fetch(ra, z0, true);
-  process(r0 + 3, rb, 1, false);
+  // the 2 KS - 2 planes below the chunk (levels only), then the chunk;
+  // fetches past the last plane re-read the last plane (valid, unused)
+  PlaneR<T> ra, rb;
+  fetch(ra, r0);
+#pragma unroll
+  for (int i = 0; i < KS - 1; ++i) {
+    const int zz = r0 + 2 * i;
+    fetch(rb, zz + 1);
+    process(zz, ra, 0, false);
+    fetch(ra, zz + 2);
+    process(zz + 1, rb, 1, false);
+  }
   for (int z = z0; z < z1; z += 2) {
-    fetch(rb, min(z + 1, z1 - 1), true);
+    fetch(rb, min(z + 1, z1 - 1));
     process(z, ra, 0, true);
     if (z + 1 >= z1) break;
-    fetch(ra, min(z + 2, z1 - 1), true);
+    fetch(ra, min(z + 2, z1 - 1));
     process(z + 1, rb, 1, true);
   }
 }
 
-template <typename T, int BYT, int RY, int OX>
-hipError_t launch_x3r(LeapArgs<T>& a, hipStream_t s) {
+template <typename T, int KS, int OX>
+hipError_t launch_xkr(LeapArgs<T>& a, hipStream_t s) {
   const Geom& g = a.g;
-  constexpr int OY = BYT * RY - 6;
-  // float32 fits two 1024-lane blocks per CU (64 VGPRs); float64 needs 96
-  // and keeps one
+  constexpr int OY = 16 - 2 * KS;
+  // float32 fits two 1024-lane blocks per CU (64 VGPRs); float64 keeps one
   constexpr int MINW = sizeof(T) == 4 ? 8 : 1;
   a.ntx = (g.nxi + OX - 1) / OX;
   a.nty = (g.nyi + OY - 1) / OY;
   a.nchunk = (g.nzi + a.chunk - 1) / a.chunk;
   a.nblocks = a.ntx * a.nty * a.nchunk;
   const int grid = pad8(a.nblocks);
-  const dim3 blk(64, BYT);
-  if (a.force) return hipErrorInvalidValue;   // three steps per pass run forcing-free
+  const dim3 blk(64, 16);
+  if (a.force) return hipErrorInvalidValue;   // three and four steps per pass run forcing-free
   if (g.pz * 8 >= (1LL << 32)) return hipErrorInvalidValue;   // 32-bit in-plane offsets
-  if (a.nq <= 4) k_leap3d_x3r<T, BYT, RY, OX, 4, false, MINW><<<grid, blk, 0, s>>>(a);
-  else k_leap3d_x3r<T, BYT, RY, OX, 8, false, MINW><<<grid, blk, 0, s>>>(a);
+  if (a.nq <= 4) k_leap3d_xkr<T, KS, OX, 4, MINW><<<grid, blk, 0, s>>>(a);
+  else k_leap3d_xkr<T, KS, OX, 8, MINW><<<grid, blk, 0, s>>>(a);
   return hipGetLastError();
 }
 
@@ -827,9 +793,14 @@ hipError_t launch_x3_3(LeapArgs<T>& a, hipStream_t s) {
 
 template <typename T, int R>
 hipError_t launch_r3(LeapArgs<T>& a, int steps, const LaunchShape& ls, hipStream_t s) {
+  if (steps == 4) {
+    if constexpr (R == 1)
+      if (ls.bx == 48 && ls.by == 16) return launch_xkr<T, 4, 48>(a, s);
+    return hipErrorInvalidValue;
+  }
   if (steps == 3) {
     if constexpr (R == 1) {
-      if (ls.bx == 48 && ls.by == 16) return launch_x3r<T, 16, 1, 48>(a, s);
+      if (ls.bx == 48 && ls.by == 16) return launch_xkr<T, 3, 48>(a, s);
       if (ls.bx == 64 && ls.by == 16) return launch_x3_3<T, 64, 16>(a, s);
       if (ls.bx == 32 && ls.by == 16) return launch_x3_3<T, 32, 16>(a, s);
     }
@@ -855,8 +826,8 @@ hipError_t launch_r3(LeapArgs<T>& a, int steps, const LaunchShape& ls, hipStream
 template <typename T>
 hipError_t launch_leap3d(LeapArgs<T>& a, int order, int steps, const LaunchShape& ls,
                          hipStream_t s) {
-  if (a.g.dim != 3 || a.nq < 0 || a.nq > MFWH_MAX_NF || steps < 1 || steps > 3 ||
-      (steps == 3 && order != 2))
+  if (a.g.dim != 3 || a.nq < 0 || a.nq > MFWH_MAX_NF || steps < 1 || steps > 4 ||
+      (steps >= 3 && order != 2))
     return hipErrorInvalidValue;
   if (steps >= 2 && (a.w1 == a.wc || a.w1 == a.wp || a.w2 == a.wc || a.w2 == a.wp ||
                      a.w1 == a.w2 || !a.w2))
@@ -874,15 +845,16 @@ LaunchShape default_leap3d_shape(const Geom& g, int steps, int order, bool fp32)
   ls.bx = 64;
   // two steps: 64 x 8 with order 2 (60 x 4 owned columns; two blocks per CU,
   // measured 4 % faster on 256^3 than 64 x 16), 64 x 16 with order 4
-  ls.by = steps == 3 ? 16 : steps == 2 ? (order == 2 ? 8 : 16) : 4;
+  ls.by = steps >= 3 ? 16 : steps == 2 ? (order == 2 ? 8 : 16) : 4;
   const int h = steps >= 2 ? steps * order : 0;              // 2 x steps x R halo columns
   const int ox = 64 - h, oy = ls.by - h;
   const long long tiles = ((g.nxi + ox - 1) / ox) * (long long)((g.nyi + oy - 1) / oy);
   const long long target_waves = 256LL * 16;
   long long ch = tiles * (ls.bx * ls.by / 64) * g.nzi / target_waves;
   ls.chunk = (int)std::min<long long>(std::max<long long>(ch, steps >= 2 ? 8 : 4), 64);
-  if (steps == 3) {
-    // three steps (order 2): the aligned 48 x 10 tile (k_leap3d_x3r).  ms
+  if (steps >= 3) {
+    // three and four steps (order 2): the aligned 48 x (16 - 2 steps)
+    // tile (k_leap3d_xkr).  Three steps, ms
     // per 256^3 application, float32 / float64: 58 x 10 tile with 16-plane
     // chunks 1040 / 1340; 48 x 10 with 8-plane chunks - / 1068, 16 910 /
     // 1076, 24 897 / -, 32 885 / 1044, 48 901 / - (one run).  Float32,
@@ -891,7 +863,8 @@ LaunchShape default_leap3d_shape(const Geom& g, int steps, int order, bool fp32)
     // blocks (0.75 per slot at two blocks per CU; 192 in float64, one block
     // per CU), else 16 on the same terms, else 8.
     ls.bx = 48;
-    const long long t48 = ((g.nxi + 47) / 48) * (long long)((g.nyi + 9) / 10);
+    const int oy = 16 - 2 * steps;
+    const long long t48 = ((g.nxi + 47) / 48) * (long long)((g.nyi + oy - 1) / oy);
     const long long want = fp32 ? 384 : 192;
     ls.chunk = t48 * ((g.nzi + 31) / 32) >= want ? 32 : t48 * ((g.nzi + 15) / 16) >= want ? 16 : 8;
   }
