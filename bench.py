@@ -61,8 +61,8 @@ HBM_PEAK_GBS = 8000.0
 # profiles/k_leap2d_xk4_fp64_2d-n1025-nf4.md).  Keyed by (steps per pass, bx,
 # chunk) and valid only for the kernel source it was measured on: reported
 # as null for another configuration or once leap2d.hip changes.
-TRAFFIC = {"leap2d_sha256_16": "b3614863954f88b3",
-           "bytes": {(4, 128, 8): 32908.4 * 1024 * 2.0 + 48688.2 * 1024 * 1.0}}
+TRAFFIC = {"leap2d_sha256_16": "d920782adb55300a",
+           "bytes": {(4, 128, 8): 32912.1 * 1024 * 2.0 + 48688.2 * 1024 * 1.0}}
 
 
 def measured_traffic(cfg):
@@ -518,9 +518,10 @@ def main():
                     choices=["solve", "copy", "apply", "batch", "warmstart", "implicit", "bc",
                              "fpi", "solve3d", "gemm"])
     ap.add_argument("--restart", type=int, default=30,
-                    help="solve3d and batch modes: GMRES restart length")
+                    help="GMRES restart length (default mode, solve3d and batch modes)")
     ap.add_argument("--deflate", type=int, default=15,
-                    help="solve3d and batch modes: harmonic Ritz vectors kept")
+                    help="harmonic Ritz vectors kept per restart (default mode, solve3d and "
+                         "batch modes)")
     ap.add_argument("--tol", type=float, default=1e-8,
                     help="solve3d and batch modes: relative residual")
     ap.add_argument("--max-iter", type=int, default=1500,
@@ -601,7 +602,7 @@ def main():
         prec = L.MFWH_FP64
     nf = len(w["omega"])
     log(f"workload {w['name']}: omega={np.round(w['omega'], 3).tolist()} N_p={w['np']}")
-    RESTART, DEFLATE = 30, 15
+    RESTART, DEFLATE = args.restart, args.deflate      # GMRES(30), 15 harmonic Ritz vectors
     gp = GpuProblem(w, precision=prec, restart=0 if args.mode == "apply" else RESTART)
     log(f"N_t={gp.nt} dt={gp.dt:.3e} interior={gp.interior_points}")
     # -1: the library's choice (2D: four steps per pass from 10^6 interior
