@@ -264,10 +264,10 @@ def implicit_bench(args):
 # rocprofv3 summaries in profiles/), keyed by precision (0: float64, 1:
 # float32 stencil) and valid only for the leap3d.hip source it was measured
 # on.
-TRAFFIC3 = {0: {"leap3d_sha256_16": "987920804d485bbe",
-                "bytes": 1104277.0 * 1024 * 2.0 + 1288635.8 * 1024 * 1.0},
-            1: {"leap3d_sha256_16": "987920804d485bbe",
-                "bytes": 975555.6 * 1024 * 2.0 + 1190744.7 * 1024 * 1.0}}
+TRAFFIC3 = {0: {"leap3d_sha256_16": "e507e3b2dac240bd",
+                "bytes": 1106832.8 * 1024 * 2.0 + 1288635.8 * 1024 * 1.0},
+            1: {"leap3d_sha256_16": "e507e3b2dac240bd",
+                "bytes": 973557.1 * 1024 * 2.0 + 1190847.2 * 1024 * 1.0}}
 
 
 def roofline_3d(precision):

@@ -386,7 +386,7 @@ int setup(Problem& pr, const mfwh_grid* g, const mfwh_time* t, int restart, void
     const LaunchShape& o = g_shape_override;
     if (pr.G.dim == 3 && x3_shape(o)) {
       pr.leap = o;             // multi-step 3D shape: the other kernels keep theirs
-    } else if (o.bx != 48) {   // (48 names a three-step 3D tile only)
+    } else if (o.bx != 48) {   // (48 names a multi-step 3D tile only)
       pr.shape64 = pr.shape32 = pr.leap1 = o;
       // 64 x 8 also suits the two-step 3D kernel with order 2
       if (!(pr.G.dim == 3 && pr.spp >= 2) || (o.bx == 64 && o.by == 8 && g->order == 2))

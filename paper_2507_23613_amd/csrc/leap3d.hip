@@ -558,15 +558,16 @@ __global__ void __launch_bounds__(BX * BY) k_leap3d_x3(LeapArgs<T> a) {
 }
 
 // KS = 3 or 4 steps per pass on aligned tiles (order 2, forcing-free):
-// the scheme of k_leap3d_x3 with KS levels.  A 64 x 16 block owns OX x
-// (16 - 2 KS) columns; level j = W^{n+j} (j = 1 .. KS) is computed on plane
-// z + KS - j at iteration z, on lanes at least j from the block edge, from
-// level j - 1 on planes z + KS - j - 1 .. z + KS - j + 1 (x/y neighbours
-// from the level's LDS plane, one barrier per iteration).  With OX = 48 the
-// owned x-range of every tile starts on a 128-byte boundary of the float64
-// accumulator rows (row pitches are multiples of 64 elements), so no
-// accumulator line is shared by two tiles; lanes past OX + 2 KS mirror the
-// last live column and never store.  The 2 KS - 2 planes a chunk computes
+// the scheme of k_leap3d_x3 with KS levels.  A BX x BY block of 1024 lanes
+// (64 x 16) owns OX x (BY - 2 KS) columns; level j = W^{n+j}
+// (j = 1 .. KS) is computed on plane z + KS - j at iteration z, on lanes at
+// least j from the block edge, from level j - 1 on planes z + KS - j - 1 ..
+// z + KS - j + 1 (x/y neighbours from the level's LDS plane, one barrier
+// per iteration).  With OX = 48 the owned x-range of every tile
+// starts on a 128-byte boundary of the float64 accumulator rows (row
+// pitches are multiples of 64 elements), so no accumulator line is shared
+// by two tiles; lanes past OX + 2 KS mirror the last live column and never
+// store.  The 2 KS - 2 planes a chunk computes
 // before its first owned plane read no accumulators.  Every access is a
 // wave-uniform plane base plus a per-lane 32-bit byte offset fixed for the
 // whole march (an in-plane offset: planes hold fewer than 2^29 points), so
@@ -594,11 +595,12 @@ __host__ __device__ constexpr int lev_len(int ks, int j) {
   return j == 0 ? 3 : (ks - j + 1 > 3 ? ks - j + 1 : 3);
 }
 
-template <typename T, int KS, int OX, int QM, int MINW>
+template <typename T, int KS, int BX, int BY, int OX, int QM, int MINW>
 __global__ void __attribute__((amdgpu_flat_work_group_size(1024, 1024),
                                amdgpu_waves_per_eu(MINW)))
 k_leap3d_xkr(LeapArgs<T> a) {
-  constexpr int BX = 64, BY = 16, H = KS;
+  constexpr int H = KS;
+  static_assert(BX * BY == 1024, "1024-lane blocks");
   constexpr int LW = OX + 2 * H;          // live lanes per row
   constexpr int OY = BY - 2 * H;
   constexpr int LM = lev_len(KS, 1);      // longest window
@@ -757,10 +759,10 @@ k_leap3d_xkr(LeapArgs<T> a) {
   }
 }
 
-template <typename T, int KS, int OX>
+template <typename T, int KS, int BX, int BY, int OX>
 hipError_t launch_xkr(LeapArgs<T>& a, hipStream_t s) {
   const Geom& g = a.g;
-  constexpr int OY = 16 - 2 * KS;
+  constexpr int OY = BY - 2 * KS;
   // float32 fits two 1024-lane blocks per CU (64 VGPRs); float64 keeps one
   constexpr int MINW = sizeof(T) == 4 ? 8 : 1;
   a.ntx = (g.nxi + OX - 1) / OX;
@@ -768,11 +770,11 @@ hipError_t launch_xkr(LeapArgs<T>& a, hipStream_t s) {
   a.nchunk = (g.nzi + a.chunk - 1) / a.chunk;
   a.nblocks = a.ntx * a.nty * a.nchunk;
   const int grid = pad8(a.nblocks);
-  const dim3 blk(64, 16);
+  const dim3 blk(BX, BY);
   if (a.force) return hipErrorInvalidValue;   // three and four steps per pass run forcing-free
   if (g.pz * 8 >= (1LL << 32)) return hipErrorInvalidValue;   // 32-bit in-plane offsets
-  if (a.nq <= 4) k_leap3d_xkr<T, KS, OX, 4, MINW><<<grid, blk, 0, s>>>(a);
-  else k_leap3d_xkr<T, KS, OX, 8, MINW><<<grid, blk, 0, s>>>(a);
+  if (a.nq <= 4) k_leap3d_xkr<T, KS, BX, BY, OX, 4, MINW><<<grid, blk, 0, s>>>(a);
+  else k_leap3d_xkr<T, KS, BX, BY, OX, 8, MINW><<<grid, blk, 0, s>>>(a);
   return hipGetLastError();
 }
 
@@ -795,19 +797,19 @@ template <typename T, int R>
 hipError_t launch_r3(LeapArgs<T>& a, int steps, const LaunchShape& ls, hipStream_t s) {
   if (steps == 4) {
     if constexpr (R == 1)
-      if (ls.bx == 48 && ls.by == 16) return launch_xkr<T, 4, 48>(a, s);
+      if (ls.bx == 48 && ls.by == 16) return launch_xkr<T, 4, 64, 16, 48>(a, s);
     return hipErrorInvalidValue;
   }
   if (steps == 3) {
     if constexpr (R == 1) {
-      if (ls.bx == 48 && ls.by == 16) return launch_xkr<T, 3, 48>(a, s);
+      if (ls.bx == 48 && ls.by == 16) return launch_xkr<T, 3, 64, 16, 48>(a, s);
       if (ls.bx == 64 && ls.by == 16) return launch_x3_3<T, 64, 16>(a, s);
       if (ls.bx == 32 && ls.by == 16) return launch_x3_3<T, 32, 16>(a, s);
     }
     return hipErrorInvalidValue;
   }
   if (steps == 2) {
-    // 48 x 16 names the aligned three-step tile; its two-step passes (the
+    // 48 x 16 names the aligned multi-step tile; its two-step passes (the
     // forced passes and the tail) take 64 x 16
     if ((ls.bx == 64 || ls.bx == 48) && ls.by == 16) return launch_x2_3<T, R, 64, 16>(a, s);
     if (ls.bx == 32 && ls.by == 16) return launch_x2_3<T, R, 32, 16>(a, s);
@@ -865,8 +867,19 @@ LaunchShape default_leap3d_shape(const Geom& g, int steps, int order, bool fp32)
     ls.bx = 48;
     const int oy = 16 - 2 * steps;
     const long long t48 = ((g.nxi + 47) / 48) * (long long)((g.nyi + oy - 1) / oy);
-    const long long want = fp32 ? 384 : 192;
-    ls.chunk = t48 * ((g.nzi + 31) / 32) >= want ? 32 : t48 * ((g.nzi + 15) / 16) >= want ? 16 : 8;
+    if (steps == 3) {
+      const long long want = fp32 ? 384 : 192;
+      ls.chunk =
+          t48 * ((g.nzi + 31) / 32) >= want ? 32 : t48 * ((g.nzi + 15) / 16) >= want ? 16 : 8;
+    } else {
+      // four steps recompute six planes per chunk: 32-plane chunks only
+      // where they still give two rounds of blocks, else 8 (float32, ms per
+      // application with chunks of 8 / 16 / 32 planes: 256^3 - / 749 / 702,
+      // 193^3 226 / - / 257, 129^3 41.3 / 39.5 (another box) / 43.4; float64
+      // 256^3 - / 867 / 834)
+      const long long want = fp32 ? 1024 : 512;
+      ls.chunk = t48 * ((g.nzi + 31) / 32) >= want ? 32 : 8;
+    }
   }
   return ls;
 }

@@ -268,7 +268,7 @@ def test_option_and_launch_shape_validation():
     L.mfwh_set_option(L.MFWH_OPT_PREFETCH_DEPTH, 4)
     with pytest.raises(L.MfwhError):
         L.mfwh_set_option(99, 1)
-    for bad in ((48, 1, 8), (48, 8, 16), (64, 0, 8), (64, 4, 0)):
+    for bad in ((48, 1, 8), (48, 8, 16), (16, 32, 8), (64, 0, 8), (64, 4, 0)):
         with pytest.raises(L.MfwhError):
             L.mfwh_set_launch_shape(*bad)
     L.mfwh_set_launch_shape(48, 16, 16)      # the aligned multi-step 3D tile

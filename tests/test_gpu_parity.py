@@ -234,9 +234,9 @@ def test_x3_3d_eight_filters(chunk, forcing, precision):
 
 
 # multi-step 3D tiles: 58 x 10 and 26 x 10 columns (k_leap3d_x3 on 64 x 16
-# and 32 x 16 lanes) and the 128-byte-aligned 48-column tile (k_leap3d_xkr,
-# named 48 x 16; 48 x 10 owned with three steps, 48 x 8 with four), with
-# whole, partial and one-plane chunks
+# and 32 x 16 lanes) and the 128-byte-aligned 48-column tile of
+# k_leap3d_xkr (named 48 x 16; 48 x 10 owned with three steps, 48 x 8 with
+# four), with whole, partial and one-plane chunks
 X3_TILES = [(64, 16, 16), (32, 16, 7), (48, 16, 16), (48, 16, 5), (48, 16, 1), (48, 16, 32),
             (48, 16, 64)]
 _X3_REF = {}
