@@ -164,7 +164,7 @@ constexpr int kMaxLev = kMgMaxLev;  // multigrid levels at most
 struct Workspace {
   double *w64a = nullptr, *w64b = nullptr, *f64 = nullptr, *c64 = nullptr;
   float *w32a = nullptr, *w32b = nullptr, *f32 = nullptr, *c32 = nullptr;
-  double *w64c = nullptr, *w64d = nullptr;   // 2D: outputs of two-step passes
+  double *w64c = nullptr, *w64d = nullptr;   // 2D, 3D: outputs of multi-step passes
   float *w32c = nullptr, *w32d = nullptr;
   double* q = nullptr;
   double* partial = nullptr;   // (restart+2) * kRedBlocks doubles
