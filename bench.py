@@ -264,10 +264,10 @@ def implicit_bench(args):
 # rocprofv3 summaries in profiles/), keyed by precision (0: float64, 1:
 # float32 stencil) and valid only for the leap3d.hip source it was measured
 # on.
-TRAFFIC3 = {0: {"leap3d_sha256_16": "e507e3b2dac240bd",
-                "bytes": 1106832.8 * 1024 * 2.0 + 1288635.8 * 1024 * 1.0},
-            1: {"leap3d_sha256_16": "e507e3b2dac240bd",
-                "bytes": 973557.1 * 1024 * 2.0 + 1190847.2 * 1024 * 1.0}}
+TRAFFIC3 = {0: {"leap3d_sha256_16": "68c33ef59439de90",
+                "bytes": 902924.9 * 1024 * 2.0 + 1288635.8 * 1024 * 1.0},
+            1: {"leap3d_sha256_16": "68c33ef59439de90",
+                "bytes": 869040.3 * 1024 * 2.0 + 1184475.1 * 1024 * 1.0}}
 
 
 def roofline_3d(precision):

@@ -610,10 +610,12 @@ k_leap3d_xkr(LeapArgs<T> a) {
   __shared__ T cs[7];
   const int lb = xcd_tile3(blockIdx.x, gridDim.x);
   if (lb >= a.nblocks) return;
-  const int cz = lb % a.nchunk;
-  const int t2 = lb / a.nchunk;
+  // y-tiles fastest: the blocks an XCD runs together are y-neighbours of
+  // one x-strip and one chunk, marching in step, whose halo rows meet in L2
+  const int ty = lb % a.nty;
+  const int t2 = lb / a.nty;
   const int tx = t2 % a.ntx;
-  const int ty = t2 / a.ntx;
+  const int cz = t2 / a.ntx;
   const int lx = threadIdx.x, ly = threadIdx.y;
   {
     const int t = ly * BX + lx;
