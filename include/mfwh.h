@@ -456,7 +456,7 @@ int mfwh_stats_read(long long* launches, double* total_ms, double* total_bytes);
  * any other shape sets the one-step kernels (and the multi-step kernels keep
  * their defaults).  The three- and four-step 2D kernels run an unrolled
  * march when bx = 128 and chunk = 8 (their default), the four-step one also
- * with chunk = 16 (its default from 1.6e7 interior points).  bx = 0 restores
+ * with chunk = 16 (its default from 6e6 interior points).  bx = 0 restores
  * the built-in heuristics. */
 int mfwh_set_launch_shape(int bx, int by, int chunk);
 

@@ -871,9 +871,10 @@ LaunchShape default_leap_shape(const Geom& g, int steps) {
   ls.chunk = (int)std::min<long long>(std::max<long long>(ch, lo), 64);
   // four steps: 8 rows, the unrolled march (ms per application with chunk
   // 8 / the rule above: 2049^2 194 / 223, 4097^2 1844 / 1888), and 16
-  // rows, unrolled too, from 1.6e7 interior points (4097^2: 1565 ms
-  // against 1597 for 8 in one run)
-  if (steps == 4) ls.chunk = (long long)g.nxi * g.nyi >= 16000000LL ? 16 : 8;
+  // rows, unrolled too, from 6e6 interior points (ms per application with
+  // 16 / 8 rows, one box: 2049^2 199.6 / 193.5, 3073^2 641 / 658, 4097^2
+  // 1564 / 1585)
+  if (steps == 4) ls.chunk = (long long)g.nxi * g.nyi >= 6000000LL ? 16 : 8;
   return ls;
 }
 
