@@ -145,7 +145,14 @@ def config3(seed=0, n=256):
 
 def config4(seed=0, count=64, sizes=(129, 257, 385, 513)):
     """Batch of independent 2D problems: n ~ U{sizes}, Nf ~ U{2..6},
-    omega ~ U(10, 50), Gaussian-sum forcings, order 4, optimised filter."""
+    omega ~ U(10, 50), Gaussian-sum forcings, order 4, optimised filter.
+
+    The optimiser's least-squares solve drops singular values below 1e-2 of
+    the largest (as for the 3D workload): for some of these frequency sets
+    the plain solve returns parameters in the hundreds to thousands, B with
+    condition numbers 1e3 - 1e4 and |mu_d| up to 9 on the discrete spectrum,
+    so A_h has eigenvalues on both sides of zero; the minimum-norm solve
+    keeps the parameters O(1) and |mu_d| <= 1."""
     rng = np.random.default_rng(seed)
     out = []
     for i in range(count):
@@ -156,7 +163,7 @@ def config4(seed=0, count=64, sizes=(129, 257, 385, 513)):
         f = gaussian_sum_forcings(rng, shape, lengths, nf)
         out.append(dict(name=f"batch{i}-2d-n{n}-nf{nf}", shape=shape, lengths=lengths,
                         order=4, omega=omega, f=f, c=None, np=np_, cfl=0.5,
-                        filter="optimised"))
+                        filter="optimised", filter_rcond=1e-2))
     return out
 
 

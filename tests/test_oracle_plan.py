@@ -266,3 +266,34 @@ def test_optimiser_truncated_least_squares_branch():
     assert all(J[k] >= J[k + 1] - 1e-12 for k in range(3)), J
     assert all(na[k] <= na[k + 1] + 1e-12 for k in range(3)), na
     assert na[-1] > 1e5          # plain least squares: the ill-conditioned solution
+
+
+def test_batch_workload_filter_cutoff():
+    """The 64-problem 2D batch draws frequency sets for which plain least
+    squares (Algorithm 2) returns parameters in the hundreds to thousands:
+    the fit only constrains mu_d on Lambda (eq. LambdaRange), and far above
+    it |mu_d| exceeds 1, so I - S_h gets eigenvalues of both signs.  The
+    workload's cutoff keeps the parameters O(1), B well conditioned and
+    |mu_d| <= 1 up to the largest discrete eigenvalue of the grid (the
+    bound holds for any lambda~ on the grid of lambdas checked here)."""
+    from paper_2507_23613_amd import inputs
+    ws = inputs.config4(0)
+    for k in (3, 8, 14, 28, 34, 39, 42):
+        w = ws[k]
+        n = w["shape"][0]
+        h = 1.0 / (n - 1)
+        Tf, dt, nt = P.time_step_explicit(w["omega"][0], w["np"], h, 2, w["order"], 1.0, w["cfl"])
+        om_t = P.omega_tilde(np.asarray(w["omega"]), dt)
+        top = np.sqrt(2.0 * np.max(np.abs(fd.laplacian_eigenvalues_1d(n, h, w["order"]))))
+        lam = np.linspace(0.0, float(P.lambda_tilde(top, dt)), 4000)
+        p0, lmax, _ = P.optimise_filter_discrete(om_t, w["np"], nt)
+        pl0 = P.Plan(w["omega"], Tf, dt, params=p0)
+        mu0 = pl0.mu_d(lam)
+        assert np.max(np.abs(p0)) > 200.0, k
+        assert np.max(np.abs(mu0)) > 1.1, k
+        assert np.max(np.abs(mu0[lam <= lmax])) <= 1.0 + 1e-6, k   # fine on Lambda
+        p1, _, _ = P.optimise_filter_discrete(om_t, w["np"], nt, rcond=w["filter_rcond"])
+        pl1 = P.Plan(w["omega"], Tf, dt, params=p1)
+        assert np.max(np.abs(p1)) < 12.0, k
+        assert np.linalg.cond(pl1.B) < 12.0, k
+        assert np.max(np.abs(pl1.mu_d(lam))) <= 1.0 + 1e-6, k
