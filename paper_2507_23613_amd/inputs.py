@@ -170,7 +170,9 @@ def config4(seed=0, count=64, sizes=(129, 257, 385, 513)):
 def config5(seed=0, count=1, n=256):
     """Warm-start workloads: 2D n^2 (h = 1/(n-1)), order 4, Nf = 4,
     omega ~ U(20, 50), Gaussian-sum forcings; ``count`` problems drawn from one
-    stream."""
+    stream.  Optimised filters with the optimiser's cutoff, as for the batch
+    (with plain least squares 319 of the 2000 draws of seed 1000 at 256^2
+    have parameters above 100)."""
     rng = np.random.default_rng(seed)
     out = []
     for i in range(count):
@@ -179,7 +181,7 @@ def config5(seed=0, count=1, n=256):
         f = gaussian_sum_forcings(rng, shape, lengths, 4)
         out.append(dict(name=f"ws{i}-2d-n{n}-nf4", shape=shape, lengths=lengths,
                         order=4, omega=omega, f=f, c=None, np=np_, cfl=0.5,
-                        filter="optimised"))
+                        filter="optimised", filter_rcond=1e-2))
     return out
 
 
