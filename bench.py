@@ -264,10 +264,10 @@ def implicit_bench(args):
 # rocprofv3 summaries in profiles/), keyed by precision (0: float64, 1:
 # float32 stencil) and valid only for the leap3d.hip source it was measured
 # on.
-TRAFFIC3 = {0: {"leap3d_sha256_16": "68c33ef59439de90",
-                "bytes": 902924.9 * 1024 * 2.0 + 1288635.8 * 1024 * 1.0},
-            1: {"leap3d_sha256_16": "68c33ef59439de90",
-                "bytes": 869040.3 * 1024 * 2.0 + 1184475.1 * 1024 * 1.0}}
+TRAFFIC3 = {0: {"leap3d_sha256_16": "5ff2c847dafb3af2",
+                "bytes": 869791.1 * 1024 * 2.0 + 1288635.8 * 1024 * 1.0},
+            1: {"leap3d_sha256_16": "5ff2c847dafb3af2",
+                "bytes": 869211.5 * 1024 * 2.0 + 1184472.0 * 1024 * 1.0}}
 
 
 def roofline_3d(precision):
@@ -315,8 +315,8 @@ def roofline_3d(precision):
     return {"workload": w["name"] + ("-fp64" if precision == L.MFWH_FP64 else "-fp32-stencil"),
             "nt": nt,
             "kernel": f"k_leap3d_xkr<{tname}, 4 steps, order 2, 48x8 tiles aligned to 128 B on "
-                      "64x16 lanes, 32-plane chunks>: 4 fused leapfrog steps + 8 filter updates "
-                      "per launch (forcing-free)",
+                      f"64x16 lanes, {64 if precision == L.MFWH_FP64 else 32}-plane chunks>: "
+                      "4 fused leapfrog steps + 8 filter updates per launch (forcing-free)",
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "bytes_per_point_per_launch": per_pass,

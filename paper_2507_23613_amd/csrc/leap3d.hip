@@ -878,9 +878,13 @@ LaunchShape default_leap3d_shape(const Geom& g, int steps, int order, bool fp32)
       // where they still give two rounds of blocks, else 8 (float32, ms per
       // application with chunks of 8 / 16 / 32 planes: 256^3 - / 749 / 702,
       // 193^3 226 / - / 257, 129^3 41.3 / 39.5 (another box) / 43.4; float64
-      // 256^3 - / 867 / 834)
+      // 256^3 - / 867 / 834); float64, one block per CU, takes 64-plane
+      // chunks on the same terms (256^3, three alternations on one box:
+      // 751 against 791 ms with 32; float32 703 against 675)
       const long long want = fp32 ? 1024 : 512;
-      ls.chunk = t48 * ((g.nzi + 31) / 32) >= want ? 32 : 8;
+      ls.chunk = !fp32 && t48 * ((g.nzi + 63) / 64) >= want ? 64
+               : t48 * ((g.nzi + 31) / 32) >= want        ? 32
+                                                           : 8;
     }
   }
   return ls;
