@@ -234,6 +234,26 @@ int mfwh_optimize_filter(int nf, const double* omega_in, int np, int nt, int nde
                          double cdelta, double rcond, double* filt_out, double* lambda_max,
                          int* n_lambda);
 
+/* Largest |mu_d| over the mode frequencies grid g can hold (Section 4, eq.
+ * MFWHmu, with the discrete filter functions of eq. betadDefA: on a discrete
+ * eigenmode of frequency lambda the fixed-point map S_h has one nonzero
+ * eigenvalue, mu_d(lambda~) = sum_m gamma_m beta_{d,m}(lambda~) with gamma_m
+ * the column sums of B^{-1}, eq. MFWHmud; lambda~ maps lambda as eq.
+ * omegaImplicit maps omega for t->scheme).  Sampled at n_lambda equally spaced lambda in [0, lambda_top],
+ * lambda_top = cmax sqrt(sum over axes of the largest eigenvalue of -Delta_h)
+ * (4/h^2 for order 2, 16/(3h^2) for order 4): the largest mode frequency for
+ * wave speeds <= cmax.  The result is the maximum over the samples (a lower
+ * bound of the supremum; mu_d oscillates on the scale 2 pi / T, so take
+ * n_lambda well above lambda_top T / pi for a close bound).  A value above 1
+ * means I - S_h has eigenvalues of both signs: the fixed-point iteration
+ * diverges and restarted GMRES slows down, as happens when plain least
+ * squares (mfwh_optimize_filter with rcond <= 0) returns large parameters
+ * for a nearly singular frequency set.  Host only; no GPU needed.
+ * mu_max: host output; lambda_at: host output or NULL, the sampled lambda
+ * where the maximum is reached.  Costs n_lambda * (N_t + 1) cosines. */
+int mfwh_filter_mu_max(const mfwh_grid* g, double cmax, const mfwh_time* t, int n_lambda,
+                       double* mu_max, double* lambda_at);
+
 /* The host step of a deflated GMRES restart (the GPU solver calls the same
  * code; exposed for inspection, no GPU needed).  From the (m+1) x m upper
  * Hessenberg matrix of an Arnoldi cycle, A V_m = V_{m+1} Hbar (Section 7's

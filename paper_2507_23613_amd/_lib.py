@@ -89,6 +89,8 @@ def _load():
         "mfwh_filter_adjusted": (c_int, [c_int, P_double, c_double, c_int, P_double]),
         "mfwh_optimize_filter": (c_int, [c_int, P_double, c_int, c_int, c_int, c_double,
                                          c_double, P_double, P_double, P_int]),
+        "mfwh_filter_mu_max": (c_int, [ctypes.POINTER(mfwh_grid), c_double,
+                                       ctypes.POINTER(mfwh_time), c_int, P_double, P_double]),
         "mfwh_deflation_step": (c_int, [c_int, P_double, P_double, c_int, P_double, P_double,
                                         P_double, P_double, P_int]),
         "mfwh_workspace_bytes": (c_size_t, [ctypes.POINTER(mfwh_grid),
@@ -275,6 +277,13 @@ def mfwh_plan_info(time):
                               npm.ctypes.data_as(P_int), tfm.ctypes.data_as(P_double),
                               B.ctypes.data_as(P_double), Binv.ctypes.data_as(P_double)))
     return dict(omega_tilde=ot, npm=npm, tfm=tfm, B=B, Binv=Binv)
+
+
+def mfwh_filter_mu_max(grid, cmax, time, n_lambda=4000):
+    mu, at = c_double(), c_double()
+    _check(LIB.mfwh_filter_mu_max(ctypes.byref(grid), cmax, ctypes.byref(time), int(n_lambda),
+                                  ctypes.byref(mu), ctypes.byref(at)))
+    return mu.value, at.value
 
 
 def mfwh_plan_coefficients(time):

@@ -1714,6 +1714,25 @@ int mfwh_optimize_filter(int nf, const double* omega_in, int np, int nt, int nde
   return rc == MFWH_OK ? rc : fail(rc, err);
 }
 
+int mfwh_filter_mu_max(const mfwh_grid* g, double cmax, const mfwh_time* t, int n_lambda,
+                       double* mu_max, double* lambda_at) {
+  Geom G;
+  CHK(make_geom(g, &G));
+  if (!(cmax > 0) || n_lambda < 2 || n_lambda > 10000000 || !mu_max)
+    return fail(MFWH_EINVAL, "bad filter_mu_max arguments");
+  Plan P;
+  std::string err;
+  int rc = build_plan(t, &P, &err);
+  if (rc != MFWH_OK) return fail(rc, err);
+  double h[3];
+  for (int k = 0; k < g->dim; ++k) h[k] = g->len[k] / (g->n[k] - 1);
+  // the largest mode frequency: the explicit stability bound's eigenvalue
+  // (dt_max = 2 / top)
+  const double top = 2.0 / dt_max_explicit(g->dim, h, g->order, cmax);
+  *mu_max = mu_d_max(P, top, n_lambda, lambda_at);
+  return MFWH_OK;
+}
+
 int mfwh_deflation_step(int m, const double* hbar, const double* rho, int k, double* theta,
                         double* P, double* hnew, double* cnew, int* kk) {
   if (m < 2 || m > MFWH_MAX_RESTART || k < 1 || k >= m || !hbar || !rho || !P || !hnew ||

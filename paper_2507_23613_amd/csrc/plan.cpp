@@ -375,4 +375,32 @@ int optimize_filter(int nf, const double* om, int np, int nt, int ndelta, double
   return MFWH_OK;
 }
 
+double mu_d_max(const Plan& p, double top, int n, double* at) {
+  // On a discrete eigenmode of frequency lambda the map S_h is B^{-1} beta(lambda~)
+  // 1^T, whose one nonzero eigenvalue is mu_d = sum_m gamma_m beta_{d,m}(lambda~)
+  // with gamma_m the column sums of B^{-1} (Section 4, eq. MFWHmu; eq. MFWHmud),
+  // and beta_{d,m}(lambda~) = sum_n kappa[n][m] cos(lambda~ t^n) (eq. betadDefA).
+  const int nf = p.nf, n1 = p.nt + 1;
+  std::vector<double> g(n1, 0.0);              // g[n] = sum_m gamma_m kappa[n][m]
+  for (int m = 0; m < nf; ++m) {
+    double gm = 0.0;
+    for (int j = 0; j < nf; ++j) gm += p.Binv[j * nf + m];
+    for (int k = 0; k < n1; ++k) g[k] += gm * p.kappa[(size_t)k * nf + m];
+  }
+  double best = 0.0, best_at = 0.0;
+  for (int i = 0; i < n; ++i) {
+    const double lam = top * i / (n - 1);
+    const double lt = omega_tilde(lam, p.dt, p.alpha);
+    if (!std::isfinite(lt)) continue;          // beyond the scheme's range
+    double mu = 0.0;
+    for (int k = 0; k < n1; ++k) mu += g[k] * std::cos(lt * (k * p.dt));
+    if (std::fabs(mu) > best) {
+      best = std::fabs(mu);
+      best_at = lam;
+    }
+  }
+  if (at) *at = best_at;
+  return best;
+}
+
 }  // namespace mfwh

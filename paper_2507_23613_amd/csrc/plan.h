@@ -39,5 +39,8 @@ int adjusted_params(int nf, const double* omega, double dt, double alpha, double
 int optimize_filter(int nf, const double* om, int np, int nt, int ndelta, double cdelta,
                     double rcond, double* out, double* lmax_out, int* nlam_out,
                     std::string* err);
+// largest |mu_d(lambda~)| over n equally spaced mode frequencies lambda in
+// [0, top]; *at (may be NULL) receives the lambda where it is reached
+double mu_d_max(const Plan& p, double top, int n, double* at);
 
 }  // namespace mfwh

@@ -5,6 +5,8 @@ Plans the time grid and the filter with the library's own host planner
 moves forcings and wave speed to device tensors, allocates the workspace with
 PyTorch and calls the C ABI.  Nothing here computes any part of the method.
 """
+import warnings
+
 import numpy as np
 import torch
 
@@ -27,6 +29,7 @@ class GpuProblem:
         self.c = None if w["c"] is None else torch.as_tensor(
             np.ascontiguousarray(w["c"]), dtype=torch.float64, device=self.device)
         cmax = 1.0 if w["c"] is None else float(np.max(w["c"]))
+        self.cmax = cmax
         self.bc = w.get("bc")
         self.g = None if w.get("g") is None else torch.as_tensor(
             np.ascontiguousarray(w["g"]), dtype=torch.float64, device=self.device)
@@ -60,6 +63,16 @@ class GpuProblem:
             raise ValueError(f"unknown filter {kind!r}")
         self.params = params
         self.time = mk(params)
+        if isinstance(kind, str) and kind == "optimised" and w.get("filter_rcond", 0.0) <= 0:
+            # plain least squares can return large parameters that amplify
+            # modes far above the fitted range: |mu_d| > 1 there
+            mu, lam = self.filter_mu_max()
+            if mu > 1.0 + 1e-6:
+                warnings.warn(f"{w.get('name', 'problem')}: the optimised filter has "
+                              f"|mu_d| = {mu:.3g} at mode frequency {lam:.4g} (> 1: the "
+                              "fixed-point iteration diverges and GMRES slows down); "
+                              "a positive 'filter_rcond' keeps the parameters bounded",
+                              RuntimeWarning, stacklevel=2)
         self.plan = L.mfwh_plan_info(self.time)
         self.f = torch.as_tensor(np.ascontiguousarray(w["f"]), dtype=torch.float64,
                                  device=self.device)
@@ -68,6 +81,14 @@ class GpuProblem:
         if nbytes == 0:
             raise L.MfwhError(-1, "invalid problem description")
         self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+
+    def filter_mu_max(self, n_lambda=None):
+        """Largest |mu_d| over mode frequencies up to the grid's largest, as
+        sampled by mfwh_filter_mu_max (default: 2 N_t + 2 samples, at most
+        4000); returns (value, mode frequency where it is reached)."""
+        if n_lambda is None:
+            n_lambda = min(2 * self.nt + 2, 4000)
+        return L.mfwh_filter_mu_max(self.grid, self.cmax, self.time, n_lambda)
 
     @property
     def interior_points(self):

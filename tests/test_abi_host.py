@@ -401,3 +401,65 @@ def test_deflation_step_rejects_bad_arguments():
         L.mfwh_deflation_step(H, np.ones(6), 5)       # k >= m
     with pytest.raises(L.MfwhError):
         L.mfwh_deflation_step(H, np.ones(6), 0)
+
+
+def _mu_max_case(w, rcond):
+    """The library's plan of one batch workload (its own time recipe and
+    optimiser) and the oracle's, each with its own parameters."""
+    g = L.make_grid(w["shape"], w["lengths"], w["order"])
+    T, dt, nt = L.mfwh_plan_time(g, 1.0, float(w["omega"][0]), int(w["np"]), float(w["cfl"]))
+    ot = L.mfwh_plan_info(L.make_time(w["omega"], T, dt))["omega_tilde"]
+    p_lib, _, _ = L.mfwh_optimize_filter(ot, int(w["np"]), nt, rcond=rcond)
+    h = 1.0 / (w["shape"][0] - 1)
+    Tf, dto, nto = P.time_step_explicit(w["omega"][0], w["np"], h, 2, w["order"], 1.0, w["cfl"])
+    p_or, _, _ = P.optimise_filter_discrete(P.omega_tilde(np.asarray(w["omega"]), dto), w["np"],
+                                            nto, rcond=rcond)
+    return g, L.make_time(w["omega"], T, dt, p_lib), P.Plan(w["omega"], Tf, dto, params=p_or), h
+
+
+@pytest.mark.parametrize("k,rcond", [(28, 0.0), (14, 0.0), (28, 1e-2), (14, 1e-2)])
+def test_filter_mu_max_matches_oracle(k, rcond):
+    """mfwh_filter_mu_max against the oracle's mu_d (eq. MFWHmud, pinned by
+    the theorem tests of test_oracle_plan.py) on the same lambda samples, for
+    two batch frequency sets whose plain least-squares filters amplify modes
+    far above the fitted range (max |mu_d| 9.4 and 2.1) and for their
+    filters with the cutoff (max |mu_d| <= 1)."""
+    w = inputs.config4(0)[k]
+    n = 3000
+    g, t, pl, h = _mu_max_case(w, rcond)
+    mu, at = L.mfwh_filter_mu_max(g, 1.0, t, n)
+    top = math.sqrt(2 * 16.0 / 3.0) / h             # order 4, two axes, c <= 1
+    lam = top * np.arange(n) / (n - 1)
+    ref = np.abs(pl.mu_d(P.lambda_tilde(lam, pl.dt)))
+    assert mu == pytest.approx(ref.max(), rel=1e-6)
+    assert at == pytest.approx(lam[np.argmax(ref)], rel=1e-12)
+    if rcond == 0.0:
+        assert mu > 2.0
+    else:
+        assert mu <= 1.0 + 1e-8
+
+
+def test_filter_mu_max_arguments():
+    w = inputs.config4(0)[28]
+    g, t, _, _ = _mu_max_case(w, 1e-2)
+    for bad in [dict(cmax=0.0), dict(n_lambda=1)]:
+        kw = dict(cmax=1.0, n_lambda=100) | bad
+        with pytest.raises(L.MfwhError):
+            L.mfwh_filter_mu_max(g, kw["cmax"], t, kw["n_lambda"])
+
+
+def test_problem_setup_warns_on_amplifying_filter():
+    """Problem set-up (host planning only; no GPU call) flags a plain
+    least-squares filter whose |mu_d| exceeds 1 on the grid's modes, and
+    stays quiet with the optimiser's cutoff."""
+    import warnings
+    from paper_2507_23613_amd.problem import GpuProblem
+    w = dict(inputs.config4(0)[28])
+    w.pop("filter_rcond")
+    with pytest.warns(RuntimeWarning, match="filter_rcond"):
+        GpuProblem(w, device="cpu", restart=0)
+    with warnings.catch_warnings():
+        warnings.simplefilter("error")
+        gp = GpuProblem(inputs.config4(0)[28], device="cpu", restart=0)
+    mu, _ = gp.filter_mu_max()
+    assert mu <= 1.0 + 1e-8
