@@ -5,6 +5,7 @@ Plans the time grid and the filter with the library's own host planner
 moves forcings and wave speed to device tensors, allocates the workspace with
 PyTorch and calls the C ABI.  Nothing here computes any part of the method.
 """
+import os
 import warnings
 
 import numpy as np
@@ -115,6 +116,45 @@ class GpuProblem:
                            zero_fallback, scale_initial, deflate, inner_max_iter)
         info = L.mfwh_solve_gmres(self.grid, self.time, self.f, v, opts, self.ws)
         return v, info
+
+    def gmres_checkpointed(self, path, every, restart=None, max_iter=1000, tol=1e-8):
+        """Restarted GMRES (Section 7) in segments of ``every`` iterations, a
+        multiple of the restart length, so every segment ends where the solver
+        restarts from the true residual anyway.  After each segment the iterate
+        and the iteration count are written to ``path`` (NumPy .npz, written
+        under a temporary name and renamed, so an interrupted write leaves the
+        previous checkpoint); a call that finds ``path`` resumes from it.  The
+        iterates equal those of one uninterrupted call (each segment re-forms
+        b = W_h(0) and the residual of its starting iterate with the same
+        kernels); a segment costs one forced and one forcing-free application
+        more.  Not offered with deflation, whose kept vectors a checkpoint would
+        have to carry."""
+        m = restart or self.restart
+        if m < 1 or every < m or every % m:
+            raise ValueError("every must be a positive multiple of the restart length")
+        path = os.fspath(path)
+        v, its = self.zeros(), 0
+        info = dict(status="MFWH_NOT_CONVERGED", converged=False, rel_residual=1.0)
+        if os.path.exists(path):
+            with np.load(path, allow_pickle=False) as d:
+                if tuple(d["v"].shape) != tuple(v.shape) or not np.array_equal(d["omega"],
+                                                                               self.omega):
+                    raise ValueError(f"{path} holds a checkpoint of another problem")
+                v.copy_(torch.as_tensor(d["v"], device=self.device))
+                its = int(d["iterations"])
+                info = dict(status="MFWH_OK" if bool(d["converged"]) else "MFWH_NOT_CONVERGED",
+                            converged=bool(d["converged"]),
+                            rel_residual=float(d["rel_residual"]))
+        while its < max_iter and not info["converged"]:
+            v, info = self.gmres(v=v, restart=m, max_iter=min(every, max_iter - its), tol=tol)
+            its += info["iterations"]
+            tmp = path + ".tmp.npz"
+            np.savez(tmp, v=v.cpu().numpy(), omega=self.omega, iterations=its,
+                     rel_residual=info["rel_residual"], converged=info["converged"])
+            os.replace(tmp, path)
+            if info["iterations"] == 0:
+                break
+        return v, dict(info, iterations=its)
 
     def fixed_point(self, v=None, max_iter=100, tol=1e-300, form=L.MFWH_FPI_AUTO):
         v = self.zeros() if v is None else v
