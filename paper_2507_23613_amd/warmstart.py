@@ -7,6 +7,7 @@ guess of GMRES: the solver scales it by the residual-optimal factor and
 rejects it (zero start) if its residual still exceeds that of the zero start,
 so the solution's accuracy never depends on the network.
 """
+import os
 import time
 
 import numpy as np
@@ -110,11 +111,41 @@ class WarmStart:
             L.mfwh_cnn_normalize(out[s:e])
         return out
 
-    def train(self, feats, targets, epochs=20, lr=1e-3, seed=0, log=None):
+    def _save(self, path, epoch, hist, seed, N):
+        """Weights, Adam moments and step, the epochs done and their losses."""
+        tmp = path + ".tmp.npz"
+        np.savez(tmp, params=self.params.cpu().numpy(), m=self.m.cpu().numpy(),
+                 v=self.v.cpu().numpy(), step=self.step, epoch=epoch,
+                 hist=np.asarray(hist, dtype=np.float64),
+                 shape=np.array([self.nf, self.H, self.W, self.batch, seed, N]))
+        os.replace(tmp, path)
+
+    def _load(self, path, seed, N):
+        with np.load(path, allow_pickle=False) as d:
+            if list(d["shape"]) != [self.nf, self.H, self.W, self.batch, seed, N]:
+                raise ValueError(f"{path} holds the training state of another run")
+            for name in ("params", "m", "v"):
+                getattr(self, name).copy_(torch.as_tensor(d[name], device=self.device))
+            self.step = int(d["step"])
+            return int(d["epoch"]), [float(x) for x in d["hist"]]
+
+    def train(self, feats, targets, epochs=20, lr=1e-3, seed=0, log=None, checkpoint=None):
+        """Adam on the mean squared error, ``epochs`` passes over the samples in
+        a seeded random order.  ``checkpoint``: a .npz path written after
+        every epoch (under a temporary name, then renamed); a call that finds
+        it resumes after its last epoch, drawing the sample orders of the
+        epochs already done so that the run continues exactly as one
+        uninterrupted call would."""
         N = feats.shape[0]
         rng = np.random.default_rng(seed)
-        hist = []
-        for ep in range(epochs):
+        hist, start = [], 0
+        if checkpoint is not None:
+            checkpoint = os.fspath(checkpoint)
+            if os.path.exists(checkpoint):
+                start, hist = self._load(checkpoint, seed, N)
+                for _ in range(start):
+                    rng.permutation(N)
+        for ep in range(start, epochs):
             order = rng.permutation(N)
             tot, cnt = 0.0, 0
             for s in range(0, N - self.batch + 1, self.batch):
@@ -130,6 +161,8 @@ class WarmStart:
             hist.append(tot / max(1, cnt))
             if log:
                 log(f"epoch {ep}: mean loss {hist[-1]:.4e}")
+            if checkpoint is not None:
+                self._save(checkpoint, ep + 1, hist, seed, N)
         return hist
 
     def predict(self, F, OM):

@@ -1,6 +1,8 @@
-"""Checkpointed GMRES (segments of whole restart cycles, the iterate saved
-after each) against one uninterrupted call through the C ABI: the same
-iterates, bit for bit, after an interruption and a resume from the file."""
+"""Checkpoint and resume against uninterrupted runs through the C ABI:
+GMRES in segments of whole restart cycles (the iterate saved after each) and
+the warm-start network's training (its state saved after each epoch) give,
+after an interruption and a resume from the file, the results of one
+uninterrupted call bit for bit."""
 import sys
 
 import numpy as np
@@ -42,3 +44,27 @@ def test_checkpointed_gmres_resumes_bitwise(tmp_path):
     assert i4["converged"] and i4["iterations"] == n and torch.equal(v4, v1)
     with pytest.raises(ValueError):
         gp.gmres_checkpointed(tmp_path / "x.npz", every=24, restart=16)
+
+
+def test_warm_start_training_resumes_bitwise(tmp_path):
+    """Training interrupted after two epochs and resumed from its per-epoch
+    checkpoint ends with the weights, Adam moments and losses of an
+    uninterrupted three-epoch run (the kernels are deterministic)."""
+    from paper_2507_23613_amd.warmstart import WarmStart
+    nf, H, W, N = 2, 32, 32, 12
+    g = torch.Generator(device="cpu").manual_seed(3)
+    feats = torch.randn((N, H, W, 6 * nf), generator=g).float().cuda()
+    targets = torch.randn((N, H, W, nf), generator=g).float().cuda()
+    a = WarmStart(nf=nf, H=H, W=W, batch=4, seed=1)
+    ha = a.train(feats, targets, epochs=3, lr=1e-3, seed=7)
+    path = tmp_path / "net.npz"
+    b = WarmStart(nf=nf, H=H, W=W, batch=4, seed=1)
+    b.train(feats, targets, epochs=2, lr=1e-3, seed=7, checkpoint=path)
+    c = WarmStart(nf=nf, H=H, W=W, batch=4, seed=1)
+    hc = c.train(feats, targets, epochs=3, lr=1e-3, seed=7, checkpoint=path)
+    assert hc == ha and c.step == a.step
+    for name in ("params", "m", "v"):
+        assert torch.equal(getattr(c, name), getattr(a, name)), name
+    with pytest.raises(ValueError):
+        WarmStart(nf=nf, H=H, W=W, batch=2, seed=1).train(feats, targets, epochs=3,
+                                                          seed=7, checkpoint=path)
