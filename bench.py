@@ -440,6 +440,16 @@ def gemm_bench(args):
                       "rows": rows}), flush=True)
 
 
+def convergence_rates(history, np_):
+    """Average convergence rate CR = (r^(N_it) / r^(1))^(1 / N_it) of a
+    fixed-point residual history r^(1) .. r^(N_it) (eq. residual) and the
+    effective rate ECR = CR^(1 / N_p), which charges the N_p periods each
+    iteration integrates over (Section 8)."""
+    h = np.asarray(history, dtype=np.float64)
+    cr = float((h[-1] / h[0]) ** (1.0 / h.size))
+    return cr, cr ** (1.0 / np_)
+
+
 def fpi_bench(args):
     """The 1D workload (N = 201, order 2, omega = (5.3, 11.7), traditional
     filter, N_p = 1): 100 plain fixed-point iterations (Algorithm 1) from
@@ -462,6 +472,7 @@ def fpi_bench(args):
            "s": round(el, 4), "ms_per_iteration": round(1e3 * el / info["iterations"], 3),
            "r1": float(h[0]), "r100": float(h[-1]),
            "contraction_last20": float((h[-1] / h[-21]) ** (1.0 / 20)),
+           "CR": convergence_rates(h, w["np"])[0], "ECR": convergence_rates(h, w["np"])[1],
            "point_steps_x_nf_per_s": gp.interior_points * gp.nt * 2 * info["iterations"] / el}
     print(json.dumps(row), flush=True)
 

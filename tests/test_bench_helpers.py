@@ -1,8 +1,9 @@
-"""Host-side checks of bench.py's solution check (no GPU): the relative
-Helmholtz residual it reports for 3D solves (eq. errorAndResid) equals the
-one computed with the oracle's Delta_h, and vanishes at the oracle's sparse
-direct solution."""
+"""Host-side checks of bench.py's helpers (no GPU): the relative Helmholtz
+residual it reports for 3D solves (eq. errorAndResid) equals the one computed
+with the oracle's Delta_h and vanishes at the oracle's sparse direct
+solution; its convergence rates CR and ECR follow their definitions."""
 import numpy as np
+import pytest
 import torch
 
 import bench
@@ -40,3 +41,19 @@ def test_helmholtz_residual_vanishes_at_direct_solution():
     got = bench.helmholtz_residual_3d(torch.as_tensor(v), torch.as_tensor(f), torch.as_tensor(c),
                                       om, h)
     assert max(got) < 1e-10
+
+
+def test_convergence_rates_follow_the_definitions():
+    """CR and ECR of Section 8: the paper's own example (CR = 0.5 at N_p = 1
+    and CR = 0.25 at N_p = 2 both give ECR = 0.5), and CR of a geometric
+    history r^(k) = q^(k-1) over N_it iterations, q^((N_it - 1) / N_it)."""
+    import bench
+    q, n = 0.8, 50
+    hist = q ** np.arange(n)
+    cr, ecr = bench.convergence_rates(hist, 1)
+    assert cr == pytest.approx(q ** ((n - 1) / n), rel=1e-14) and ecr == cr
+    for cr_p, np_ in ((0.5, 1), (0.25, 2)):
+        h = np.array([1.0, cr_p ** 2])              # N_it = 2: CR = (r2 / r1)^(1/2)
+        cr, ecr = bench.convergence_rates(h, np_)
+        assert cr == pytest.approx(cr_p, rel=1e-14)
+        assert ecr == pytest.approx(0.5, rel=1e-14)
