@@ -250,7 +250,8 @@ int mfwh_optimize_filter(int nf, const double* omega_in, int np, int nt, int nde
  * squares (mfwh_optimize_filter with rcond <= 0) returns large parameters
  * for a nearly singular frequency set.  Host only; no GPU needed.
  * mu_max: host output; lambda_at: host output or NULL, the sampled lambda
- * where the maximum is reached.  Costs n_lambda * (N_t + 1) cosines. */
+ * where the maximum is reached.  Costs n_lambda * (N_t + 1) multiply-adds
+ * (the cosines by their three-term recurrence). */
 int mfwh_filter_mu_max(const mfwh_grid* g, double cmax, const mfwh_time* t, int n_lambda,
                        double* mu_max, double* lambda_at);
 

@@ -392,8 +392,18 @@ double mu_d_max(const Plan& p, double top, int n, double* at) {
     const double lam = top * i / (n - 1);
     const double lt = omega_tilde(lam, p.dt, p.alpha);
     if (!std::isfinite(lt)) continue;          // beyond the scheme's range
-    double mu = 0.0;
-    for (int k = 0; k < n1; ++k) mu += g[k] * std::cos(lt * (k * p.dt));
+    // cos(k x) by the three-term recurrence cos((k+1)x) = 2 cos(x) cos(kx) -
+    // cos((k-1)x): rounding grows about linearly in k (by k eps / sin x),
+    // well below what a comparison with 1 needs, at one multiply-add a term
+    const double x = lt * p.dt, c1 = std::cos(x);
+    double cm = 1.0, ck = c1;                  // cos(0 x), cos(1 x)
+    double mu = g[0];
+    for (int k = 1; k < n1; ++k) {
+      mu += g[k] * ck;
+      const double cn = 2.0 * c1 * ck - cm;
+      cm = ck;
+      ck = cn;
+    }
     if (std::fabs(mu) > best) {
       best = std::fabs(mu);
       best_at = lam;

@@ -64,15 +64,17 @@ class GpuProblem:
             raise ValueError(f"unknown filter {kind!r}")
         self.params = params
         self.time = mk(params)
-        if isinstance(kind, str) and kind == "optimised" and w.get("filter_rcond", 0.0) <= 0:
-            # plain least squares can return large parameters that amplify
-            # modes far above the fitted range: |mu_d| > 1 there
+        if isinstance(kind, str) and kind == "optimised":
+            # least squares fits the filter on a range of frequencies only; far
+            # above it large parameters can make |mu_d| > 1
             mu, lam = self.filter_mu_max()
             if mu > 1.0 + 1e-6:
+                hint = ("a positive 'filter_rcond' keeps the parameters bounded"
+                        if w.get("filter_rcond", 0.0) <= 0 else
+                        "another 'filter_rcond' or filter may avoid it")
                 warnings.warn(f"{w.get('name', 'problem')}: the optimised filter has "
                               f"|mu_d| = {mu:.3g} at mode frequency {lam:.4g} (> 1: the "
-                              "fixed-point iteration diverges and GMRES slows down); "
-                              "a positive 'filter_rcond' keeps the parameters bounded",
+                              f"fixed-point iteration diverges and GMRES slows down); {hint}",
                               RuntimeWarning, stacklevel=2)
         self.plan = L.mfwh_plan_info(self.time)
         self.f = torch.as_tensor(np.ascontiguousarray(w["f"]), dtype=torch.float64,
