@@ -463,3 +463,19 @@ def test_problem_setup_warns_on_amplifying_filter():
         gp = GpuProblem(inputs.config4(0)[28], device="cpu", restart=0)
     mu, _ = gp.filter_mu_max()
     assert mu <= 1.0 + 1e-8
+
+
+def test_checkpoint_arguments_and_foreign_files_are_refused(tmp_path):
+    """Checkpointed GMRES checks its segment length and refuses a checkpoint
+    of another problem before any solver call (host only)."""
+    from paper_2507_23613_amd.problem import GpuProblem
+    w = inputs.small(seed=21, shape=(33, 29), nf=3, order=4, hi=20.0, filter="adjusted")
+    gp = GpuProblem(w, device="cpu", restart=16)
+    for every in (8, 24, 0):
+        with pytest.raises(ValueError, match="multiple"):
+            gp.gmres_checkpointed(tmp_path / "a.npz", every=every, restart=16)
+    other = tmp_path / "other.npz"
+    np.savez(other, v=np.zeros((3, 33, 29)), omega=np.asarray(w["omega"]) + 1.0, iterations=16,
+             rel_residual=0.5, converged=False)
+    with pytest.raises(ValueError, match="another problem"):
+        gp.gmres_checkpointed(other, every=16, restart=16)
