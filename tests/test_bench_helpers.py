@@ -57,3 +57,17 @@ def test_convergence_rates_follow_the_definitions():
         cr, ecr = bench.convergence_rates(h, np_)
         assert cr == pytest.approx(cr_p, rel=1e-14)
         assert ecr == pytest.approx(0.5, rel=1e-14)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU; asked for more it exits with a message
+    before touching a device (run as its own process, no GPU needed)."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU only" in r.stderr
+    assert r.stdout == ""
