@@ -15,7 +15,12 @@ from . import _lib as L
 
 
 class GpuProblem:
-    """``w``: workload dict from ``paper_2507_23613_amd.inputs``."""
+    """``w``: workload dict from ``paper_2507_23613_amd.inputs``.  With
+    ``filter_rcond = "auto"`` an optimised filter takes the first cutoff of
+    ``AUTO_RCOND`` (plain least squares first) whose filter keeps |mu_d| <= 1
+    on the grid's modes; ``filter_rcond`` then holds the one chosen."""
+
+    AUTO_RCOND = (0.0, 1e-4, 1e-3, 1e-2, 1e-1)
 
     def __init__(self, w, precision=L.MFWH_FP64, restart=30, device="cuda", filt=None,
                  time=None, scheme=L.MFWH_EXPLICIT, steps_per_period=10, imp_tol=0.0,
@@ -50,6 +55,8 @@ class GpuProblem:
         def mk(params):
             return L.make_time(self.omega, T, dt, params, scheme, imp_tol, imp_max_cycles)
         kind = w["filter"] if filt is None else filt
+        rcond = w.get("filter_rcond", 0.0)
+        self.filter_rcond = None
         if isinstance(kind, np.ndarray):
             params = kind
         elif kind == "traditional":
@@ -57,9 +64,27 @@ class GpuProblem:
         elif kind == "adjusted":
             params = L.mfwh_filter_adjusted(self.omega, dt, scheme)
         elif kind == "optimised":
-            info = L.mfwh_plan_info(mk(None))
-            params, _, _ = L.mfwh_optimize_filter(info["omega_tilde"], int(w["np"]), nt,
-                                                  rcond=w.get("filter_rcond", 0.0))
+            ot = L.mfwh_plan_info(mk(None))["omega_tilde"]
+
+            def optimise(rc):
+                return L.mfwh_optimize_filter(ot, int(w["np"]), nt, rcond=rc)[0]
+            if rcond == "auto":
+                # the first of plain least squares and growing cutoffs whose
+                # filter keeps |mu_d| <= 1 on the grid's modes, else the one
+                # with the smallest maximum
+                best = None
+                for rc in self.AUTO_RCOND:
+                    params = optimise(rc)
+                    self.time = mk(params)
+                    mu, _ = self.filter_mu_max()
+                    if best is None or mu < best[0]:
+                        best = (mu, rc, params)
+                    if mu <= 1.0 + 1e-9:
+                        break
+                _, rcond, params = best
+            else:
+                params = optimise(rcond)
+            self.filter_rcond = rcond
         else:
             raise ValueError(f"unknown filter {kind!r}")
         self.params = params
@@ -70,7 +95,7 @@ class GpuProblem:
             mu, lam = self.filter_mu_max()
             if mu > 1.0 + 1e-6:
                 hint = ("a positive 'filter_rcond' keeps the parameters bounded"
-                        if w.get("filter_rcond", 0.0) <= 0 else
+                        if rcond <= 0 else
                         "another 'filter_rcond' or filter may avoid it")
                 warnings.warn(f"{w.get('name', 'problem')}: the optimised filter has "
                               f"|mu_d| = {mu:.3g} at mode frequency {lam:.4g} (> 1: the "

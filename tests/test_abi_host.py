@@ -479,3 +479,20 @@ def test_checkpoint_arguments_and_foreign_files_are_refused(tmp_path):
              rel_residual=0.5, converged=False)
     with pytest.raises(ValueError, match="another problem"):
         gp.gmres_checkpointed(other, every=16, restart=16)
+
+
+def test_automatic_filter_cutoff():
+    """filter_rcond = "auto" keeps plain least squares where its filter has
+    |mu_d| <= 1 on the grid's modes (the 1025^2 workload) and otherwise takes
+    the first cutoff that does (batch problem 28, whose plain filter reaches
+    |mu_d| = 9.4), without a warning (host planning only)."""
+    import warnings
+    from paper_2507_23613_amd.problem import GpuProblem
+    with warnings.catch_warnings():
+        warnings.simplefilter("error")
+        gp2 = GpuProblem(dict(inputs.config2(0), filter_rcond="auto"), device="cpu", restart=0)
+        gp4 = GpuProblem(dict(inputs.config4(0)[28], filter_rcond="auto"), device="cpu",
+                         restart=0)
+    assert gp2.filter_rcond == 0.0 and gp2.filter_mu_max()[0] <= 1.0 + 1e-9
+    assert gp4.filter_rcond > 0.0 and gp4.filter_mu_max()[0] <= 1.0 + 1e-9
+    assert gp4.filter_rcond == min(rc for rc in GpuProblem.AUTO_RCOND if rc > 0.0)
