@@ -128,6 +128,9 @@ def batch_bench(args):
     from paper_2507_23613_amd import inputs
     from paper_2507_23613_amd.problem import GpuBatch, GpuProblem
     ws = inputs.config4(0)
+    if args.filter_rcond is not None:        # the optimiser's cutoff for every problem
+        rc = args.filter_rcond if args.filter_rcond == "auto" else float(args.filter_rcond)
+        ws = [dict(w, filter_rcond=rc) for w in ws]
     log(f"batch of {len(ws)} problems")
     gb = GpuBatch(ws, restart=args.restart)
     log(f"workspace {gb.ws.numel() / 2**30:.1f} GiB")
@@ -146,7 +149,8 @@ def batch_bench(args):
            "iterations_max": max(i["iterations"] for i in infos),
            "iterations_median": float(np.median([i["iterations"] for i in infos])),
            "gmres_restart": args.restart, "gmres_deflate": args.deflate,
-           "max_iter": args.max_iter}
+           "max_iter": args.max_iter,
+           "filter_rcond": sorted({str(gp.filter_rcond) for gp in gb.items})}
     for k, (i, w) in enumerate(zip(infos, ws)):
         if not i["converged"]:
             log(f"problem {k} ({w['shape'][0]}^2, N_f = {len(w['omega'])}): not converged, "
@@ -564,6 +568,8 @@ def main():
     ap.add_argument("--sequential", action="store_true",
                     help="batch mode: also solve the problems one at a time")
     ap.add_argument("--applies", type=int, default=3)
+    ap.add_argument("--filter-rcond", default=None,
+                    help="batch: the optimiser's cutoff for every problem (a number or 'auto')")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-fp32", action="store_true", help="skip the float32-stencil solve")
     ap.add_argument("--no-3d", action="store_true", help="skip the 3D 256^3 kernel rate")
